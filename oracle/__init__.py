@@ -1,0 +1,194 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``oracle/lqcd_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library or its binding.  All
+arrays are numpy complex128 in natural lexicographic layout (see the C file).
+
+Parity status: every function here is pinned in ``tests/test_oracle.py``
+(closed-form free-field spectrum, anti-Hermiticity, gauge covariance, dense
+LAPACK solves, exact derivatives and finite differences).  The one convention
+those pins cannot fix is the order of the staggered phases over the axes,
+eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}) with (x, y, z, t) = (0, 1, 2, 3):
+any ordering gives the same spectrum and symmetries, so that ordering is a
+stated convention shared with the GPU path, not a pinned result.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lqcd_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liblqcd_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE: no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_hop.argtypes = [_ip, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int]
+    lib.orc_doe.argtypes = [_ip, ctypes.c_int, _dp, _dp, _dp]
+    lib.orc_deo.argtypes = [_ip, ctypes.c_int, _dp, _dp, _dp]
+    lib.orc_apply_A.argtypes = [_ip, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double,
+                                _dp, _dp, _dp]
+    lib.orc_true_residual.argtypes = [_ip, ctypes.c_int, _dp, ctypes.c_double,
+                                      ctypes.c_double, _dp, _dp]
+    lib.orc_true_residual.restype = ctypes.c_double
+    lib.orc_cg.argtypes = [_ip, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp,
+                           _dp, ctypes.c_double, ctypes.c_int, _ip, _dp]
+    lib.orc_cg.restype = ctypes.c_int
+    lib.orc_cg_multishift.argtypes = [_ip, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int,
+                                      _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp]
+    lib.orc_cg_multishift.restype = ctypes.c_int
+    lib.orc_action.argtypes = [_ip, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+    lib.orc_action.restype = ctypes.c_double
+    lib.orc_force.argtypes = [_ip, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                              ctypes.c_int, _dp]
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_get_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _geom(L):
+    arr = (ctypes.c_int * 4)(*[int(v) for v in L])
+    if any(int(v) < 2 or int(v) % 2 for v in L):
+        raise ValueError(f"every extent must be even and >= 2, got {tuple(L)}")
+    return arr
+
+
+def _c128(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _V(L):
+    return int(L[0]) * int(L[1]) * int(L[2]) * int(L[3])
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
+
+
+def hop(L, U, psi, out_parity: int, antiperiodic: bool = True) -> np.ndarray:
+    V = _V(L)
+    U = _c128(U, (4, V, 3, 3))
+    psi = _c128(psi, (V, 3))
+    out = np.zeros((V, 3), np.complex128)
+    _load().orc_hop(_geom(L), int(antiperiodic), _ptr(U), _ptr(psi), _ptr(out), int(out_parity))
+    return out
+
+
+def doe(L, U, psi_even, antiperiodic: bool = True) -> np.ndarray:
+    """D_oe: even-site input -> odd-site output (natural layout, other parity zero)."""
+    return hop(L, U, psi_even, 1, antiperiodic)
+
+
+def deo(L, U, psi_odd, antiperiodic: bool = True) -> np.ndarray:
+    """D_eo: odd-site input -> even-site output."""
+    return hop(L, U, psi_odd, 0, antiperiodic)
+
+
+def apply_A(L, U, mass: float, sigma: float, x, antiperiodic: bool = True) -> np.ndarray:
+    """((m^2 + sigma) - D_eo D_oe) x on even sites."""
+    V = _V(L)
+    U = _c128(U, (4, V, 3, 3))
+    x = _c128(x, (V, 3))
+    y = np.zeros((V, 3), np.complex128)
+    tmp = np.zeros((V, 3), np.complex128)
+    _load().orc_apply_A(_geom(L), int(antiperiodic), _ptr(U), float(mass) ** 2, float(sigma),
+                        _ptr(x), _ptr(y), _ptr(tmp))
+    return y
+
+
+def true_residual(L, U, mass, sigma, b, x, antiperiodic: bool = True) -> float:
+    V = _V(L)
+    U = _c128(U, (4, V, 3, 3))
+    b = _c128(b, (V, 3))
+    x = _c128(x, (V, 3))
+    return float(_load().orc_true_residual(_geom(L), int(antiperiodic), _ptr(U),
+                                           float(mass) ** 2, float(sigma), _ptr(b), _ptr(x)))
+
+
+def cg(L, U, mass, sigma, b, tol=1e-10, max_iter=10000, x0=None, antiperiodic=True):
+    """Returns (x, status, iterations, true relative residual)."""
+    V = _V(L)
+    U = _c128(U, (4, V, 3, 3))
+    b = _c128(b, (V, 3))
+    x = np.zeros((V, 3), np.complex128) if x0 is None else _c128(x0, (V, 3)).copy()
+    it = ctypes.c_int(0)
+    tr = ctypes.c_double(0.0)
+    st = _load().orc_cg(_geom(L), int(antiperiodic), _ptr(U), float(mass) ** 2, float(sigma),
+                        _ptr(b), _ptr(x), float(tol), int(max_iter), ctypes.byref(it),
+                        ctypes.byref(tr))
+    return x, int(st), int(it.value), float(tr.value)
+
+
+def cg_multishift(L, U, mass, sigmas, b, tol=1e-10, max_iter=10000, antiperiodic=True):
+    """Returns (x [nshift][V][3], status, (ms_iters, refine_iters), true_res [nshift])."""
+    V = _V(L)
+    U = _c128(U, (4, V, 3, 3))
+    b = _c128(b, (V, 3))
+    sig = np.ascontiguousarray(sigmas, dtype=np.float64)
+    ns = sig.size
+    x = np.zeros((ns, V, 3), np.complex128)
+    iters = (ctypes.c_int * 2)(0, 0)
+    tr = np.zeros(ns, np.float64)
+    st = _load().orc_cg_multishift(_geom(L), int(antiperiodic), _ptr(U), float(mass) ** 2, ns,
+                                   _ptr(sig), _ptr(b), _ptr(x), float(tol), int(max_iter),
+                                   iters, _ptr(tr))
+    return x, int(st), (int(iters[0]), int(iters[1])), tr
+
+
+def action(L, alpha0, alpha, phi, X) -> float:
+    """S = sum_j [alpha0 ||phi_j||^2 + sum_i alpha_i Re <phi_j, X_ij>]."""
+    V = _V(L)
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    phi = np.ascontiguousarray(phi, dtype=np.complex128).reshape(-1, V, 3)
+    npf = phi.shape[0]
+    X = _c128(np.asarray(X).reshape(npf, al.size, V, 3), (npf, al.size, V, 3))
+    return float(_load().orc_action(_geom(L), npf, al.size, float(alpha0), _ptr(al),
+                                    _ptr(phi), _ptr(X)))
+
+
+def force(L, U, alpha, X, mode: int = 0, antiperiodic: bool = True) -> np.ndarray:
+    """mode 0: TA(U M) per link; mode 1: M^dag (raw gradient).  Natural [4][V][3][3]."""
+    V = _V(L)
+    U = _c128(U, (4, V, 3, 3))
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.complex128)
+    X = X.reshape(-1, al.size, V, 3)
+    F = np.zeros((4, V, 3, 3), np.complex128)
+    _load().orc_force(_geom(L), int(antiperiodic), _ptr(U), X.shape[0], al.size, _ptr(al),
+                      _ptr(X), int(mode), _ptr(F))
+    return F

@@ -1,0 +1,171 @@
+"""Seeded synthetic inputs for the staggered even/odd solver.
+
+This module is shared by the CPU oracle tests, the GPU parity tests, the
+benchmark and the smoke check.  It holds no arithmetic of the method itself
+(no hopping term, no solver, no force): it only draws gauge links, sources,
+gauge transformations and su(3) directions from a seeded PCG64 stream, and
+fixes the lattice geometry conventions (site ordering, parity) that both sides
+must agree on as an input format.
+
+Conventions
+-----------
+* A lattice has extents ``L = (Lx, Ly, Lz, Lt)``; direction mu = 0, 1, 2, 3 is
+  x, y, z, t.  The lexicographic site index is
+  ``lex = x + Lx*(y + Ly*(z + Lz*t))`` (x fastest).
+* The parity of a site is ``(x + y + z + t) % 2``; 0 is even.
+* Natural gauge field: complex128 array ``[4][V][3][3]``, ``U[mu, lex, a, b]``
+  is row a, column b of the link leaving site lex in direction mu.
+* Natural colour vector field: complex128 ``[V][3]`` (or ``[n][V][3]``).
+
+The paper (Sec. 2) only states that links are SU(3) matrices; the
+distributions below are the synthetic stand-ins for its thermalised
+production configurations, which are not available.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "volume", "site_coords", "site_parity", "rng",
+    "links_unit", "links_exp", "links_haar", "haar_su3",
+    "gaussian_field", "gaussian_even_source", "su3_algebra_directions",
+    "rational_shifts", "rational_weights",
+]
+
+
+def volume(L) -> int:
+    L = tuple(int(v) for v in L)
+    return L[0] * L[1] * L[2] * L[3]
+
+
+def site_coords(L) -> np.ndarray:
+    """Coordinates ``[V][4]`` (x, y, z, t) of every site in lexicographic order."""
+    Lx, Ly, Lz, Lt = (int(v) for v in L)
+    t, z, y, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly),
+                             np.arange(Lx), indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel(), t.ravel()], axis=1)
+
+
+def site_parity(L) -> np.ndarray:
+    """Parity ``[V]`` (0 even, 1 odd) of every site in lexicographic order."""
+    return site_coords(L).sum(axis=1) % 2
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _complex_gauss(g: np.random.Generator, shape) -> np.ndarray:
+    """Complex Gaussian with E|z|^2 = 1: (N(0,1) + i N(0,1)) / sqrt(2)."""
+    re = g.standard_normal(shape)
+    im = g.standard_normal(shape)
+    return (re + 1j * im) / np.sqrt(2.0)
+
+
+def links_unit(L) -> np.ndarray:
+    """Free field: every link is the 3x3 identity."""
+    V = volume(L)
+    U = np.zeros((4, V, 3, 3), dtype=np.complex128)
+    U[:, :, 0, 0] = U[:, :, 1, 1] = U[:, :, 2, 2] = 1.0
+    return U
+
+
+def _gell_mann() -> np.ndarray:
+    lam = np.zeros((8, 3, 3), dtype=np.complex128)
+    lam[0][0, 1] = lam[0][1, 0] = 1
+    lam[1][0, 1] = -1j; lam[1][1, 0] = 1j
+    lam[2][0, 0] = 1; lam[2][1, 1] = -1
+    lam[3][0, 2] = lam[3][2, 0] = 1
+    lam[4][0, 2] = -1j; lam[4][2, 0] = 1j
+    lam[5][1, 2] = lam[5][2, 1] = 1
+    lam[6][1, 2] = -1j; lam[6][2, 1] = 1j
+    lam[7][0, 0] = lam[7][1, 1] = 1 / np.sqrt(3); lam[7][2, 2] = -2 / np.sqrt(3)
+    return lam
+
+
+def _gaussian_hermitian(g: np.random.Generator, n: int) -> np.ndarray:
+    """n traceless Hermitian 3x3 matrices H = sum_a c_a lambda_a / 2, c_a ~ N(0,1)."""
+    c = g.standard_normal((n, 8))
+    return np.einsum("na,aij->nij", c, _gell_mann() / 2.0)
+
+
+def _expi_hermitian(H: np.ndarray, beta: float) -> np.ndarray:
+    """exp(i*beta*H) for a stack of Hermitian matrices, via eigendecomposition."""
+    w, v = np.linalg.eigh(H)
+    ph = np.exp(1j * beta * w)
+    return np.einsum("nij,nj,nkj->nik", v, ph, v.conj())
+
+
+def links_exp(L, beta: float, seed: int) -> np.ndarray:
+    """Near-unit SU(3) links exp(i*beta*H), H Gaussian traceless Hermitian."""
+    V = volume(L)
+    g = rng(seed)
+    H = _gaussian_hermitian(g, 4 * V)
+    return _expi_hermitian(H, beta).reshape(4, V, 3, 3)
+
+
+def haar_su3(g: np.random.Generator, n: int) -> np.ndarray:
+    """n Haar-distributed SU(3) matrices from the QR of complex Gaussians.
+
+    The phases of R's diagonal are moved into Q (which makes Q Haar on U(3)),
+    then Q is divided by a cube root of det(Q) to land on SU(3).
+    """
+    Z = _complex_gauss(g, (n, 3, 3))
+    Q, R = np.linalg.qr(Z)
+    d = np.diagonal(R, axis1=1, axis2=2)
+    Q = Q * (d / np.abs(d))[:, None, :]
+    det = np.linalg.det(Q)
+    return Q / np.exp(1j * np.angle(det) / 3.0)[:, None, None]
+
+
+def links_haar(L, seed: int) -> np.ndarray:
+    V = volume(L)
+    return haar_su3(rng(seed), 4 * V).reshape(4, V, 3, 3)
+
+
+def gaussian_field(L, n: int, seed: int) -> np.ndarray:
+    """n complex Gaussian colour-vector fields on all sites, ``[n][V][3]``."""
+    return _complex_gauss(rng(seed), (n, volume(L), 3))
+
+
+def gaussian_even_source(L, n: int, seed: int) -> np.ndarray:
+    """n Gaussian sources living on even sites (odd sites are zero), ``[n][V][3]``."""
+    f = gaussian_field(L, n, seed)
+    f[:, site_parity(L) == 1, :] = 0.0
+    return f
+
+
+def su3_algebra_directions(L, n: int, seed: int) -> np.ndarray:
+    """n random su(3) directions, one traceless anti-Hermitian matrix per link.
+
+    Shape ``[n][4][V][3][3]``; each matrix is i * sum_a c_a lambda_a / 2.
+    """
+    V = volume(L)
+    H = _gaussian_hermitian(rng(seed), n * 4 * V)
+    return (1j * H).reshape(n, 4, V, 3, 3)
+
+
+def random_gauge_transform(L, seed: int) -> np.ndarray:
+    """A Haar SU(3) matrix per site, ``[V][3][3]``."""
+    return haar_su3(rng(seed), volume(L))
+
+
+def rational_shifts(n: int = 12, lo: float = 1e-4, hi: float = 10.0) -> np.ndarray:
+    """Pole positions sigma_k, log-spaced and inclusive on [lo, hi]."""
+    return np.logspace(np.log10(lo), np.log10(hi), n)
+
+
+def rational_weights(sigma: np.ndarray) -> np.ndarray:
+    """Residues alpha_k for a stand-in rational form of x^(-1/4).
+
+    The paper does not print its coefficients.  This uses the integral
+    x^(-1/4) = sin(pi/4)/pi * int_0^inf t^(-1/4) / (t + x) dt discretised on
+    the same logarithmic grid as the poles, so alpha_k = sin(pi/4)/pi *
+    sigma_k^(3/4) * Delta with Delta the log-grid step.  Every check that
+    uses them holds for any positive alpha.
+    """
+    sigma = np.asarray(sigma, dtype=np.float64)
+    if sigma.size < 2:
+        return np.ones_like(sigma)
+    delta = np.log(sigma[-1] / sigma[0]) / (sigma.size - 1)
+    return np.sin(np.pi / 4) / np.pi * sigma ** 0.75 * delta
