@@ -1,0 +1,261 @@
+/*
+ * lqcd.h -- C ABI of the MI355X (gfx950) staggered even/odd solver library.
+ *
+ * The library applies the off-diagonal blocks D_oe, D_eo of the staggered
+ * Dirac matrix and solves the shifted systems of Eq. (2),
+ *     (m^2 I - D_eo D_oe + sigma_i) x_i = b,   i = 1..r,
+ * with conjugate gradient and its multi-shift form (Sec. 2), and computes the
+ * fermion force, the link derivative of the rational pseudofermion action of
+ * Eq. (1) (Sec. 2, the MD force that dominates the run time).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Geometry: extents L = {Lx, Ly, Lz, Lt} (direction mu = 0..3 is x, y, z, t),
+ *   each even and >= 2; lex = x + Lx*(y + Ly*(z + Lz*t)); parity =
+ *   (x+y+z+t) mod 2 (0 even, 1 odd); V = Lx*Ly*Lz*Lt; Vh = V/2.  Within one
+ *   parity a site's half index is lex >> 1 (unique because Lx is even).
+ *   Boundaries are periodic in x, y, z; time is antiperiodic when
+ *   antiperiodic_t != 0 (the time links leaving the last time slice carry a
+ *   minus sign).  Staggered phases eta_mu(x) = (-1)^(x_0+...+x_{mu-1}).
+ *
+ * Hopping term (Sec. 2; the U(1) factor of Sec. 4.1 carrying the staggered
+ * phases and the antiperiodic time boundary):
+ *   (D psi)(x) = 1/2 sum_mu eta_mu(x) [ s_mu(x) U_mu(x) psi(x+mu)
+ *                                       - s_mu(x-mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *   D_oe maps even sites to odd sites, D_eo odd to even; D_oe^dag = -D_eo.
+ *
+ * Natural layouts (what callers hold):
+ *   links   complex128 [4][V][3][3]   U[mu][lex][row][col]
+ *   fields  complex128 [nrhs][V][3]
+ * Packed layouts (what the solver streams; all structure-of-arrays so that
+ * consecutive half indices are consecutive in memory):
+ *   spinor  complex  [nrhs][3][Vh]                  one parity
+ *   links   complex  [2][4][NE][Vh]  parity of the site the link leaves,
+ *           direction, element, half index.  NE = 9 (LQCD_LINKS18, full
+ *           matrix, element = 3*row+col) or NE = 6 (LQCD_LINKS12, rows 0-1;
+ *           row 2 is rebuilt as the complex conjugate of the cross product of
+ *           rows 0 and 1, Sec. 4.1 -- only valid for SU(3) links).
+ *   complex = two IEEE doubles (LQCD_F64) or two floats (LQCD_F32).
+ *
+ * Memory and streams: every data pointer is a device pointer owned by the
+ * caller, 16-byte aligned; the library never frees it.  `stream` is a
+ * hipStream_t (NULL = the default stream).  Pack, unpack, D_oe/D_eo and the
+ * force are asynchronous on that stream.  The solvers and the action read
+ * results back to the host and synchronise the stream before returning.
+ *
+ * Errors: every call validates its arguments on the host before any device
+ * work; on error nothing is written and a status != LQCD_OK is returned,
+ * with a readable detail in lqcd_last_error() (thread-local).  No C++
+ * exception crosses this boundary.
+ */
+#ifndef LQCD_H
+#define LQCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lqcd_status {
+    LQCD_OK = 0,
+    LQCD_ERR_INVALID_ARG = 1,   /* bad geometry, pointer, size or enum          */
+    LQCD_ERR_UNSUPPORTED = 2,   /* valid but not implemented combination         */
+    LQCD_ERR_WORKSPACE = 3,     /* workspace missing or smaller than required    */
+    LQCD_ERR_HIP = 4,           /* a HIP runtime call failed (detail in message) */
+    LQCD_ERR_NOT_CONVERGED = 5, /* max_iter reached; best iterate and stats kept */
+    LQCD_ERR_NUMERIC = 6        /* NaN/Inf or a non-positive curvature p.Ap      */
+};
+
+enum lqcd_prec { LQCD_F64 = 0, LQCD_F32 = 1 };
+enum lqcd_link_fmt { LQCD_LINKS18 = 0, LQCD_LINKS12 = 1 };
+
+typedef struct {
+    int32_t L[4];           /* Lx, Ly, Lz, Lt: each even and >= 2; Vh < 2^31 */
+    int32_t antiperiodic_t; /* 1: antiperiodic time boundary, 0: periodic    */
+} lqcd_geom;
+
+/* Human-readable name of a status code (static storage). */
+const char *lqcd_status_string(int status);
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char *lqcd_last_error(void);
+/* Library version: major*10000 + minor*100 + patch. */
+int lqcd_version(void);
+/* Releases cached graphs and tuning tables; later calls rebuild them. */
+int lqcd_finalize(void);
+
+/* Bytes of one packed link field ([2][4][NE][Vh] complex), 0 on bad input. */
+size_t lqcd_links_bytes(const lqcd_geom *g, int prec, int fmt);
+/* Bytes of one packed single-parity spinor ([3][Vh] complex), 0 on bad input. */
+size_t lqcd_spinor_bytes(const lqcd_geom *g, int prec);
+
+/*
+ * Pack natural complex128 links [4][V][3][3] into the packed layout of the
+ * requested precision (round to nearest for LQCD_F32) and format.
+ * LQCD_LINKS12 drops row 2, which is exact only for SU(3) links; the caller
+ * must not fold phases or boundary signs into the links (the kernels apply
+ * them).  U_packed must hold lqcd_links_bytes(g, prec, fmt) bytes.
+ */
+int lqcd_pack_links(const lqcd_geom *g, const void *U_nat, int prec, int fmt,
+                    void *U_packed, void *stream);
+
+/*
+ * Convert an already packed field into another precision/format
+ * (e.g. LQCD_F64/LQCD_LINKS18 -> LQCD_F32/LQCD_LINKS12 for the inner solver).
+ */
+int lqcd_convert_links(const lqcd_geom *g, const void *src, int src_prec, int src_fmt,
+                       void *dst, int dst_prec, int dst_fmt, void *stream);
+
+/*
+ * Unpack a packed LQCD_F64/LQCD_LINKS18 field (links or force) into natural
+ * complex128 [4][V][3][3].
+ */
+int lqcd_unpack_links(const lqcd_geom *g, const void *U_packed, void *U_nat, void *stream);
+
+/*
+ * Pack the sites of one parity of natural complex128 fields [nrhs][V][3]
+ * into packed [nrhs][3][Vh] of precision prec.  Sites of the other parity
+ * are not read.
+ */
+int lqcd_pack_spinor(const lqcd_geom *g, int parity, int prec, const void *nat,
+                     void *packed, int32_t nrhs, void *stream);
+
+/*
+ * Inverse of lqcd_pack_spinor: writes every site of nat [nrhs][V][3]
+ * (complex128); sites of the other parity are set to zero.
+ */
+int lqcd_unpack_spinor(const lqcd_geom *g, int parity, int prec, const void *packed,
+                       void *nat, int32_t nrhs, void *stream);
+
+/*
+ * D_oe (Sec. 2): out_odd = D_oe in_even for nrhs packed right-hand sides
+ * ([nrhs][3][Vh] each, precision prec) with links U_packed of (prec, fmt).
+ * Each link is loaded once per site and reused across the right-hand sides.
+ * 1 <= nrhs <= 64.  in and out must not overlap.
+ */
+int lqcd_doe(const lqcd_geom *g, int prec, int fmt, const void *U_packed,
+             const void *in_even, void *out_odd, int32_t nrhs, void *stream);
+
+/* D_eo (Sec. 2): out_even = D_eo in_odd; otherwise as lqcd_doe. */
+int lqcd_deo(const lqcd_geom *g, int prec, int fmt, const void *U_packed,
+             const void *in_odd, void *out_even, int32_t nrhs, void *stream);
+
+/*
+ * The operator of Eq. (2) on even sites:
+ *   out_even = (mass^2 + sigma) in_even - D_eo D_oe in_even
+ * computed as D_oe into tmp_odd ([nrhs][3][Vh], caller scratch) followed by
+ * D_eo with the diagonal term fused into its store (the paper's separate
+ * final sum kernel, Sec. 5.2, folded into D_eo).
+ */
+int lqcd_apply_A(const lqcd_geom *g, int prec, int fmt, const void *U_packed,
+                 double mass, double sigma, const void *in_even, void *out_even,
+                 void *tmp_odd, int32_t nrhs, void *stream);
+
+typedef struct {
+    double mass;               /* m > 0 (the operator uses m^2)                     */
+    double tol;                /* relative true residual target, 0 < tol < 1         */
+    int32_t max_iter;          /* per solve (refinement counted separately)          */
+    int32_t inner_prec;        /* LQCD_F64: plain FP64; LQCD_F32: mixed, see below   */
+    int32_t inner_fmt;         /* link format of the inner operator                  */
+    int32_t reliable_interval; /* mixed: FP64 residual recomputation period (iters)  */
+    int32_t use_graph;         /* 1: replay iteration blocks as a captured hipGraph  */
+    int32_t rhs_block;         /* right-hand sides per D_oe/D_eo link load, 0 = tuned */
+    int32_t poll_interval;     /* iterations between host convergence checks, 0 = auto */
+    int32_t max_refine;        /* rounds of per-shift refinement allowed, >= 0       */
+} lqcd_solver_params;
+
+typedef struct {
+    int32_t iters;             /* Krylov iterations of the main (multi-shift) solve */
+    int32_t reliable_updates;  /* FP64 residual recomputations                       */
+    int32_t refine_iters;      /* iterations spent in per-shift refinement           */
+    int32_t converged;         /* 1 if the true residual is <= tol                   */
+    double true_rel_residual;  /* ||b - (A+sigma) x|| / ||b||, FP64, FP64-18 links   */
+    double seconds;            /* wall time of the whole call                        */
+} lqcd_solve_stats;
+
+/* Fills p with defaults: tol 1e-10, max_iter 10000, F64 inner, LINKS18,
+ * reliable_interval 100, use_graph 1, rhs_block 0, poll 0, max_refine 3. */
+void lqcd_solver_params_default(lqcd_solver_params *p);
+
+/* Device workspace that lqcd_cg / lqcd_cg_multishift need for these sizes. */
+size_t lqcd_solver_workspace_bytes(const lqcd_geom *g, const lqcd_solver_params *p,
+                                   int32_t nshift, int32_t nrhs);
+
+/*
+ * Conjugate gradient on one shifted system of Eq. (2) for nrhs independent
+ * right-hand sides:  ((m^2 + sigma) - D_eo D_oe) x_j = b_j.
+ *   U64_packed   LQCD_F64/LQCD_LINKS18 links (used for every FP64 residual)
+ *   Uinner       links of (inner_prec, inner_fmt) or NULL (then converted
+ *                from U64_packed into the workspace); ignored for F64/18
+ *   b            packed even FP64 [nrhs][3][Vh]
+ *   x            packed even FP64 [nrhs][3][Vh]; on entry the initial guess
+ *   stats        host array [nrhs]
+ * Mixed precision (inner_prec = LQCD_F32): the Krylov iteration runs in FP32
+ * and every reliable_interval iterations the FP32 correction is added into
+ * the FP64 solution and the residual is recomputed in FP64 (Sec. 6: the
+ * production split, single precision for MD and double for the accept step).
+ * Dot products, norms and the CG scalars are always FP64.
+ * Returns LQCD_ERR_NOT_CONVERGED if any system misses tol within max_iter
+ * (x holds the best iterate, stats are filled).
+ */
+int lqcd_cg(const lqcd_geom *g, const lqcd_solver_params *p, const void *U64_packed,
+            const void *Uinner, double sigma, const void *b, void *x, int32_t nrhs,
+            lqcd_solve_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Multi-shift CG (Sec. 2): solves all systems of Eq. (2)
+ *   ((m^2 + sigma_i) - D_eo D_oe) x_ji = b_j,  i < nshift, j < nrhs
+ * from one Krylov sequence per right-hand side, built on the smallest shift.
+ *   sigma   host [nshift], each >= 0, 1 <= nshift <= 32
+ *   b       packed even FP64 [nrhs][3][Vh]
+ *   x       packed even FP64 [nrhs][nshift][3][Vh] (output; not read)
+ *   stats   host [nrhs][nshift]
+ * A shift stops updating once its collinear residual is below tol.  After
+ * the base system converges, the FP64 true residual of every (j, i) is
+ * computed; systems above tol are refined together by warm-started CG on
+ * their residuals, up to max_refine rounds.  All right-hand sides share each
+ * link load in D_oe/D_eo.  1 <= nrhs <= 64.
+ */
+int lqcd_cg_multishift(const lqcd_geom *g, const lqcd_solver_params *p,
+                       const void *U64_packed, const void *Uinner, int32_t nshift,
+                       const double *sigma, const void *b, void *x, int32_t nrhs,
+                       lqcd_solve_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Fermion force (Sec. 2): the derivative of
+ *   S = sum_j sum_i alpha_i Re <phi_j, X_ji>,  X_ji = (A + sigma_i)^-1 phi_j,
+ * with respect to the links, given the solutions X.  With M_mu(x) defined by
+ * dS = sum_{x,mu} Re Tr[dU_mu(x) M_mu(x)]:
+ *   mode 0: F = TA(U M), TA(W) = (W - W^dag)/2 - Tr(W - W^dag)/6, the su(3)
+ *           force (dS/deps = sum Tr[T F] for U -> exp(eps T) U, T in su(3));
+ *   mode 1: F = M^dag = dS/dRe U + i dS/dIm U (torch's gradient convention).
+ *   U64_packed  LQCD_F64/LQCD_LINKS18 links
+ *   alpha       host [nshift]
+ *   X           packed even FP64 [npf][nshift][3][Vh]
+ *   F           packed FP64 [2][4][9][Vh] (layout of LQCD_LINKS18 links);
+ *               accumulate != 0 adds into F instead of overwriting it.
+ * D_oe X is recomputed per odd site in registers, never stored; each link is
+ * written by exactly one thread (no atomics).
+ */
+int lqcd_fermion_force(const lqcd_geom *g, const void *U64_packed, int32_t npf,
+                       int32_t nshift, const double *alpha, const void *X, int32_t mode,
+                       int32_t accumulate, void *F, void *stream);
+
+/*
+ * Rational pseudofermion action (Eq. (1) fermion term in rational form):
+ *   S = sum_j [ alpha0 ||phi_j||^2 + sum_i alpha_i Re <phi_j, X_ji> ]
+ *   phi  packed even FP64 [npf][3][Vh];  X as for lqcd_fermion_force.
+ * The result (FP64, fixed-order reduction) is written to *S on the host.
+ * ws must hold lqcd_action_workspace_bytes(g) bytes.
+ */
+size_t lqcd_action_workspace_bytes(const lqcd_geom *g);
+int lqcd_action(const lqcd_geom *g, int32_t npf, int32_t nshift, double alpha0,
+                const double *alpha, const void *phi, const void *X, double *S,
+                void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQCD_H */

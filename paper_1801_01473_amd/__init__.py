@@ -1,0 +1,404 @@
+"""Python binding of liblqcd, the MI355X staggered even/odd solver library.
+
+Argument marshalling only: every operation runs in the library's HIP kernels.
+Tensors are torch tensors on the GPU (torch provides device memory and the
+current stream).  The binding fails loudly when the library has not been
+built; there is no CPU fallback.
+
+Layouts follow ``include/lqcd.h``:
+  natural links   complex128 [4][V][3][3]     natural fields complex128 [n][V][3]
+  packed links    complex128/complex64 [2][4][NE][Vh]  (NE = 9 or 6)
+  packed spinors  complex128/complex64 [n][3][Vh] (one parity)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblqcd.so")
+
+F64, F32 = 0, 1
+LINKS18, LINKS12 = 0, 1
+
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_UNSUPPORTED = 2
+ERR_WORKSPACE = 3
+ERR_HIP = 4
+ERR_NOT_CONVERGED = 5
+ERR_NUMERIC = 6
+
+
+class LqcdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it first (python -m paper_1801_01473_amd.build "
+        "or __graft_entry__.build()); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class lqcd_geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("antiperiodic_t", ctypes.c_int32)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+        ("inner_prec", ctypes.c_int32), ("inner_fmt", ctypes.c_int32),
+        ("reliable_interval", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+        ("rhs_block", ctypes.c_int32), ("poll_interval", ctypes.c_int32),
+        ("max_refine", ctypes.c_int32),
+    ]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+        ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_gp = ctypes.POINTER(lqcd_geom)
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+_dp = ctypes.POINTER(ctypes.c_double)
+_pp = ctypes.POINTER(SolverParams)
+_sp = ctypes.POINTER(SolveStats)
+
+_SIGS = {
+    "lqcd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "lqcd_last_error": (ctypes.c_char_p, []),
+    "lqcd_version": (ctypes.c_int, []),
+    "lqcd_finalize": (ctypes.c_int, []),
+    "lqcd_links_bytes": (ctypes.c_size_t, [_gp, ctypes.c_int, ctypes.c_int]),
+    "lqcd_spinor_bytes": (ctypes.c_size_t, [_gp, ctypes.c_int]),
+    "lqcd_pack_links": (ctypes.c_int, [_gp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "lqcd_convert_links": (ctypes.c_int, [_gp, _vp, ctypes.c_int, ctypes.c_int, _vp,
+                                          ctypes.c_int, ctypes.c_int, _vp]),
+    "lqcd_unpack_links": (ctypes.c_int, [_gp, _vp, _vp, _vp]),
+    "lqcd_pack_spinor": (ctypes.c_int, [_gp, ctypes.c_int, ctypes.c_int, _vp, _vp, _i32, _vp]),
+    "lqcd_unpack_spinor": (ctypes.c_int, [_gp, ctypes.c_int, ctypes.c_int, _vp, _vp, _i32, _vp]),
+    "lqcd_doe": (ctypes.c_int, [_gp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _i32, _vp]),
+    "lqcd_deo": (ctypes.c_int, [_gp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _i32, _vp]),
+    "lqcd_apply_A": (ctypes.c_int, [_gp, ctypes.c_int, ctypes.c_int, _vp, _dbl, _dbl, _vp, _vp,
+                                    _vp, _i32, _vp]),
+    "lqcd_solver_params_default": (None, [_pp]),
+    "lqcd_solver_workspace_bytes": (ctypes.c_size_t, [_gp, _pp, _i32, _i32]),
+    "lqcd_cg": (ctypes.c_int, [_gp, _pp, _vp, _vp, _dbl, _vp, _vp, _i32, _sp, _vp,
+                               ctypes.c_size_t, _vp]),
+    "lqcd_cg_multishift": (ctypes.c_int, [_gp, _pp, _vp, _vp, _i32, _dp, _vp, _vp, _i32, _sp,
+                                          _vp, ctypes.c_size_t, _vp]),
+    "lqcd_fermion_force": (ctypes.c_int, [_gp, _vp, _i32, _i32, _dp, _vp, _i32, _i32, _vp, _vp]),
+    "lqcd_action_workspace_bytes": (ctypes.c_size_t, [_gp]),
+    "lqcd_action": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp,
+                                   ctypes.c_size_t, _vp]),
+}
+
+EXPORTED = tuple(_SIGS)
+_fns = {}
+
+
+def _fn(name):
+    f = _fns.get(name)
+    if f is None:
+        f = getattr(_lib, name)
+        f.restype, f.argtypes = _SIGS[name]
+        _fns[name] = f
+    return f
+
+
+def status_string(s: int) -> str:
+    return _fn("lqcd_status_string")(s).decode()
+
+
+def last_error() -> str:
+    return _fn("lqcd_last_error")().decode()
+
+
+def version() -> int:
+    return int(_fn("lqcd_version")())
+
+
+def finalize() -> None:
+    _check(_fn("lqcd_finalize")())
+
+
+def _check(status: int, allow=()):
+    if status != OK and status not in allow:
+        raise LqcdError(status, f"{status_string(status)}: {last_error()}")
+    return status
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return _vp(0)
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return _vp(t.data_ptr())
+
+
+@dataclass(frozen=True)
+class Geometry:
+    L: tuple
+    antiperiodic: bool = True
+
+    @property
+    def V(self) -> int:
+        return self.L[0] * self.L[1] * self.L[2] * self.L[3]
+
+    @property
+    def Vh(self) -> int:
+        return self.V // 2
+
+    def c(self):
+        g = lqcd_geom()
+        for i in range(4):
+            g.L[i] = int(self.L[i])
+        g.antiperiodic_t = 1 if self.antiperiodic else 0
+        return ctypes.byref(g)
+
+
+def _cdtype(prec):
+    return torch.complex128 if prec == F64 else torch.complex64
+
+
+def _ne(fmt):
+    return 9 if fmt == LINKS18 else 6
+
+
+def links_bytes(geom: Geometry, prec=F64, fmt=LINKS18) -> int:
+    return int(_fn("lqcd_links_bytes")(geom.c(), prec, fmt))
+
+
+def spinor_bytes(geom: Geometry, prec=F64) -> int:
+    return int(_fn("lqcd_spinor_bytes")(geom.c(), prec))
+
+
+def empty_links(geom: Geometry, prec=F64, fmt=LINKS18, device="cuda"):
+    return torch.empty((2, 4, _ne(fmt), geom.Vh), dtype=_cdtype(prec), device=device)
+
+
+def empty_spinor(geom: Geometry, n=1, prec=F64, device="cuda"):
+    return torch.empty((n, 3, geom.Vh), dtype=_cdtype(prec), device=device)
+
+
+def pack_links(geom: Geometry, U_nat: torch.Tensor, prec=F64, fmt=LINKS18, out=None):
+    if U_nat.dtype != torch.complex128 or tuple(U_nat.shape) != (4, geom.V, 3, 3):
+        raise ValueError("U_nat must be complex128 [4][V][3][3]")
+    out = empty_links(geom, prec, fmt, U_nat.device) if out is None else out
+    _check(_fn("lqcd_pack_links")(geom.c(), _ptr(U_nat), prec, fmt, _ptr(out), _stream()))
+    return out
+
+
+def convert_links(geom: Geometry, src, src_prec, src_fmt, dst_prec, dst_fmt, out=None):
+    out = empty_links(geom, dst_prec, dst_fmt, src.device) if out is None else out
+    _check(_fn("lqcd_convert_links")(geom.c(), _ptr(src), src_prec, src_fmt, _ptr(out),
+                                     dst_prec, dst_fmt, _stream()))
+    return out
+
+
+def unpack_links(geom: Geometry, U_packed, out=None):
+    out = torch.empty((4, geom.V, 3, 3), dtype=torch.complex128,
+                      device=U_packed.device) if out is None else out
+    _check(_fn("lqcd_unpack_links")(geom.c(), _ptr(U_packed), _ptr(out), _stream()))
+    return out
+
+
+def pack_spinor(geom: Geometry, nat: torch.Tensor, parity: int, prec=F64, out=None):
+    nat = nat.reshape(-1, geom.V, 3)
+    if nat.dtype != torch.complex128:
+        raise ValueError("natural fields must be complex128")
+    n = nat.shape[0]
+    out = empty_spinor(geom, n, prec, nat.device) if out is None else out
+    _check(_fn("lqcd_pack_spinor")(geom.c(), parity, prec, _ptr(nat), _ptr(out), n, _stream()))
+    return out
+
+
+def unpack_spinor(geom: Geometry, packed: torch.Tensor, parity: int, out=None):
+    prec = F64 if packed.dtype == torch.complex128 else F32
+    n = packed.numel() // (3 * geom.Vh)
+    out = torch.empty((n, geom.V, 3), dtype=torch.complex128,
+                      device=packed.device) if out is None else out
+    _check(_fn("lqcd_unpack_spinor")(geom.c(), parity, prec, _ptr(packed), _ptr(out), n,
+                                     _stream()))
+    return out
+
+
+def _prec_of(t):
+    return F64 if t.dtype == torch.complex128 else F32
+
+
+def _fmt_of(U):
+    return LINKS18 if U.shape[2] == 9 else LINKS12
+
+
+def doe(geom: Geometry, U, psi_even, out=None):
+    """D_oe: packed even spinors [n][3][Vh] -> packed odd spinors."""
+    n = psi_even.numel() // (3 * geom.Vh)
+    out = torch.empty_like(psi_even) if out is None else out
+    _check(_fn("lqcd_doe")(geom.c(), _prec_of(U), _fmt_of(U), _ptr(U), _ptr(psi_even),
+                           _ptr(out), n, _stream()))
+    return out
+
+
+def deo(geom: Geometry, U, psi_odd, out=None):
+    """D_eo: packed odd spinors -> packed even spinors."""
+    n = psi_odd.numel() // (3 * geom.Vh)
+    out = torch.empty_like(psi_odd) if out is None else out
+    _check(_fn("lqcd_deo")(geom.c(), _prec_of(U), _fmt_of(U), _ptr(U), _ptr(psi_odd),
+                           _ptr(out), n, _stream()))
+    return out
+
+
+def apply_A(geom: Geometry, U, mass, sigma, x_even, out=None, tmp=None):
+    """((m^2 + sigma) - D_eo D_oe) x on packed even spinors."""
+    n = x_even.numel() // (3 * geom.Vh)
+    out = torch.empty_like(x_even) if out is None else out
+    tmp = torch.empty_like(x_even) if tmp is None else tmp
+    _check(_fn("lqcd_apply_A")(geom.c(), _prec_of(U), _fmt_of(U), _ptr(U), float(mass),
+                               float(sigma), _ptr(x_even), _ptr(out), _ptr(tmp), n, _stream()))
+    return out
+
+
+def solver_params(**kw) -> SolverParams:
+    p = SolverParams()
+    _fn("lqcd_solver_params_default")(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def solver_workspace_bytes(geom: Geometry, params: SolverParams, nshift: int, nrhs: int) -> int:
+    return int(_fn("lqcd_solver_workspace_bytes")(geom.c(), ctypes.byref(params), nshift, nrhs))
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    key = str(device)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        _ws_cache[key] = None
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def release_workspace() -> None:
+    _ws_cache.clear()
+
+
+def cg(geom: Geometry, params: SolverParams, U64, b, x=None, sigma=0.0, Uinner=None,
+       check=True):
+    """CG on ((m^2 + sigma) - D_eo D_oe) x = b for packed FP64 even b [n][3][Vh].
+
+    Returns (x, status, [stats per right-hand side]).  x holds the initial
+    guess on entry when given.
+    """
+    n = b.numel() // (3 * geom.Vh)
+    x = torch.zeros_like(b) if x is None else x
+    ws_bytes = solver_workspace_bytes(geom, params, 1, n)
+    ws = _workspace(ws_bytes, b.device)
+    stats = (SolveStats * n)()
+    st = _fn("lqcd_cg")(geom.c(), ctypes.byref(params), _ptr(U64), _ptr(Uinner), float(sigma),
+                        _ptr(b), _ptr(x), n, stats, _ptr(ws), ws.numel(), _stream())
+    if check:
+        _check(st)
+    return x, st, [s.as_dict() for s in stats]
+
+
+def cg_multishift(geom: Geometry, params: SolverParams, U64, sigmas, b, x=None, Uinner=None,
+                  check=True):
+    """Multi-shift CG.  b: packed FP64 even [n][3][Vh]; returns x [n][nshift][3][Vh]."""
+    n = b.numel() // (3 * geom.Vh)
+    sig = (ctypes.c_double * len(sigmas))(*[float(s) for s in sigmas])
+    ns = len(sigmas)
+    if x is None:
+        x = torch.empty((n, ns, 3, geom.Vh), dtype=torch.complex128, device=b.device)
+    ws_bytes = solver_workspace_bytes(geom, params, ns, n)
+    ws = _workspace(ws_bytes, b.device)
+    stats = (SolveStats * (n * ns))()
+    st = _fn("lqcd_cg_multishift")(geom.c(), ctypes.byref(params), _ptr(U64), _ptr(Uinner), ns,
+                                   sig, _ptr(b), _ptr(x), n, stats, _ptr(ws), ws.numel(),
+                                   _stream())
+    if check:
+        _check(st)
+    return x, st, [[stats[j * ns + i].as_dict() for i in range(ns)] for j in range(n)]
+
+
+def fermion_force(geom: Geometry, U64, alpha, X, mode=0, out=None, accumulate=False):
+    """Force from solutions X [npf][nshift][3][Vh] (packed FP64 even).
+
+    mode 0: TA(U M) (su(3) force); mode 1: M^dag (raw gradient).  Output in the
+    packed FP64 18-real link layout [2][4][9][Vh].
+    """
+    nshift = len(alpha)
+    npf = X.numel() // (nshift * 3 * geom.Vh)
+    al = (ctypes.c_double * nshift)(*[float(a) for a in alpha])
+    out = empty_links(geom, F64, LINKS18, X.device) if out is None else out
+    _check(_fn("lqcd_fermion_force")(geom.c(), _ptr(U64), npf, nshift, al, _ptr(X), int(mode),
+                                     1 if accumulate else 0, _ptr(out), _stream()))
+    return out
+
+
+def action(geom: Geometry, alpha0, alpha, phi, X) -> float:
+    nshift = len(alpha)
+    npf = phi.numel() // (3 * geom.Vh)
+    al = (ctypes.c_double * nshift)(*[float(a) for a in alpha])
+    nbytes = int(_fn("lqcd_action_workspace_bytes")(geom.c()))
+    ws = _workspace(nbytes, phi.device)
+    S = ctypes.c_double(0.0)
+    _check(_fn("lqcd_action")(geom.c(), npf, nshift, float(alpha0), al, _ptr(phi), _ptr(X),
+                              ctypes.byref(S), _ptr(ws), ws.numel(), _stream()))
+    return float(S.value)
+
+
+class FermionAction(torch.autograd.Function):
+    """S_f(U) = sum_j [alpha0 |phi_j|^2 + sum_i alpha_i <phi_j, (A[U] + sigma_i)^-1 phi_j>].
+
+    Forward: multi-shift CG for all shifts and pseudofermions, then the FP64
+    action.  Backward: the adjoint force kernel in raw mode, whose output M^dag
+    is torch's gradient for complex inputs (dS/dRe U + i dS/dIm U).
+
+    U_nat: complex128 [4][V][3][3] on the GPU; phi: packed FP64 even [npf][3][Vh].
+    """
+
+    @staticmethod
+    def forward(ctx, U_nat, phi, geom, alpha0, alpha, sigma, params):
+        U64 = pack_links(geom, U_nat.detach().contiguous())
+        X, _, _ = cg_multishift(geom, params, U64, sigma, phi)
+        S = action(geom, alpha0, alpha, phi, X)
+        ctx.save_for_backward(X)
+        ctx.geom, ctx.alpha, ctx.U64 = geom, list(alpha), U64
+        return torch.tensor(S, dtype=torch.float64, device=U_nat.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (X,) = ctx.saved_tensors
+        G = fermion_force(ctx.geom, ctx.U64, ctx.alpha, X, mode=1)
+        G_nat = unpack_links(ctx.geom, G)
+        return grad_out * G_nat, None, None, None, None, None, None

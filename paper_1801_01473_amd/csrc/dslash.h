@@ -1,0 +1,69 @@
+// Internal interface of the D_oe / D_eo kernel family.
+#pragma once
+
+#include "common.h"
+
+namespace lqcd {
+
+// What the kernel does with acc = (D in)(x) at its output site:
+enum DMode {
+  DM_PLAIN = 0,  // out = acc                       (+ sum |acc|^2 if partials)
+  DM_AXPY = 1,   // out = m2s * diag - acc          (operator of Eq. (2))
+  DM_CG = 2,     // r -= alpha * (m2s * diag - acc) (+ sum |r|^2)
+  DM_RES = 3     // res = b - (m2s * diag - acc), FP64; r = res if r (+ sum |res|^2)
+};
+
+struct DslashCall {
+  KGeom g;
+  int out_par = 0;        // parity of the output sites (1: D_oe, 0: D_eo)
+  int prec = LQCD_F64;    // links, input and arithmetic
+  int fmt = LQCD_LINKS18;
+  int nrhs = 1;
+  int mode = DM_PLAIN;
+  int r_prec = LQCD_F64;  // DM_RES: precision of the stored residual
+  const void* U = nullptr;
+  const void* in = nullptr;
+  int64_t in_stride = 0;  // complex elements between consecutive right-hand sides
+  void* out = nullptr;
+  int64_t out_stride = 0;
+  const void* diag = nullptr;
+  int64_t diag_stride = 0;
+  void* r = nullptr;
+  int64_t r_stride = 0;
+  const void* b = nullptr;  // DM_RES: FP64 right-hand side
+  int64_t b_stride = 0;
+  const double* m2s = nullptr;  // per right-hand side diagonal, or m2s_c when null
+  int m2s_stride = 0;           // in doubles
+  double m2s_c = 0.0;
+  const double* alpha = nullptr;
+  int alpha_stride = 0;
+  const int* live = nullptr;  // per right-hand side work flag, null = all
+  int live_stride = 0;        // in ints
+  const int* halt = nullptr;  // early-exit flag checked at kernel entry
+  double* partials = nullptr; // [nrhs][nblocks]
+};
+
+struct DslashCfg {
+  int block = 256;  // threads per workgroup (64, 128, 256)
+  int rhs_block = 1;  // right-hand sides sharing one link load (1, 2, 4, 8)
+  int xcd = 1;      // XCD-contiguous block remap
+};
+
+// Number of workgroups along the site dimension for a configuration.
+inline int dslash_nblocks(const KGeom& g, const DslashCfg& c) {
+  return (g.Vh + c.block - 1) / c.block;
+}
+// Largest partials array any configuration can need.
+inline size_t dslash_partials_max(const KGeom& g, int nrhs) {
+  return size_t(nrhs) * size_t((g.Vh + 63) / 64);
+}
+
+int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);
+
+// Tuned configuration for this call's shape (times candidates on first use
+// with private scratch buffers; cached per process).  `forced_rhs_block` > 0
+// pins the right-hand-side block.
+int dslash_tuned(const DslashCall& c, int forced_rhs_block, hipStream_t st, DslashCfg* out);
+void dslash_clear_tuning();
+
+}  // namespace lqcd

@@ -1,0 +1,448 @@
+// The staggered hopping term D_oe / D_eo (Sec. 2) on one GPU.
+//
+// One thread per output site; each thread
+//   * decodes its coordinates and the half indices of its 8 neighbours with
+//     periodic wrap, and the staggered phase / antiperiodic time sign from
+//     the coordinates (Sec. 4.1 carries both in a U(1) factor; for +-1
+//     factors nothing needs to be stored),
+//   * loads each of its 8 links once (rebuilding row 2 for the 12-real
+//     format) and applies it to up to B right-hand sides, so B spinor fields
+//     share one link stream,
+//   * writes the result, or folds it into the solver's vector update
+//     (the paper's separate final sum kernel of Eq. (2), Sec. 5.2), and
+//     accumulates FP64 block partials of the norms the solver needs.
+// Links dominate the traffic (8 links per site vs 8+1 spinors): every link of
+// the lattice is read exactly once per application, spinor neighbour reuse
+// comes from L2 / MALL.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "dslash.h"
+#include "su3.h"
+
+namespace lqcd {
+
+namespace {
+
+template <typename R, int NE, int B, int MODE, typename RO>
+__global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xcd) {
+  __shared__ double lds[B][4];
+  if (a.halt && *a.halt) return;
+  const KGeom& g = a.g;
+  const int rhs0 = blockIdx.y * B;
+  bool lv[B];
+  bool any = false;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = rhs0 + b;
+    lv[b] = j < a.nrhs && (a.live == nullptr || a.live[j * a.live_stride] != 0);
+    any |= lv[b];
+  }
+  if (!any) return;  // uniform over the block
+
+  const int blk = xcd_block(blockIdx.x, gridDim.x, xcd);
+  const int h = blk * blockDim.x + threadIdx.x;
+  double nrm[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) nrm[b] = 0.0;
+
+  if (h < g.Vh) {
+    const Site s = decode_site(g, h, a.out_par);
+    int fwd[4], bwd[4];
+    neighbours(g, s, h, fwd, bwd);
+    double eta[4];
+    staggered_eta(s, eta);
+
+    cplx<R> acc[B][3];
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[b][c] = mk<R>(0, 0);
+
+    const int64_t par_stride = int64_t(4) * NE * g.Vh;
+    const cplx<R>* Uout = static_cast<const cplx<R>*>(a.U) + a.out_par * par_stride;
+    const cplx<R>* Uin = static_cast<const cplx<R>*>(a.U) + (1 - a.out_par) * par_stride;
+    const cplx<R>* in = static_cast<const cplx<R>*>(a.in) + int64_t(rhs0) * a.in_stride;
+
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      R cf = R(0.5 * eta[mu]), cb = cf;
+      if (mu == 3 && g.anti) {
+        if (s.t == g.Lt - 1) cf = -cf;  // link (x, t) crosses the time boundary
+        if (s.t == 0) cb = -cb;         // link (x - t, t) crosses it
+      }
+      {
+        Su3<R> u;
+        load_link<R, NE>(Uout + int64_t(mu) * NE * g.Vh, h, g.Vh, u);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          if (!lv[b]) continue;
+          cplx<R> v[3], y[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[c] = in[b * a.in_stride + int64_t(c) * g.Vh + fwd[mu]];
+          mat_vec<R>(u, v, y);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            acc[b][c].x = fma(cf, y[c].x, acc[b][c].x);
+            acc[b][c].y = fma(cf, y[c].y, acc[b][c].y);
+          }
+        }
+      }
+      {
+        Su3<R> u;
+        load_link<R, NE>(Uin + int64_t(mu) * NE * g.Vh, bwd[mu], g.Vh, u);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          if (!lv[b]) continue;
+          cplx<R> v[3], y[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[c] = in[b * a.in_stride + int64_t(c) * g.Vh + bwd[mu]];
+          adj_mat_vec<R>(u, v, y);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            acc[b][c].x = fma(-cb, y[c].x, acc[b][c].x);
+            acc[b][c].y = fma(-cb, y[c].y, acc[b][c].y);
+          }
+        }
+      }
+    }
+
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (!lv[b]) continue;
+      const int j = rhs0 + b;
+      if (MODE == DM_PLAIN) {
+        cplx<R>* out = static_cast<cplx<R>*>(a.out) + int64_t(j) * a.out_stride + h;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          out[int64_t(c) * g.Vh] = acc[b][c];
+          nrm[b] += cnorm2<R>(acc[b][c]);
+        }
+      } else {
+        const double m2s = a.m2s ? a.m2s[j * a.m2s_stride] : a.m2s_c;
+        const cplx<R>* d = static_cast<const cplx<R>*>(a.diag) + int64_t(j) * a.diag_stride + h;
+        if (MODE == DM_AXPY) {
+          cplx<R>* out = static_cast<cplx<R>*>(a.out) + int64_t(j) * a.out_stride + h;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const cplx<R> dv = d[int64_t(c) * g.Vh];
+            out[int64_t(c) * g.Vh] =
+                mk<R>(fma(R(m2s), dv.x, -acc[b][c].x), fma(R(m2s), dv.y, -acc[b][c].y));
+          }
+        } else if (MODE == DM_CG) {
+          const R al = R(a.alpha[j * a.alpha_stride]);
+          cplx<R>* r = static_cast<cplx<R>*>(a.r) + int64_t(j) * a.r_stride + h;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const cplx<R> dv = d[int64_t(c) * g.Vh];
+            const R wx = fma(R(m2s), dv.x, -acc[b][c].x);
+            const R wy = fma(R(m2s), dv.y, -acc[b][c].y);
+            cplx<R> rv = r[int64_t(c) * g.Vh];
+            rv.x = fma(-al, wx, rv.x);
+            rv.y = fma(-al, wy, rv.y);
+            r[int64_t(c) * g.Vh] = rv;
+            nrm[b] += cnorm2<R>(rv);
+          }
+        } else {  // DM_RES, R = double
+          const double2* bv = static_cast<const double2*>(a.b) + int64_t(j) * a.b_stride + h;
+          cplx<RO>* r = a.r ? static_cast<cplx<RO>*>(a.r) + int64_t(j) * a.r_stride + h : nullptr;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const cplx<R> dv = d[int64_t(c) * g.Vh];
+            const double2 bb = bv[int64_t(c) * g.Vh];
+            const double rx = bb.x - fma(m2s, (double)dv.x, -(double)acc[b][c].x);
+            const double ry = bb.y - fma(m2s, (double)dv.y, -(double)acc[b][c].y);
+            if (r) r[int64_t(c) * g.Vh] = mk<RO>(RO(rx), RO(ry));
+            nrm[b] += rx * rx + ry * ry;
+          }
+        }
+      }
+    }
+  }
+
+  if (a.partials) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const double sum = block_sum(nrm[b], lds[b]);
+      if (threadIdx.x == 0 && lv[b]) a.partials[int64_t(rhs0 + b) * gridDim.x + blk] = sum;
+    }
+  }
+}
+
+template <typename R, int NE, int B, int MODE, typename RO>
+int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
+  const dim3 grid(dslash_nblocks(c.g, cfg), (c.nrhs + B - 1) / B);
+  hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO>), grid, dim3(cfg.block), 0, st, c, cfg.xcd);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+template <typename R, int NE, int MODE, typename RO>
+int launch_b(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
+  switch (cfg.rhs_block) {
+    case 1: return launch_one<R, NE, 1, MODE, RO>(c, cfg, st);
+    case 2: return launch_one<R, NE, 2, MODE, RO>(c, cfg, st);
+    case 4: return launch_one<R, NE, 4, MODE, RO>(c, cfg, st);
+    case 8: return launch_one<R, NE, 8, MODE, RO>(c, cfg, st);
+    default:
+      set_error("unsupported right-hand-side block %d", cfg.rhs_block);
+      return LQCD_ERR_UNSUPPORTED;
+  }
+}
+
+template <typename R, int NE>
+int launch_mode(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
+  switch (c.mode) {
+    case DM_PLAIN: return launch_b<R, NE, DM_PLAIN, R>(c, cfg, st);
+    case DM_AXPY: return launch_b<R, NE, DM_AXPY, R>(c, cfg, st);
+    case DM_CG: return launch_b<R, NE, DM_CG, R>(c, cfg, st);
+    default: break;
+  }
+  set_error("dslash mode %d not available for this precision/format", c.mode);
+  return LQCD_ERR_UNSUPPORTED;
+}
+
+}  // namespace
+
+int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
+  if (cfg.block != 64 && cfg.block != 128 && cfg.block != 256) {
+    set_error("unsupported dslash block size %d", cfg.block);
+    return LQCD_ERR_UNSUPPORTED;
+  }
+  if (c.mode == DM_RES) {
+    if (c.prec != LQCD_F64 || c.fmt != LQCD_LINKS18) {
+      set_error("residual mode needs FP64 18-real links");
+      return LQCD_ERR_UNSUPPORTED;
+    }
+    if (c.r_prec == LQCD_F32) return launch_b<double, 9, DM_RES, float>(c, cfg, st);
+    return launch_b<double, 9, DM_RES, double>(c, cfg, st);
+  }
+  if (c.prec == LQCD_F64)
+    return c.fmt == LQCD_LINKS12 ? launch_mode<double, 6>(c, cfg, st)
+                                 : launch_mode<double, 9>(c, cfg, st);
+  return c.fmt == LQCD_LINKS12 ? launch_mode<float, 6>(c, cfg, st)
+                               : launch_mode<float, 9>(c, cfg, st);
+}
+
+// ----------------------------------------------------------------- tuner
+
+namespace {
+
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, DslashCfg> g_tune;
+
+DslashCfg default_cfg(int nrhs, int forced) {
+  DslashCfg c;
+  c.block = 256;
+  c.xcd = 1;
+  int b = 1;
+  while (b * 2 <= std::min(nrhs, 8)) b *= 2;
+  c.rhs_block = forced > 0 ? forced : b;
+  return c;
+}
+
+bool tuning_enabled() {
+  const char* e = std::getenv("LQCD_TUNE");
+  return !(e && e[0] == '0');
+}
+
+bool tuning_verbose() {
+  const char* e = std::getenv("LQCD_TUNE_VERBOSE");
+  return e && e[0] == '1';
+}
+
+}  // namespace
+
+void dslash_clear_tuning() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out) {
+  if (forced != 0 && forced != 1 && forced != 2 && forced != 4 && forced != 8) {
+    set_error("rhs_block must be 0 (tuned), 1, 2, 4 or 8, got %d", forced);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const TuneKey key{c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, c.prec, c.fmt, c.nrhs, forced,
+                    c.mode == DM_RES ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *out = it->second;
+      return LQCD_OK;
+    }
+  }
+  DslashCfg best = default_cfg(c.nrhs, forced);
+  if (!tuning_enabled()) {
+    *out = best;
+    return LQCD_OK;
+  }
+
+  // Candidates are timed in plain mode on private scratch fields with the
+  // caller's links, so no caller data is touched.
+  std::vector<DslashCfg> cand;
+  for (int blk : {64, 128, 256})
+    for (int b : {1, 2, 4, 8}) {
+      if (forced ? b != forced : b > c.nrhs) continue;
+      for (int x : {0, 1}) cand.push_back(DslashCfg{blk, b, x});
+    }
+
+  const size_t vec = size_t(3) * c.g.Vh * 2 * (c.prec == LQCD_F32 ? 4 : 8);
+  void* scratch = nullptr;
+  LQCD_HIP_TRY(hipStreamSynchronize(st));
+  LQCD_HIP_TRY(hipMalloc(&scratch, 2 * vec * c.nrhs));
+  LQCD_HIP_TRY(hipMemsetAsync(scratch, 0, 2 * vec * c.nrhs, st));
+  hipEvent_t e0, e1;
+  LQCD_HIP_TRY(hipEventCreate(&e0));
+  LQCD_HIP_TRY(hipEventCreate(&e1));
+
+  DslashCall t = c;
+  t.mode = DM_PLAIN;
+  t.in = scratch;
+  t.in_stride = int64_t(3) * c.g.Vh;
+  t.out = static_cast<char*>(scratch) + vec * c.nrhs;
+  t.out_stride = int64_t(3) * c.g.Vh;
+  t.live = nullptr;
+  t.halt = nullptr;
+  t.partials = nullptr;
+  t.prec = c.prec;
+  t.fmt = c.fmt;
+  if (c.mode == DM_RES) {  // the residual kernels run on FP64 18-real links
+    t.prec = LQCD_F64;
+    t.fmt = LQCD_LINKS18;
+  }
+
+  float best_ms = 1e30f;
+  int rc = LQCD_OK;
+  for (const DslashCfg& cfg : cand) {
+    if ((rc = dslash_launch(t, cfg, st)) != LQCD_OK) break;  // warm-up
+    constexpr int kReps = 4;
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < kReps; ++i) dslash_launch(t, cfg, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      set_error("dslash tuning run failed");
+      rc = LQCD_ERR_HIP;
+      break;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (tuning_verbose())
+      fprintf(stderr, "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d block=%d B=%d xcd=%d: %.2f us\n",
+              c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, cfg.block, cfg.rhs_block,
+              cfg.xcd, 1000.0 * ms / kReps);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cfg;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(scratch);
+  if (rc != LQCD_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+  }
+  *out = best;
+  return LQCD_OK;
+}
+
+}  // namespace lqcd
+
+// ----------------------------------------------------------------- C ABI
+
+using namespace lqcd;
+
+namespace {
+
+int hop_entry(const lqcd_geom* g, int prec, int fmt, const void* U, const void* in, void* out,
+              int32_t nrhs, void* stream, int out_par, const char* name) {
+  clear_error();
+  int st;
+  if ((st = check_geom(g)) || (st = check_prec_fmt(prec, fmt)) || (st = check_ptr(U, "U")) ||
+      (st = check_ptr(in, "in")) || (st = check_ptr(out, "out")) || (st = check_nrhs(nrhs)))
+    return st;
+  if (in == out) {
+    set_error("%s: in and out must not alias", name);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  DslashCall c;
+  c.g = make_kgeom(g);
+  c.out_par = out_par;
+  c.prec = prec;
+  c.fmt = fmt;
+  c.nrhs = nrhs;
+  c.mode = DM_PLAIN;
+  c.U = U;
+  c.in = in;
+  c.in_stride = int64_t(3) * c.g.Vh;
+  c.out = out;
+  c.out_stride = c.in_stride;
+  hipStream_t s = (hipStream_t)stream;
+  DslashCfg cfg;
+  if ((st = dslash_tuned(c, 0, s, &cfg))) return st;
+  return dslash_launch(c, cfg, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lqcd_doe(const lqcd_geom* g, int prec, int fmt, const void* U, const void* in_even,
+             void* out_odd, int32_t nrhs, void* stream) {
+  return hop_entry(g, prec, fmt, U, in_even, out_odd, nrhs, stream, 1, "lqcd_doe");
+}
+
+int lqcd_deo(const lqcd_geom* g, int prec, int fmt, const void* U, const void* in_odd,
+             void* out_even, int32_t nrhs, void* stream) {
+  return hop_entry(g, prec, fmt, U, in_odd, out_even, nrhs, stream, 0, "lqcd_deo");
+}
+
+int lqcd_apply_A(const lqcd_geom* g, int prec, int fmt, const void* U, double mass, double sigma,
+                 const void* in_even, void* out_even, void* tmp_odd, int32_t nrhs,
+                 void* stream) {
+  clear_error();
+  int st;
+  if ((st = check_ptr(tmp_odd, "tmp_odd")) || (st = check_ptr(out_even, "out_even"))) return st;
+  if (tmp_odd == in_even || tmp_odd == out_even || in_even == out_even) {
+    set_error("lqcd_apply_A: in, out and tmp must be distinct buffers");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (!(mass == mass) || !(sigma == sigma)) {
+    set_error("lqcd_apply_A: mass and sigma must be finite");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if ((st = hop_entry(g, prec, fmt, U, in_even, tmp_odd, nrhs, stream, 1, "lqcd_apply_A")))
+    return st;
+  DslashCall c;
+  c.g = make_kgeom(g);
+  c.out_par = 0;
+  c.prec = prec;
+  c.fmt = fmt;
+  c.nrhs = nrhs;
+  c.mode = DM_AXPY;
+  c.U = U;
+  c.in = tmp_odd;
+  c.in_stride = int64_t(3) * c.g.Vh;
+  c.out = out_even;
+  c.out_stride = c.in_stride;
+  c.diag = in_even;
+  c.diag_stride = c.in_stride;
+  c.m2s_c = mass * mass + sigma;
+  hipStream_t s = (hipStream_t)stream;
+  DslashCfg cfg;
+  if ((st = dslash_tuned(c, 0, s, &cfg))) return st;
+  return dslash_launch(c, cfg, s);
+}
+
+}  // extern "C"

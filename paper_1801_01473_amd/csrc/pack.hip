@@ -1,0 +1,277 @@
+// Conversion between the natural (lexicographic, array-of-structures) layout
+// callers hold and the parity-split structure-of-arrays layout the kernels
+// stream (Sec. 4.1 stores fields as one array per colour component for the
+// same reason: consecutive sites are consecutive in memory).  The 12-real
+// link format keeps rows 0 and 1 only; row 2 is rebuilt from them.
+#include "common.h"
+#include "su3.h"
+
+namespace lqcd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// natural complex128 [4][V][3][3] -> packed [2][4][NE][Vh] of R
+template <typename R, int NE>
+__global__ void __launch_bounds__(kBlock) k_pack_links(KGeom g, const double2* __restrict__ nat,
+                                                       cplx<R>* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t V = int64_t(2) * g.Vh;
+  if (i >= 4 * V) return;
+  const int mu = int(i / V);
+  const int lex = int(i % V);
+  int r = lex;
+  const int x = r % g.Lx;
+  r /= g.Lx;
+  const int y = r % g.Ly;
+  r /= g.Ly;
+  const int z = r % g.Lz;
+  const int t = r / g.Lz;
+  const int par = (x + y + z + t) & 1;
+  const int h = lex >> 1;
+  const double2* src = nat + i * 9;
+  cplx<R>* dst = out + (int64_t(par) * 4 + mu) * NE * g.Vh + h;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) dst[int64_t(e) * g.Vh] = mk<R>((R)src[e].x, (R)src[e].y);
+}
+
+// packed F64-18 -> natural complex128
+__global__ void __launch_bounds__(kBlock) k_unpack_links(KGeom g, const double2* __restrict__ in,
+                                                         double2* __restrict__ nat) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t V = int64_t(2) * g.Vh;
+  if (i >= 4 * V) return;
+  const int mu = int(i / V);
+  const int lex = int(i % V);
+  int r = lex;
+  const int x = r % g.Lx;
+  r /= g.Lx;
+  const int y = r % g.Ly;
+  r /= g.Ly;
+  const int z = r % g.Lz;
+  const int t = r / g.Lz;
+  const int par = (x + y + z + t) & 1;
+  const int h = lex >> 1;
+  const double2* src = in + (int64_t(par) * 4 + mu) * 9 * g.Vh + h;
+  double2* dst = nat + i * 9;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) dst[e] = src[int64_t(e) * g.Vh];
+}
+
+// packed (RS, NS) -> packed (RD, ND); one thread per (parity, mu, half index)
+template <typename RS, int NS, typename RD, int ND>
+__global__ void __launch_bounds__(kBlock) k_convert_links(int Vh, const cplx<RS>* __restrict__ in,
+                                                          cplx<RD>* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(8) * Vh) return;
+  const int64_t pm = i / Vh;  // parity*4 + mu
+  const int h = int(i % Vh);
+  Su3<double> u;
+  const cplx<RS>* src = in + pm * NS * Vh + h;
+#pragma unroll
+  for (int e = 0; e < NS; ++e) {
+    const cplx<RS> v = src[int64_t(e) * Vh];
+    u.e[e] = mk<double>((double)v.x, (double)v.y);
+  }
+  if (NS == 6) reconstruct_row2(u);
+  cplx<RD>* dst = out + pm * ND * Vh + h;
+#pragma unroll
+  for (int e = 0; e < ND; ++e) dst[int64_t(e) * Vh] = mk<RD>((RD)u.e[e].x, (RD)u.e[e].y);
+}
+
+// natural complex128 [nrhs][V][3] -> packed [nrhs][3][Vh] of R, one parity
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pack_spinor(KGeom g, int par, int nrhs,
+                                                        const double2* __restrict__ nat,
+                                                        cplx<R>* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(nrhs) * g.Vh) return;
+  const int rhs = int(i / g.Vh);
+  const int h = int(i % g.Vh);
+  const Site s = decode_site(g, h, par);
+  const int64_t lex = int64_t(2) * h + (s.x & 1);
+  const double2* src = nat + (int64_t(rhs) * 2 * g.Vh + lex) * 3;
+  cplx<R>* dst = out + int64_t(rhs) * 3 * g.Vh + h;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dst[int64_t(c) * g.Vh] = mk<R>((R)src[c].x, (R)src[c].y);
+}
+
+// packed [nrhs][3][Vh] -> natural [nrhs][V][3], other parity zero
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_unpack_spinor(KGeom g, int par, int nrhs,
+                                                          const cplx<R>* __restrict__ in,
+                                                          double2* __restrict__ nat) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t V = int64_t(2) * g.Vh;
+  if (i >= int64_t(nrhs) * V) return;
+  const int rhs = int(i / V);
+  const int lex = int(i % V);
+  int r = lex;
+  const int x = r % g.Lx;
+  r /= g.Lx;
+  const int y = r % g.Ly;
+  r /= g.Ly;
+  const int z = r % g.Lz;
+  const int t = r / g.Lz;
+  double2* dst = nat + i * 3;
+  if (((x + y + z + t) & 1) != par) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[c] = make_double2(0.0, 0.0);
+    return;
+  }
+  const cplx<R>* src = in + int64_t(rhs) * 3 * g.Vh + (lex >> 1);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cplx<R> v = src[int64_t(c) * g.Vh];
+    dst[c] = make_double2((double)v.x, (double)v.y);
+  }
+}
+
+}  // namespace
+
+int convert_links_async(const KGeom& k, const void* src, int sp, int sf, void* dst, int dp,
+                        int df, hipStream_t st) {
+  const unsigned grid = grid_for(int64_t(8) * k.Vh);
+#define LQCD_CONV(RS, NS, RD, ND)                                                      \
+  hipLaunchKernelGGL((k_convert_links<RS, NS, RD, ND>), dim3(grid), dim3(kBlock), 0, st, \
+                     k.Vh, (const cplx<RS>*)src, (cplx<RD>*)dst)
+  const int key = (sp << 3) | (sf << 2) | (dp << 1) | df;
+  switch (key) {
+    case 0b0000: LQCD_CONV(double, 9, double, 9); break;
+    case 0b0001: LQCD_CONV(double, 9, double, 6); break;
+    case 0b0010: LQCD_CONV(double, 9, float, 9); break;
+    case 0b0011: LQCD_CONV(double, 9, float, 6); break;
+    case 0b0100: LQCD_CONV(double, 6, double, 9); break;
+    case 0b0101: LQCD_CONV(double, 6, double, 6); break;
+    case 0b0110: LQCD_CONV(double, 6, float, 9); break;
+    case 0b0111: LQCD_CONV(double, 6, float, 6); break;
+    case 0b1000: LQCD_CONV(float, 9, double, 9); break;
+    case 0b1001: LQCD_CONV(float, 9, double, 6); break;
+    case 0b1010: LQCD_CONV(float, 9, float, 9); break;
+    case 0b1011: LQCD_CONV(float, 9, float, 6); break;
+    case 0b1100: LQCD_CONV(float, 6, double, 9); break;
+    case 0b1101: LQCD_CONV(float, 6, double, 6); break;
+    case 0b1110: LQCD_CONV(float, 6, float, 9); break;
+    default: LQCD_CONV(float, 6, float, 6); break;
+  }
+#undef LQCD_CONV
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+}  // namespace lqcd
+
+using namespace lqcd;
+
+extern "C" {
+
+int lqcd_pack_links(const lqcd_geom* g, const void* U_nat, int prec, int fmt, void* U_packed,
+                    void* stream) {
+  clear_error();
+  int st;
+  if ((st = check_geom(g)) || (st = check_prec_fmt(prec, fmt)) ||
+      (st = check_ptr(U_nat, "U_nat")) || (st = check_ptr(U_packed, "U_packed")))
+    return st;
+  const KGeom k = make_kgeom(g);
+  const unsigned grid = grid_for(int64_t(8) * k.Vh);
+  hipStream_t s = (hipStream_t)stream;
+  const double2* src = (const double2*)U_nat;
+  if (prec == LQCD_F64 && fmt == LQCD_LINKS18)
+    hipLaunchKernelGGL((k_pack_links<double, 9>), dim3(grid), dim3(kBlock), 0, s, k, src,
+                       (double2*)U_packed);
+  else if (prec == LQCD_F64)
+    hipLaunchKernelGGL((k_pack_links<double, 6>), dim3(grid), dim3(kBlock), 0, s, k, src,
+                       (double2*)U_packed);
+  else if (fmt == LQCD_LINKS18)
+    hipLaunchKernelGGL((k_pack_links<float, 9>), dim3(grid), dim3(kBlock), 0, s, k, src,
+                       (float2*)U_packed);
+  else
+    hipLaunchKernelGGL((k_pack_links<float, 6>), dim3(grid), dim3(kBlock), 0, s, k, src,
+                       (float2*)U_packed);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int lqcd_convert_links(const lqcd_geom* g, const void* src, int src_prec, int src_fmt, void* dst,
+                       int dst_prec, int dst_fmt, void* stream) {
+  clear_error();
+  int st;
+  if ((st = check_geom(g)) || (st = check_prec_fmt(src_prec, src_fmt)) ||
+      (st = check_prec_fmt(dst_prec, dst_fmt)) || (st = check_ptr(src, "src")) ||
+      (st = check_ptr(dst, "dst")))
+    return st;
+  if (src == dst) {
+    set_error("convert_links: src and dst must be different buffers");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  return convert_links_async(make_kgeom(g), src, src_prec, src_fmt, dst, dst_prec, dst_fmt,
+                             (hipStream_t)stream);
+}
+
+int lqcd_unpack_links(const lqcd_geom* g, const void* U_packed, void* U_nat, void* stream) {
+  clear_error();
+  int st;
+  if ((st = check_geom(g)) || (st = check_ptr(U_packed, "U_packed")) ||
+      (st = check_ptr(U_nat, "U_nat")))
+    return st;
+  const KGeom k = make_kgeom(g);
+  hipLaunchKernelGGL(k_unpack_links, dim3(grid_for(int64_t(8) * k.Vh)), dim3(kBlock), 0,
+                     (hipStream_t)stream, k, (const double2*)U_packed, (double2*)U_nat);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int lqcd_pack_spinor(const lqcd_geom* g, int parity, int prec, const void* nat, void* packed,
+                     int32_t nrhs, void* stream) {
+  clear_error();
+  int st;
+  if ((st = check_geom(g)) || (st = check_prec_fmt(prec, LQCD_LINKS18)) ||
+      (st = check_ptr(nat, "nat")) || (st = check_ptr(packed, "packed")) ||
+      (st = check_nrhs(nrhs)))
+    return st;
+  if (parity != 0 && parity != 1) {
+    set_error("parity must be 0 or 1, got %d", parity);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const unsigned grid = grid_for(int64_t(nrhs) * k.Vh);
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == LQCD_F64)
+    hipLaunchKernelGGL(k_pack_spinor<double>, dim3(grid), dim3(kBlock), 0, s, k, parity, nrhs,
+                       (const double2*)nat, (double2*)packed);
+  else
+    hipLaunchKernelGGL(k_pack_spinor<float>, dim3(grid), dim3(kBlock), 0, s, k, parity, nrhs,
+                       (const double2*)nat, (float2*)packed);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int lqcd_unpack_spinor(const lqcd_geom* g, int parity, int prec, const void* packed, void* nat,
+                       int32_t nrhs, void* stream) {
+  clear_error();
+  int st;
+  if ((st = check_geom(g)) || (st = check_prec_fmt(prec, LQCD_LINKS18)) ||
+      (st = check_ptr(nat, "nat")) || (st = check_ptr(packed, "packed")) ||
+      (st = check_nrhs(nrhs)))
+    return st;
+  if (parity != 0 && parity != 1) {
+    set_error("parity must be 0 or 1, got %d", parity);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const unsigned grid = grid_for(int64_t(nrhs) * 2 * k.Vh);
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == LQCD_F64)
+    hipLaunchKernelGGL(k_unpack_spinor<double>, dim3(grid), dim3(kBlock), 0, s, k, parity, nrhs,
+                       (const double2*)packed, (double2*)nat);
+  else
+    hipLaunchKernelGGL(k_unpack_spinor<float>, dim3(grid), dim3(kBlock), 0, s, k, parity, nrhs,
+                       (const float2*)packed, (double2*)nat);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+}  // extern "C"

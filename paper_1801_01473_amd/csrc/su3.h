@@ -1,0 +1,57 @@
+// 3x3 complex matrices held in registers, and the link loads of the packed
+// layouts.
+#pragma once
+
+#include "common.h"
+
+namespace lqcd {
+
+template <typename R>
+struct Su3 {
+  cplx<R> e[9];  // row-major: e[3*row + col]
+};
+
+template <typename R>
+__device__ __forceinline__ cplx<R> conj_of(cplx<R> a) { return mk<R>(a.x, -a.y); }
+
+// Row 2 of an SU(3) matrix is the complex conjugate of the cross product of
+// rows 0 and 1 (Sec. 4.1, gauge link compression).
+template <typename R>
+__device__ __forceinline__ void reconstruct_row2(Su3<R>& u) {
+  u.e[6] = conj_of<R>(csub<R>(cmul<R>(u.e[1], u.e[5]), cmul<R>(u.e[2], u.e[4])));
+  u.e[7] = conj_of<R>(csub<R>(cmul<R>(u.e[2], u.e[3]), cmul<R>(u.e[0], u.e[5])));
+  u.e[8] = conj_of<R>(csub<R>(cmul<R>(u.e[0], u.e[4]), cmul<R>(u.e[1], u.e[3])));
+}
+
+// Load the link with half index h from a packed [NE][Vh] block.
+template <typename R, int NE>
+__device__ __forceinline__ void load_link(const cplx<R>* __restrict__ base, int h, int Vh,
+                                          Su3<R>& u) {
+#pragma unroll
+  for (int e = 0; e < NE; ++e) u.e[e] = base[int64_t(e) * Vh + h];
+  if (NE == 6) reconstruct_row2<R>(u);
+}
+
+// y = U v
+template <typename R>
+__device__ __forceinline__ void mat_vec(const Su3<R>& u, const cplx<R> v[3], cplx<R> y[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    y[a] = cmul<R>(u.e[3 * a], v[0]);
+    cfma<R>(y[a], u.e[3 * a + 1], v[1]);
+    cfma<R>(y[a], u.e[3 * a + 2], v[2]);
+  }
+}
+
+// y = U^dag v
+template <typename R>
+__device__ __forceinline__ void adj_mat_vec(const Su3<R>& u, const cplx<R> v[3], cplx<R> y[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    y[a] = cmulc<R>(u.e[a], v[0]);
+    cfmac<R>(y[a], u.e[3 + a], v[1]);
+    cfmac<R>(y[a], u.e[6 + a], v[2]);
+  }
+}
+
+}  // namespace lqcd

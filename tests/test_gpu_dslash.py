@@ -1,0 +1,170 @@
+"""GPU parity of the packing and D_oe / D_eo kernels against the CPU oracle.
+
+Tolerances (max relative error = max |gpu - oracle| / max |oracle| over all
+sites, colours and right-hand sides): FP64 <= 1e-13, FP32 <= 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lq():
+    import paper_1801_01473_amd as lq
+    return lq
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+SHAPES = [(2, 2, 2, 2), (4, 4, 4, 4), (4, 2, 6, 4), (6, 4, 2, 8), (8, 8, 8, 8)]
+
+
+def _links(L, kind, seed):
+    if kind == "haar":
+        return synth.links_haar(L, seed)
+    if kind == "unit":
+        return synth.links_unit(L)
+    return synth.links_exp(L, 0.5, seed)
+
+
+@pytest.mark.parametrize("L", SHAPES)
+def test_pack_roundtrip(lq, L):
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 1)
+    Up = lq.pack_links(g, cu(U))
+    back = host(lq.unpack_links(g, Up))
+    assert np.array_equal(back, U)
+    f = synth.gaussian_field(L, 3, 2)
+    for par in (0, 1):
+        pk = lq.pack_spinor(g, cu(f), par)
+        un = host(lq.unpack_spinor(g, pk, par))
+        mask = synth.site_parity(L) == par
+        assert np.array_equal(un[:, mask], f[:, mask])
+        assert np.all(un[:, ~mask] == 0)
+    # FP32 rounds to nearest
+    pk32 = lq.pack_spinor(g, cu(f), 0, lq.F32)
+    un32 = host(lq.unpack_spinor(g, pk32, 0))
+    mask = synth.site_parity(L) == 0
+    assert np.array_equal(un32[:, mask], f[:, mask].astype(np.complex64).astype(np.complex128))
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (2, 4, 6, 2)])
+def test_convert_links_12_reconstructs(lq, L):
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 4)
+    U64 = lq.pack_links(g, cu(U))
+    U12 = lq.convert_links(g, U64, lq.F64, lq.LINKS18, lq.F64, lq.LINKS12)
+    back = lq.convert_links(g, U12, lq.F64, lq.LINKS12, lq.F64, lq.LINKS18)
+    assert H.max_rel(host(lq.unpack_links(g, back)), U) < 1e-14
+    direct12 = lq.pack_links(g, cu(U), lq.F64, lq.LINKS12)
+    assert torch.equal(direct12, U12)
+
+
+@pytest.mark.parametrize("L", SHAPES)
+@pytest.mark.parametrize("prec,fmt,tol", [(0, 0, 1e-13), (0, 1, 1e-13), (1, 0, 1e-6), (1, 1, 1e-6)])
+@pytest.mark.parametrize("anti", [True, False])
+def test_hop_vs_oracle(lq, L, prec, fmt, tol, anti):
+    g = lq.Geometry(L, anti)
+    U = _links(L, "haar", 10)
+    f = synth.gaussian_field(L, 1, 11)[0]
+    Up = lq.pack_links(g, cu(U), prec, fmt)
+    ev = lq.pack_spinor(g, cu(f[None]), 0, prec)
+    od = lq.pack_spinor(g, cu(f[None]), 1, prec)
+    got_o = host(lq.unpack_spinor(g, lq.doe(g, Up, ev), 1))[0]
+    got_e = host(lq.unpack_spinor(g, lq.deo(g, Up, od), 0))[0]
+    ref_o = oracle.doe(L, U, f, anti)
+    ref_e = oracle.deo(L, U, f, anti)
+    assert H.max_rel(got_o, ref_o) <= tol
+    assert H.max_rel(got_e, ref_e) <= tol
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 5, 8, 11])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_multi_rhs_equals_single_rhs(lq, nrhs, prec):
+    """Batched right-hand sides give bitwise the single-RHS result per RHS."""
+    L = (4, 6, 4, 4)
+    g = lq.Geometry(L)
+    U = _links(L, "exp", 12)
+    fmt = lq.LINKS12 if prec == 1 else lq.LINKS18
+    Up = lq.pack_links(g, cu(U), prec, fmt)
+    f = synth.gaussian_field(L, nrhs, 13)
+    ev = lq.pack_spinor(g, cu(f), 0, prec)
+    batched = lq.doe(g, Up, ev)
+    for j in range(nrhs):
+        single = lq.doe(g, Up, ev[j:j + 1].contiguous())
+        assert torch.equal(single[0], batched[j])
+    ref = np.stack([oracle.doe(L, U, f[j]) for j in range(nrhs)])
+    got = host(lq.unpack_spinor(g, batched, 1))
+    assert H.max_rel(got, ref) <= (1e-13 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec,fmt,tol", [(0, 0, 1e-13), (1, 1, 1e-6)])
+def test_apply_A_vs_oracle(lq, prec, fmt, tol):
+    L = (4, 4, 6, 8)
+    g = lq.Geometry(L)
+    U = _links(L, "haar", 14)
+    b = synth.gaussian_even_source(L, 2, 15)
+    Up = lq.pack_links(g, cu(U), prec, fmt)
+    x = lq.pack_spinor(g, cu(b), 0, prec)
+    got = host(lq.unpack_spinor(g, lq.apply_A(g, Up, 0.1, 0.25, x), 0))
+    ref = np.stack([oracle.apply_A(L, U, 0.1, 0.25, b[j]) for j in range(2)])
+    assert H.max_rel(got, ref) <= tol
+
+
+def test_free_field_plane_wave_24(lq):
+    """24^4 unit links: even-site plane waves are eigenvectors of A with
+    eigenvalue m^2 + sum sin^2 p (closed form, FP64 <= 1e-13)."""
+    L = (24, 24, 24, 24)
+    g = lq.Geometry(L)
+    m = 0.05
+    Up = lq.pack_links(g, cu(synth.links_unit(L)))
+    r = synth.rng(77)
+    for _ in range(2):
+        n = r.integers(0, 24, size=4)
+        p = 2 * np.pi * n / 24.0
+        p[3] = (2 * n[3] + 1) * np.pi / 24.0
+        c = r.standard_normal(3) + 1j * r.standard_normal(3)
+        f = H.plane_wave_even(L, p, c)
+        x = lq.pack_spinor(g, cu(f[None]), 0)
+        Ax = lq.apply_A(g, Up, m, 0.0, x)
+        lam = m * m + float(np.sum(np.sin(p) ** 2))
+        err = (Ax - lam * x).abs().max().item() / x.abs().max().item()
+        assert err < 1e-13
+
+
+def test_anti_hermiticity_gpu(lq):
+    L = (8, 8, 8, 8)
+    g = lq.Geometry(L)
+    U = _links(L, "haar", 16)
+    Up = lq.pack_links(g, cu(U))
+    f = synth.gaussian_field(L, 2, 17)
+    psi = lq.pack_spinor(g, cu(f[0:1]), 0)
+    chi = lq.pack_spinor(g, cu(f[1:2]), 1)
+    lhs = torch.vdot(chi.flatten(), lq.doe(g, Up, psi).flatten()).item()
+    rhs = -torch.vdot(lq.deo(g, Up, chi).flatten(), psi.flatten()).item()
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("prec,fmt,tol", [(0, 0, 1e-13), (1, 1, 1e-6)])
+def test_hop_24_vs_oracle(lq, prec, fmt, tol):
+    L = (24, 24, 24, 24)
+    g = lq.Geometry(L)
+    U = _links(L, "haar", 102)
+    f = synth.gaussian_even_source(L, 1, 202)[0]
+    Up = lq.pack_links(g, cu(U), prec, fmt)
+    ev = lq.pack_spinor(g, cu(f[None]), 0, prec)
+    got = host(lq.unpack_spinor(g, lq.doe(g, Up, ev), 1))[0]
+    assert H.max_rel(got, oracle.doe(L, U, f)) <= tol
