@@ -163,6 +163,7 @@ typedef struct {
     int32_t rhs_block;         /* right-hand sides per D_oe/D_eo link load, 0 = tuned */
     int32_t poll_interval;     /* iterations between host convergence checks, 0 = auto */
     int32_t max_refine;        /* rounds of per-shift refinement allowed, >= 0       */
+    double reliable_delta;     /* mixed: also update when |r| fell by this factor    */
 } lqcd_solver_params;
 
 typedef struct {
@@ -175,7 +176,8 @@ typedef struct {
 } lqcd_solve_stats;
 
 /* Fills p with defaults: tol 1e-10, max_iter 10000, F64 inner, LINKS18,
- * reliable_interval 100, use_graph 1, rhs_block 0, poll 0, max_refine 3. */
+ * reliable_interval 100, use_graph 1, rhs_block 0, poll 0, max_refine 3,
+ * reliable_delta 1e-3. */
 void lqcd_solver_params_default(lqcd_solver_params *p);
 
 /* Device workspace that lqcd_cg / lqcd_cg_multishift need for these sizes. */
@@ -191,10 +193,12 @@ size_t lqcd_solver_workspace_bytes(const lqcd_geom *g, const lqcd_solver_params 
  *   b            packed even FP64 [nrhs][3][Vh]
  *   x            packed even FP64 [nrhs][3][Vh]; on entry the initial guess
  *   stats        host array [nrhs]
- * Mixed precision (inner_prec = LQCD_F32): the Krylov iteration runs in FP32
- * and every reliable_interval iterations the FP32 correction is added into
- * the FP64 solution and the residual is recomputed in FP64 (Sec. 6: the
- * production split, single precision for MD and double for the accept step).
+ * Mixed precision (inner_prec = LQCD_F32): the Krylov iteration runs in FP32;
+ * whenever the iterated residual has fallen by reliable_delta since the last
+ * update, or reliable_interval iterations have passed, or the iteration
+ * believes it has converged, the FP32 correction is added into the FP64
+ * solution and the residual is recomputed in FP64 (Sec. 6: the production
+ * split, single precision for MD and double for the accept step).
  * Dot products, norms and the CG scalars are always FP64.
  * Returns LQCD_ERR_NOT_CONVERGED if any system misses tol within max_iter
  * (x holds the best iterate, stats are filled).
@@ -253,6 +257,16 @@ size_t lqcd_action_workspace_bytes(const lqcd_geom *g);
 int lqcd_action(const lqcd_geom *g, int32_t npf, int32_t nshift, double alpha0,
                 const double *alpha, const void *phi, const void *X, double *S,
                 void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Achievable HBM bandwidth of the current device: STREAM-style copy
+ * (read + write) and triad (2 reads + write) over `bytes` per array, median
+ * of `reps` timed launches, in GB/s (1e9 B/s).  The roofline of the
+ * bandwidth-bound kernels above (the Dirac operator is ~6x below machine
+ * balance, Sec. 4.1) is read against this figure and the 8 TB/s specification.
+ * Allocates three temporary arrays and synchronises the device.
+ */
+int lqcd_stream_bandwidth(size_t bytes, int32_t reps, double *copy_gbs, double *triad_gbs);
 
 #ifdef __cplusplus
 }

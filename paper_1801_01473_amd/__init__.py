@@ -57,7 +57,7 @@ class SolverParams(ctypes.Structure):
         ("inner_prec", ctypes.c_int32), ("inner_fmt", ctypes.c_int32),
         ("reliable_interval", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("rhs_block", ctypes.c_int32), ("poll_interval", ctypes.c_int32),
-        ("max_refine", ctypes.c_int32),
+        ("max_refine", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
     ]
 
 
@@ -107,6 +107,7 @@ _SIGS = {
     "lqcd_action_workspace_bytes": (ctypes.c_size_t, [_gp]),
     "lqcd_action": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp,
                                    ctypes.c_size_t, _vp]),
+    "lqcd_stream_bandwidth": (ctypes.c_int, [ctypes.c_size_t, _i32, _dp, _dp]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -375,6 +376,14 @@ def action(geom: Geometry, alpha0, alpha, phi, X) -> float:
     _check(_fn("lqcd_action")(geom.c(), npf, nshift, float(alpha0), al, _ptr(phi), _ptr(X),
                               ctypes.byref(S), _ptr(ws), ws.numel(), _stream()))
     return float(S.value)
+
+
+def stream_bandwidth(nbytes: int = 1 << 30, reps: int = 20):
+    """(copy GB/s, triad GB/s) of the current device."""
+    c = ctypes.c_double(0.0)
+    t = ctypes.c_double(0.0)
+    _check(_fn("lqcd_stream_bandwidth")(int(nbytes), int(reps), ctypes.byref(c), ctypes.byref(t)))
+    return float(c.value), float(t.value)
 
 
 class FermionAction(torch.autograd.Function):

@@ -1,0 +1,52 @@
+// Device-side state of the CG / multi-shift CG solver.
+#pragma once
+
+#include "common.h"
+
+namespace lqcd {
+
+constexpr int kMaxShift = 32;
+constexpr int kScalarThreads = 1024;  // one workgroup runs every scalar recurrence
+
+// Scalars of one system (one right-hand side of the main solve, or one
+// refined (right-hand side, shift) pair).  All FP64.
+struct alignas(16) SysState {
+  double rho;      // |r|^2 of the current (iterated or recomputed) residual
+  double pp;       // |p|^2 of the base search direction
+  double a;        // CG step of the base system
+  double a_old, b_old;
+  double bnorm2;   // |b|^2
+  double target2;  // (tol |b|)^2
+  double m2s;      // base diagonal m^2 + sigma_0
+  double r2ref;    // |r|^2 at the last reliable update (or start)
+  double rho_iter; // iterated |r|^2 just before the last reliable update
+  int iters;       // Krylov iterations done
+  int done;        // stopped (converged or out of iterations)
+  int live;        // = !done, read by the D_oe kernel
+  int upd_any;     // this iteration's update is to be applied
+  int rel;         // takes part in the current reliable update
+  int nrel;        // reliable updates done
+  int conv;        // converged on the FP64 recomputed residual
+  int err;         // non-finite or non-positive curvature seen
+  int restart;     // directions are rebuilt from the recomputed residual
+  int pad_;
+  double zeta[kMaxShift], zeta_old[kMaxShift], zeta_new[kMaxShift];
+  double a_s[kMaxShift], b_s[kMaxShift], delta[kMaxShift];
+  int active[kMaxShift];  // shift still iterating
+  int upd[kMaxShift];     // shift updated in this iteration
+  int dirty[kMaxShift];   // low-precision solution changed since the last reliable update
+};
+
+static_assert(sizeof(SysState) % 8 == 0, "state stride must be a whole number of doubles");
+
+struct alignas(16) GlobalFlags {
+  int all_done;
+  int error;
+  int rel_req;  // some system's residual fell by the reliable-update factor
+  int pad;
+};
+
+constexpr int kStateStrideD = int(sizeof(SysState) / sizeof(double));
+constexpr int kStateStrideI = int(sizeof(SysState) / sizeof(int));
+
+}  // namespace lqcd

@@ -1,0 +1,1220 @@
+// CG and multi-shift CG for the shifted systems of Eq. (2),
+//     ((m^2 + sigma_i) - D_eo D_oe) x_i = b,
+// whose building blocks are scalar products, vector sums and D_oe / D_eo
+// (Sec. 2).  Everything runs on the GPU; the host only launches and, every
+// few iterations, reads one small flag word.
+//
+// One iteration per system of the base shift sigma_0 (smallest sigma):
+//   K1  t = D_oe p                     + FP64 partials of |t|^2
+//   K2  (one workgroup) a = rho / (m2s |p|^2 + |t|^2) -- equal to <p, A p>
+//       because -D_eo = D_oe^dag -- and the shifted zeta_s, a_s
+//   K3  r -= a (m2s p - D_eo t)        + FP64 partials of |r|^2   (fused)
+//   K4  (one workgroup) beta, beta_s, zeta history, per-shift freezing,
+//       convergence and iteration limits
+//   K5  for every active shift: x_s += a_s p_s ; p_s = zeta_s r + beta_s p_s
+//                                      + FP64 partials of |p_0|^2
+// All reductions are two-stage and in fixed order, so results do not depend
+// on scheduling.  Kernels skip systems (and whole launches) that are done,
+// so a block of iterations can be replayed as one captured hipGraph.
+//
+// Mixed precision: the iteration above runs in FP32 (links FP32 18- or
+// 12-real) and accumulates each shift's solution in an FP32 partial sum;
+// every reliable_interval iterations (and at convergence) those sums are
+// added into the FP64 solutions and the base residual is recomputed in FP64
+// with FP64 links (Sec. 6: floating point for the molecular dynamics, double
+// precision for the accept/reject step).  After the base system converges the
+// FP64 true residual of every (right-hand side, shift) is computed, and the
+// ones above tol are refined together as independent systems by CG started
+// from their current solutions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dslash.h"
+#include "solver.h"
+
+namespace lqcd {
+
+int convert_links_async(const KGeom& k, const void* src, int sp, int sf, void* dst, int dp,
+                        int df, hipStream_t st);
+
+namespace {
+
+constexpr int kVecBlock = 256;
+
+// --------------------------------------------------------------- kernels
+
+// Deterministic sum of p[0..n) by the whole workgroup, broadcast to all threads.
+__device__ double wg_sum(const double* __restrict__ p, int n, double* lds) {
+  __shared__ double bc;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += p[i];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) bc = s;
+  __syncthreads();
+  s = bc;
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return v == v && fabs(v) <= 1.7e308; }
+
+template <typename T>
+__global__ void __launch_bounds__(kVecBlock) k_zero(T* __restrict__ p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = T{};
+}
+
+// partials[v][blk] = sum |v|^2 over the block's sites (FP64 vectors [nvec][3][Vh])
+__global__ void __launch_bounds__(kVecBlock) k_norm2_f64(const double2* __restrict__ v,
+                                                         int64_t stride, int Vh,
+                                                         double* __restrict__ part) {
+  __shared__ double lds[kVecBlock / 64];
+  const int j = blockIdx.y;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (h < Vh) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double2 z = v[int64_t(j) * stride + int64_t(c) * Vh + h];
+      s += z.x * z.x + z.y * z.y;
+    }
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = s;
+}
+
+// r = (RI) b, partials of |r|^2
+template <typename RI>
+__global__ void __launch_bounds__(kVecBlock) k_copy_to_inner(const double2* __restrict__ b,
+                                                             cplx<RI>* __restrict__ r, int Vh,
+                                                             double* __restrict__ part) {
+  __shared__ double lds[kVecBlock / 64];
+  const int j = blockIdx.y;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (h < Vh) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = (int64_t(j) * 3 + c) * Vh + h;
+      const cplx<RI> z = mk<RI>(RI(b[i].x), RI(b[i].y));
+      r[i] = z;
+      s += cnorm2<RI>(z);
+    }
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = s;
+}
+
+// p_s = r for every shift, optionally x_s = 0; partials of |r|^2 (= |p|^2)
+template <typename RI, typename RX>
+__global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restrict__ r,
+                                                         cplx<RI>* __restrict__ p,
+                                                         cplx<RX>* __restrict__ x, int nshift,
+                                                         int zero_x, int Vh,
+                                                         double* __restrict__ part) {
+  __shared__ double lds[kVecBlock / 64];
+  const int j = blockIdx.y;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (h < Vh) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cplx<RI> z = r[(int64_t(j) * 3 + c) * Vh + h];
+      s += cnorm2<RI>(z);
+      for (int k = 0; k < nshift; ++k) {
+        const int64_t i = ((int64_t(j) * nshift + k) * 3 + c) * Vh + h;
+        p[i] = z;
+        if (zero_x) x[i] = mk<RX>(0, 0);
+      }
+    }
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = s;
+}
+
+// params = [m2s per system][delta per (system, shift)]
+__global__ void __launch_bounds__(kScalarThreads) k_sc_init(
+    SysState* __restrict__ st, GlobalFlags* __restrict__ gf, int nsys, int nshift,
+    const double* __restrict__ params, double tol2, const double* part_b, int nb_b,
+    const double* part_r, int nb_r, const double* part_p, int nb_p) {
+  __shared__ double lds[kScalarThreads / 64];
+  int all_done = 1, err = 0;
+  for (int j = 0; j < nsys; ++j) {
+    const double bn = wg_sum(part_b + int64_t(j) * nb_b, nb_b, lds);
+    const double rr = wg_sum(part_r + int64_t(j) * nb_r, nb_r, lds);
+    const double pp = wg_sum(part_p + int64_t(j) * nb_p, nb_p, lds);
+    if (threadIdx.x == 0) {
+      SysState& S = st[j];
+      S.bnorm2 = bn;
+      S.target2 = tol2 * bn;
+      S.rho = rr;
+      S.pp = pp;
+      S.m2s = params[j];
+      S.a = 0.0;
+      S.a_old = 1.0;
+      S.b_old = 0.0;
+      S.iters = 0;
+      S.nrel = 0;
+      S.rel = 0;
+      S.upd_any = 0;
+      S.r2ref = rr;
+      S.rho_iter = rr;
+      S.restart = 0;
+      S.err = finite_d(rr) && finite_d(bn) ? 0 : 1;
+      for (int s = 0; s < kMaxShift; ++s) {
+        S.zeta[s] = S.zeta_old[s] = S.zeta_new[s] = 1.0;
+        S.a_s[s] = S.b_s[s] = 0.0;
+        S.delta[s] = s < nshift ? params[nsys + j * nshift + s] : 0.0;
+        S.active[s] = s < nshift ? 1 : 0;
+        S.upd[s] = 0;
+        S.dirty[s] = 0;
+      }
+      S.conv = rr <= S.target2 ? 1 : 0;
+      S.done = (S.conv || S.err) ? 1 : 0;
+      S.live = !S.done;
+      all_done &= S.done;
+      err |= S.err;
+    }
+  }
+  if (threadIdx.x == 0) {
+    gf->all_done = all_done;
+    gf->error = err;
+    gf->rel_req = 0;
+  }
+}
+
+// K2: step length of the base system and the shifted zetas
+__global__ void __launch_bounds__(kScalarThreads) k_sc_alpha(SysState* __restrict__ st,
+                                                              GlobalFlags* __restrict__ gf,
+                                                              int nsys, int nshift,
+                                                              const double* part_t, int nb_t,
+                                                              const double* part_p, int nb_p) {
+  __shared__ double lds[kScalarThreads / 64];
+  for (int j = 0; j < nsys; ++j) {
+    const double tt = wg_sum(part_t + int64_t(j) * nb_t, nb_t, lds);
+    const double pp = wg_sum(part_p + int64_t(j) * nb_p, nb_p, lds);
+    if (threadIdx.x != 0) continue;
+    SysState& S = st[j];
+    S.upd_any = 0;
+    S.restart = 0;
+    for (int s = 0; s < nshift; ++s) S.upd[s] = 0;
+    if (S.done) continue;
+    const double pAp = S.m2s * pp + tt;  // <p, (m2s - D_eo D_oe) p>
+    S.pp = pp;
+    if (!(pAp > 0.0) || !finite_d(pAp)) {
+      S.err = 1;
+      S.done = 1;
+      S.live = 0;
+      gf->error = 1;
+      continue;
+    }
+    const double a = S.rho / pAp;
+    S.a = a;
+    for (int s = 0; s < nshift; ++s) {
+      if (!S.active[s]) continue;
+      const double z = S.zeta[s], zo = S.zeta_old[s];
+      const double zn =
+          z * zo * S.a_old / (a * S.b_old * (zo - z) + zo * S.a_old * (1.0 + S.delta[s] * a));
+      S.zeta_new[s] = zn;
+      S.a_s[s] = a * zn / z;
+      S.upd[s] = 1;
+    }
+    S.upd_any = 1;
+  }
+}
+
+// K4: beta, shifted betas, freezing, convergence
+__global__ void __launch_bounds__(kScalarThreads) k_sc_beta(SysState* __restrict__ st,
+                                                             GlobalFlags* __restrict__ gf,
+                                                             int nsys, int nshift,
+                                                             const double* part_r, int nb_r,
+                                                             int max_iter, double rel_delta2) {
+  __shared__ double lds[kScalarThreads / 64];
+  int all_done = 1, rel_req = 0;
+  for (int j = 0; j < nsys; ++j) {
+    const double rr = wg_sum(part_r + int64_t(j) * nb_r, nb_r, lds);
+    if (threadIdx.x != 0) continue;
+    SysState& S = st[j];
+    if (S.upd_any) {
+      if (!finite_d(rr)) {
+        S.err = 1;
+        S.done = 1;
+        S.live = 0;
+        S.upd_any = 0;
+        gf->error = 1;
+      } else {
+        const double beta = rr / S.rho;
+        for (int s = 0; s < nshift; ++s) {
+          if (!S.upd[s]) continue;
+          const double ratio = S.zeta_new[s] / S.zeta[s];
+          S.b_s[s] = beta * ratio * ratio;
+          S.zeta_old[s] = S.zeta[s];
+          S.zeta[s] = S.zeta_new[s];
+          S.dirty[s] = 1;
+          if (S.zeta_new[s] * S.zeta_new[s] * rr <= S.target2) S.active[s] = 0;
+        }
+        S.a_old = S.a;
+        S.b_old = beta;
+        S.rho = rr;
+        S.iters += 1;
+        if (rr < rel_delta2 * S.r2ref) rel_req = 1;
+        if (rr <= S.target2 || S.iters >= max_iter) {
+          S.done = 1;
+          S.live = 0;
+          S.conv = rr <= S.target2 ? 1 : 0;
+        }
+      }
+    }
+    all_done &= S.done;
+  }
+  if (threadIdx.x == 0) {
+    gf->all_done = all_done;
+    if (rel_req) gf->rel_req = 1;
+  }
+}
+
+// K5: x_s += a_s p_s ; p_s = zeta_s r + beta_s p_s for the shifts updated this iteration
+template <typename RI, typename RX>
+__global__ void __launch_bounds__(kVecBlock) k_ms_update(const SysState* __restrict__ st,
+                                                         const cplx<RI>* __restrict__ r,
+                                                         cplx<RI>* __restrict__ p,
+                                                         cplx<RX>* __restrict__ x, int nshift,
+                                                         int base, int Vh,
+                                                         double* __restrict__ part) {
+  __shared__ double lds[kVecBlock / 64];
+  const int j = blockIdx.y;
+  const SysState& S = st[j];
+  if (!S.upd_any) return;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  double pn = 0.0;
+  if (h < Vh) {
+    cplx<RI> rv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rv[c] = r[(int64_t(j) * 3 + c) * Vh + h];
+    for (int s = 0; s < nshift; ++s) {
+      if (!S.upd[s]) continue;
+      const RI as = RI(S.a_s[s]), zs = RI(S.zeta[s]), bs = RI(S.b_s[s]);
+      const int64_t o = (int64_t(j) * nshift + s) * 3 * Vh + h;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cplx<RI> pv = p[o + int64_t(c) * Vh];
+        cplx<RX> xv = x[o + int64_t(c) * Vh];
+        xv.x = fma(RX(as), RX(pv.x), xv.x);
+        xv.y = fma(RX(as), RX(pv.y), xv.y);
+        pv.x = fma(zs, rv[c].x, bs * pv.x);
+        pv.y = fma(zs, rv[c].y, bs * pv.y);
+        x[o + int64_t(c) * Vh] = xv;
+        p[o + int64_t(c) * Vh] = pv;
+        if (s == base) pn += cnorm2<RI>(pv);
+      }
+    }
+  }
+  pn = block_sum(pn, lds);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = pn;
+}
+
+__global__ void k_sc_rel_begin(SysState* __restrict__ st, GlobalFlags* __restrict__ gf, int nsys,
+                               int nshift) {
+  if (threadIdx.x != 0) return;
+  gf->rel_req = 0;
+  for (int j = 0; j < nsys; ++j) {
+    int any = 0;
+    for (int s = 0; s < nshift; ++s) any |= st[j].dirty[s];
+    st[j].rel = any;
+  }
+}
+
+// x_hi += x_lo ; x_lo = 0 for every shift changed since the last reliable update
+__global__ void __launch_bounds__(kVecBlock) k_accum(const SysState* __restrict__ st,
+                                                     float2* __restrict__ xlo,
+                                                     double2* __restrict__ xhi, int nshift,
+                                                     int Vh) {
+  const int k = blockIdx.y;
+  const int j = k / nshift, s = k % nshift;
+  if (!st[j].rel || !st[j].dirty[s]) return;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= Vh) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t i = (int64_t(k) * 3 + c) * Vh + h;
+    const float2 lo = xlo[i];
+    double2 hi = xhi[i];
+    hi.x += double(lo.x);
+    hi.y += double(lo.y);
+    xhi[i] = hi;
+    xlo[i] = make_float2(0.f, 0.f);
+  }
+}
+
+__global__ void __launch_bounds__(kScalarThreads) k_sc_reliable(SysState* __restrict__ st,
+                                                                 GlobalFlags* __restrict__ gf,
+                                                                 int nsys, int nshift, int base,
+                                                                 const double* part, int nb,
+                                                                 int max_iter) {
+  __shared__ double lds[kScalarThreads / 64];
+  int all_done = 1;
+  for (int j = 0; j < nsys; ++j) {
+    const double rr = wg_sum(part + int64_t(j) * nb, nb, lds);
+    if (threadIdx.x != 0) continue;
+    SysState& S = st[j];
+    if (S.rel) {
+      S.rel = 0;
+      S.nrel += 1;
+      for (int s = 0; s < nshift; ++s) S.dirty[s] = 0;
+      if (!finite_d(rr)) {
+        S.err = 1;
+        S.done = 1;
+        S.live = 0;
+        gf->error = 1;
+      } else {
+        S.rho_iter = S.rho;
+        S.rho = rr;
+        S.r2ref = rr;
+        // The FP32 recurrence drifted far from the FP64 residual: the old
+        // directions no longer fit it, so restart the (shifted) directions
+        // from the recomputed residual, r_s = zeta_s r.
+        if (rr > 4.0 * S.rho_iter && rr > S.target2) {
+          S.restart = 1;
+          S.a_old = 1.0;
+          S.b_old = 0.0;
+          for (int s = 0; s < nshift; ++s) S.zeta_old[s] = S.zeta[s];
+        }
+        if (rr <= S.target2) {
+          S.conv = 1;
+          S.done = 1;
+          S.live = 0;
+        } else {
+          S.conv = 0;
+          if (S.iters < max_iter) {
+            S.done = 0;
+            S.live = 1;
+            S.active[base] = 1;
+          }
+        }
+      }
+    }
+    all_done &= S.done;
+  }
+  if (threadIdx.x == 0) gf->all_done = all_done;
+}
+
+// p_s = zeta_s r for the shifts of restarted systems, partials of |p_base|^2
+template <typename RI>
+__global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __restrict__ st,
+                                                            const cplx<RI>* __restrict__ r,
+                                                            cplx<RI>* __restrict__ p, int nshift,
+                                                            int base, int Vh,
+                                                            double* __restrict__ part) {
+  __shared__ double lds[kVecBlock / 64];
+  const int j = blockIdx.y;
+  const SysState& S = st[j];
+  if (!S.restart) return;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  double pn = 0.0;
+  if (h < Vh) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cplx<RI> rv = r[(int64_t(j) * 3 + c) * Vh + h];
+      for (int s = 0; s < nshift; ++s) {
+        if (!S.active[s] && s != base) continue;
+        const RI z = RI(S.zeta[s]);
+        const cplx<RI> pv = mk<RI>(z * rv.x, z * rv.y);
+        p[((int64_t(j) * nshift + s) * 3 + c) * Vh + h] = pv;
+        if (s == base) pn += cnorm2<RI>(pv);
+      }
+    }
+  }
+  pn = block_sum(pn, lds);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = pn;
+}
+
+// out[v] = sum_b part[v][b], fixed order, one workgroup per vector
+__global__ void __launch_bounds__(kVecBlock) k_reduce_vec(const double* __restrict__ part, int nb,
+                                                          double* __restrict__ out) {
+  __shared__ double lds[kVecBlock / 64];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[int64_t(v) * nb + i];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) out[v] = s;
+}
+
+// --------------------------------------------------------------- host side
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t r, t, p, xlo, thi, bb, xb, st, gf, params, pt, pr, pp, pb, pres, resn, links, total;
+  bool has_xlo, has_links;
+};
+
+Layout make_layout(const KGeom& g, int iprec, int ifmt, int nshift, int nrhs) {
+  Layout L{};
+  const size_t ri = iprec == LQCD_F32 ? 4 : 8;
+  const size_t vin = size_t(3) * g.Vh * 2 * ri;
+  const size_t v64 = size_t(3) * g.Vh * 16;
+  const size_t nparts = size_t(nrhs) * ((g.Vh + 63) / 64);
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    const size_t o = off;
+    off = align_up(off + n);
+    return o;
+  };
+  L.r = take(nrhs * vin);
+  L.t = take(nrhs * vin);
+  L.p = take(size_t(nrhs) * nshift * vin);
+  L.has_xlo = iprec == LQCD_F32;
+  L.xlo = L.has_xlo ? take(size_t(nrhs) * nshift * vin) : 0;
+  L.thi = take(nrhs * v64);
+  L.bb = take(nrhs * v64);
+  L.xb = take(nrhs * v64);
+  L.st = take(size_t(nrhs) * sizeof(SysState));
+  L.gf = take(sizeof(GlobalFlags));
+  L.params = take(size_t(nrhs) * (1 + nshift) * sizeof(double));
+  L.pt = take(nparts * 8);
+  L.pr = take(nparts * 8);
+  L.pp = take(nparts * 8);
+  L.pb = take(nparts * 8);
+  L.pres = take(nparts * 8);
+  L.resn = take(size_t(nrhs) * nshift * 8);
+  L.has_links = !(iprec == LQCD_F64 && ifmt == LQCD_LINKS18);
+  L.links = L.has_links ? take(size_t(8) * link_elems(ifmt) * g.Vh * 2 * ri) : 0;
+  L.total = off;
+  return L;
+}
+
+// Process-wide resources: pinned host staging, capture stream, graph cache.
+// Pinned staging: [0, kPinnedParams) receives the flag word, parameters follow.
+constexpr size_t kPinnedParams = 256;
+
+struct Global {
+  std::mutex mu;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipStream_t cap = nullptr;
+  std::map<std::string, hipGraphExec_t> graphs;
+};
+Global& G() {
+  static Global g;
+  return g;
+}
+
+int pinned(size_t n, void** out) {
+  Global& gl = G();
+  if (gl.pinned_bytes < n) {
+    if (gl.pinned) (void)hipHostFree(gl.pinned);
+    gl.pinned = nullptr;
+    gl.pinned_bytes = 0;
+    LQCD_HIP_TRY(hipHostMalloc(&gl.pinned, n, hipHostMallocDefault));
+    gl.pinned_bytes = n;
+  }
+  *out = gl.pinned;
+  return LQCD_OK;
+}
+
+void clear_graphs() {
+  for (auto& kv : G().graphs) (void)hipGraphExecDestroy(kv.second);
+  G().graphs.clear();
+}
+
+struct Ctx {
+  KGeom g;
+  lqcd_solver_params p;
+  int iprec, ifmt;
+  const void* U64;
+  const void* Uin;
+  char* ws;
+  Layout L;
+  hipStream_t s;
+  int nrhs_max;
+  double m2;
+  double rel_delta;  // reliable update when |r| fell by this factor
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+};
+
+// One run of the Krylov iteration on nsys independent systems.
+struct Core {
+  int nsys, nshift, base;
+  bool guess;
+  const double2* b;  // [nsys][3][Vh] FP64
+  double2* x;        // [nsys][nshift][3][Vh] FP64
+  double tol;
+  DslashCfg c_oe, c_eo, c64_oe, c64_eo;
+  int nb_oe, nb_eo, nb64_eo, nbv;
+  int poll;
+};
+
+bool is_mixed(const Ctx& c) { return c.iprec == LQCD_F32; }
+
+int64_t vstride(const Ctx& c) { return int64_t(3) * c.g.Vh; }
+
+DslashCall inner_call(const Ctx& c, const Core& k, int out_par) {
+  DslashCall d;
+  d.g = c.g;
+  d.out_par = out_par;
+  d.prec = c.iprec;
+  d.fmt = c.ifmt;
+  d.nrhs = k.nsys;
+  d.U = c.Uin;
+  return d;
+}
+
+DslashCall fp64_call(const Ctx& c, const Core& k, int out_par) {
+  DslashCall d;
+  d.g = c.g;
+  d.out_par = out_par;
+  d.prec = LQCD_F64;
+  d.fmt = LQCD_LINKS18;
+  d.nrhs = k.nsys;
+  d.U = c.U64;
+  return d;
+}
+
+size_t inner_real(const Ctx& c) { return c.iprec == LQCD_F32 ? 8 : 16; }  // bytes per complex
+
+char* inner_vec(const Ctx& c, size_t off, int64_t index) {
+  return c.ws + off + size_t(index) * vstride(c) * inner_real(c);
+}
+
+int launch_iteration(const Ctx& c, const Core& k, hipStream_t s) {
+  SysState* st = c.at<SysState>(c.L.st);
+  GlobalFlags* gf = c.at<GlobalFlags>(c.L.gf);
+  const int64_t vs = vstride(c);
+  int rc;
+  // K1: t = D_oe p_base
+  DslashCall d1 = inner_call(c, k, 1);
+  d1.mode = DM_PLAIN;
+  d1.in = inner_vec(c, c.L.p, k.base);
+  d1.in_stride = int64_t(k.nshift) * vs;
+  d1.out = c.ws + c.L.t;
+  d1.out_stride = vs;
+  d1.live = &st->live;
+  d1.live_stride = kStateStrideI;
+  d1.halt = &gf->all_done;
+  d1.partials = c.at<double>(c.L.pt);
+  if ((rc = dslash_launch(d1, k.c_oe, s))) return rc;
+  // K2
+  hipLaunchKernelGGL(k_sc_alpha, dim3(1), dim3(kScalarThreads), 0, s, st, gf, k.nsys, k.nshift,
+                     c.at<double>(c.L.pt), k.nb_oe, c.at<double>(c.L.pp), k.nbv);
+  LQCD_LAUNCH_CHECK();
+  // K3: r -= a (m2s p - D_eo t)
+  DslashCall d3 = inner_call(c, k, 0);
+  d3.mode = DM_CG;
+  d3.in = c.ws + c.L.t;
+  d3.in_stride = vs;
+  d3.diag = inner_vec(c, c.L.p, k.base);
+  d3.diag_stride = int64_t(k.nshift) * vs;
+  d3.r = c.ws + c.L.r;
+  d3.r_stride = vs;
+  d3.m2s = &st->m2s;
+  d3.m2s_stride = kStateStrideD;
+  d3.alpha = &st->a;
+  d3.alpha_stride = kStateStrideD;
+  d3.live = &st->upd_any;
+  d3.live_stride = kStateStrideI;
+  d3.halt = &gf->all_done;
+  d3.partials = c.at<double>(c.L.pr);
+  if ((rc = dslash_launch(d3, k.c_eo, s))) return rc;
+  // K4
+  const double d2 = is_mixed(c) ? c.rel_delta * c.rel_delta : 0.0;
+  hipLaunchKernelGGL(k_sc_beta, dim3(1), dim3(kScalarThreads), 0, s, st, gf, k.nsys, k.nshift,
+                     c.at<double>(c.L.pr), k.nb_eo, c.p.max_iter, d2);
+  LQCD_LAUNCH_CHECK();
+  // K5
+  const dim3 grid(k.nbv, k.nsys);
+  if (is_mixed(c))
+    hipLaunchKernelGGL((k_ms_update<float, float>), grid, dim3(kVecBlock), 0, s, st,
+                       c.at<const float2>(c.L.r), c.at<float2>(c.L.p), c.at<float2>(c.L.xlo),
+                       k.nshift, k.base, c.g.Vh, c.at<double>(c.L.pp));
+  else
+    hipLaunchKernelGGL((k_ms_update<double, double>), grid, dim3(kVecBlock), 0, s, st,
+                       c.at<const double2>(c.L.r), c.at<double2>(c.L.p), k.x, k.nshift, k.base,
+                       c.g.Vh, c.at<double>(c.L.pp));
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+// r = b - A_{sigma_0} x_base in FP64 (stored in inner precision), partials into part
+int launch_residual(const Ctx& c, const Core& k, const double* m2s, int m2s_stride,
+                    const int* live, double* part, hipStream_t s) {
+  const int64_t vs = vstride(c);
+  int rc;
+  DslashCall e1 = fp64_call(c, k, 1);
+  e1.mode = DM_PLAIN;
+  e1.in = k.x + int64_t(k.base) * vs;
+  e1.in_stride = int64_t(k.nshift) * vs;
+  e1.out = c.ws + c.L.thi;
+  e1.out_stride = vs;
+  e1.live = live;
+  e1.live_stride = kStateStrideI;
+  if ((rc = dslash_launch(e1, k.c64_oe, s))) return rc;
+  DslashCall e2 = fp64_call(c, k, 0);
+  e2.mode = DM_RES;
+  e2.r_prec = c.iprec;
+  e2.in = c.ws + c.L.thi;
+  e2.in_stride = vs;
+  e2.diag = k.x + int64_t(k.base) * vs;
+  e2.diag_stride = int64_t(k.nshift) * vs;
+  e2.b = k.b;
+  e2.b_stride = vs;
+  e2.r = c.ws + c.L.r;
+  e2.r_stride = vs;
+  e2.m2s = m2s;
+  e2.m2s_stride = m2s_stride;
+  e2.live = live;
+  e2.live_stride = kStateStrideI;
+  e2.partials = part;
+  return dslash_launch(e2, k.c64_eo, s);
+}
+
+int launch_reliable(const Ctx& c, const Core& k, hipStream_t s) {
+  SysState* st = c.at<SysState>(c.L.st);
+  GlobalFlags* gf = c.at<GlobalFlags>(c.L.gf);
+  hipLaunchKernelGGL(k_sc_rel_begin, dim3(1), dim3(64), 0, s, st, gf, k.nsys, k.nshift);
+  LQCD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_accum, dim3(k.nbv, k.nsys * k.nshift), dim3(kVecBlock), 0, s, st,
+                     c.at<float2>(c.L.xlo), k.x, k.nshift, c.g.Vh);
+  LQCD_LAUNCH_CHECK();
+  int rc = launch_residual(c, k, &st->m2s, kStateStrideD, &st->rel, c.at<double>(c.L.pres), s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_sc_reliable, dim3(1), dim3(kScalarThreads), 0, s, st, gf, k.nsys,
+                     k.nshift, k.base, c.at<double>(c.L.pres), k.nb64_eo, c.p.max_iter);
+  LQCD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_restart_dirs<float>, dim3(k.nbv, k.nsys), dim3(kVecBlock), 0, s, st,
+                     c.at<const float2>(c.L.r), c.at<float2>(c.L.p), k.nshift, k.base, c.g.Vh,
+                     c.at<double>(c.L.pp));
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+std::string graph_key(const Ctx& c, const Core& k) {
+  std::string key;
+  auto add = [&](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
+  add(&c.g, sizeof(c.g));
+  add(&c.iprec, sizeof(int));
+  add(&c.ifmt, sizeof(int));
+  add(&c.Uin, sizeof(void*));
+  add(&c.ws, sizeof(void*));
+  add(&c.L.total, sizeof(size_t));
+  add(&c.p.max_iter, sizeof(int));
+  add(&k.nsys, sizeof(int));
+  add(&k.nshift, sizeof(int));
+  add(&k.base, sizeof(int));
+  add(&k.x, sizeof(void*));
+  add(&k.c_oe, sizeof(DslashCfg));
+  add(&k.c_eo, sizeof(DslashCfg));
+  add(&k.poll, sizeof(int));
+  return key;
+}
+
+int iteration_graph(const Ctx& c, const Core& k, hipGraphExec_t* out) {
+  Global& gl = G();
+  const std::string key = graph_key(c, k);
+  auto it = gl.graphs.find(key);
+  if (it != gl.graphs.end()) {
+    *out = it->second;
+    return LQCD_OK;
+  }
+  if (gl.graphs.size() >= 32) clear_graphs();
+  if (!gl.cap) LQCD_HIP_TRY(hipStreamCreateWithFlags(&gl.cap, hipStreamNonBlocking));
+  LQCD_HIP_TRY(hipStreamBeginCapture(gl.cap, hipStreamCaptureModeThreadLocal));
+  int rc = LQCD_OK;
+  for (int i = 0; i < k.poll && rc == LQCD_OK; ++i) rc = launch_iteration(c, k, gl.cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(gl.cap, &graph);
+  if (rc != LQCD_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    set_error("graph capture failed: %s", hipGetErrorString(e));
+    return LQCD_ERR_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) {
+    set_error("graph instantiation failed: %s", hipGetErrorString(e2));
+    return LQCD_ERR_HIP;
+  }
+  gl.graphs[key] = exec;
+  *out = exec;
+  return LQCD_OK;
+}
+
+bool debug_enabled() {
+  const char* e = std::getenv("LQCD_DEBUG");
+  return e && e[0] == '1';
+}
+
+// LQCD_DEBUG=1: print the scalars of every system (synchronises the stream).
+void debug_dump(const Ctx& c, const Core& k, const char* where) {
+  if (!debug_enabled()) return;
+  std::vector<SysState> h(k.nsys);
+  if (hipMemcpy(h.data(), c.at<SysState>(c.L.st), sizeof(SysState) * k.nsys,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return;
+  for (int j = 0; j < k.nsys; ++j)
+    fprintf(stderr,
+            "[lqcd debug] %s sys %d: it=%d done=%d conv=%d err=%d rel=%d nrel=%d rho=%.3e "
+            "pp=%.3e a=%.3e target2=%.3e m2s=%.3e\n",
+            where, j, h[j].iters, h[j].done, h[j].conv, h[j].err, h[j].rel, h[j].nrel, h[j].rho,
+            h[j].pp, h[j].a, h[j].target2, h[j].m2s);
+}
+
+int read_flags(const Ctx& c, GlobalFlags* host) {
+  void* pin = nullptr;
+  int rc = pinned(kPinnedParams, &pin);
+  if (rc) return rc;
+  GlobalFlags* hf = static_cast<GlobalFlags*>(pin);  // flags live in [0, kPinnedParams)
+  LQCD_HIP_TRY(hipMemcpyAsync(hf, c.at<GlobalFlags>(c.L.gf), sizeof(GlobalFlags),
+                              hipMemcpyDeviceToHost, c.s));
+  LQCD_HIP_TRY(hipStreamSynchronize(c.s));
+  *host = *hf;
+  return LQCD_OK;
+}
+
+int tune_core(const Ctx& c, Core& k) {
+  int rc;
+  DslashCall t = inner_call(c, k, 1);
+  if ((rc = dslash_tuned(t, c.p.rhs_block, c.s, &k.c_oe))) return rc;
+  t.out_par = 0;
+  t.mode = DM_CG;
+  if ((rc = dslash_tuned(t, c.p.rhs_block, c.s, &k.c_eo))) return rc;
+  DslashCall f = fp64_call(c, k, 1);
+  if ((rc = dslash_tuned(f, 0, c.s, &k.c64_oe))) return rc;
+  f.out_par = 0;
+  f.mode = DM_RES;
+  if ((rc = dslash_tuned(f, 0, c.s, &k.c64_eo))) return rc;
+  k.nb_oe = dslash_nblocks(c.g, k.c_oe);
+  k.nb_eo = dslash_nblocks(c.g, k.c_eo);
+  k.nb64_eo = dslash_nblocks(c.g, k.c64_eo);
+  k.nbv = (c.g.Vh + kVecBlock - 1) / kVecBlock;
+  return LQCD_OK;
+}
+
+// Runs the Krylov iteration to convergence (or max_iter) for k.nsys systems.
+int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delta_host,
+               std::vector<SysState>* state_out) {
+  int rc;
+  if ((rc = tune_core(c, k))) return rc;
+  const hipStream_t s = c.s;
+  SysState* st = c.at<SysState>(c.L.st);
+  GlobalFlags* gf = c.at<GlobalFlags>(c.L.gf);
+  double* dparams = c.at<double>(c.L.params);
+  const bool mixed = is_mixed(c);
+
+  // per-system parameters
+  const size_t np = size_t(k.nsys) * (1 + k.nshift);
+  void* pin = nullptr;
+  if ((rc = pinned(kPinnedParams + np * sizeof(double), &pin))) return rc;
+  double* hp = reinterpret_cast<double*>(static_cast<char*>(pin) + kPinnedParams);
+  for (int j = 0; j < k.nsys; ++j) hp[j] = m2s_host[j];
+  for (size_t i = 0; i < size_t(k.nsys) * k.nshift; ++i) hp[k.nsys + i] = delta_host[i];
+  LQCD_HIP_TRY(hipMemcpyAsync(dparams, hp, np * sizeof(double), hipMemcpyHostToDevice, s));
+
+  const dim3 gv(k.nbv, k.nsys);
+  hipLaunchKernelGGL(k_norm2_f64, gv, dim3(kVecBlock), 0, s, k.b, vstride(c), c.g.Vh,
+                     c.at<double>(c.L.pb));
+  LQCD_LAUNCH_CHECK();
+  int nb_r = k.nbv;
+  if (k.guess) {
+    if ((rc = launch_residual(c, k, dparams, 1, nullptr, c.at<double>(c.L.pr), s))) return rc;
+    nb_r = k.nb64_eo;
+  } else if (mixed) {
+    hipLaunchKernelGGL(k_copy_to_inner<float>, gv, dim3(kVecBlock), 0, s, k.b,
+                       c.at<float2>(c.L.r), c.g.Vh, c.at<double>(c.L.pr));
+  } else {
+    hipLaunchKernelGGL(k_copy_to_inner<double>, gv, dim3(kVecBlock), 0, s, k.b,
+                       c.at<double2>(c.L.r), c.g.Vh, c.at<double>(c.L.pr));
+  }
+  LQCD_LAUNCH_CHECK();
+  if (mixed) {
+    if (!k.guess) {
+      const int64_t n = int64_t(k.nsys) * k.nshift * vstride(c);
+      hipLaunchKernelGGL(k_zero<double2>, dim3(2048), dim3(kVecBlock), 0, s, k.x, n);
+      LQCD_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL((k_init_dirs<float, float>), gv, dim3(kVecBlock), 0, s,
+                       c.at<const float2>(c.L.r), c.at<float2>(c.L.p), c.at<float2>(c.L.xlo),
+                       k.nshift, 1, c.g.Vh, c.at<double>(c.L.pp));
+  } else {
+    hipLaunchKernelGGL((k_init_dirs<double, double>), gv, dim3(kVecBlock), 0, s,
+                       c.at<const double2>(c.L.r), c.at<double2>(c.L.p), k.x, k.nshift,
+                       k.guess ? 0 : 1, c.g.Vh, c.at<double>(c.L.pp));
+  }
+  LQCD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_sc_init, dim3(1), dim3(kScalarThreads), 0, s, st, gf, k.nsys, k.nshift,
+                     dparams, k.tol * k.tol, c.at<double>(c.L.pb), k.nbv,
+                     c.at<double>(c.L.pr), nb_r, c.at<double>(c.L.pp), k.nbv);
+  LQCD_LAUNCH_CHECK();
+
+  hipGraphExec_t exec = nullptr;
+  if (c.p.use_graph) {
+    if ((rc = iteration_graph(c, k, &exec))) return rc;
+  }
+  const int ri = std::max(1, c.p.reliable_interval);
+  int since_rel = 0, total = 0;
+  GlobalFlags f{};
+  if ((rc = read_flags(c, &f))) return rc;
+  debug_dump(c, k, "init");
+  while (!f.all_done && !f.error) {
+    if (exec) {
+      LQCD_HIP_TRY(hipGraphLaunch(exec, s));
+    } else {
+      for (int i = 0; i < k.poll; ++i)
+        if ((rc = launch_iteration(c, k, s))) return rc;
+    }
+    total += k.poll;
+    since_rel += k.poll;
+    if ((rc = read_flags(c, &f))) return rc;
+    debug_dump(c, k, "poll");
+    if (mixed && !f.error && (f.rel_req || f.all_done || since_rel >= ri)) {
+      if ((rc = launch_reliable(c, k, s))) return rc;
+      since_rel = 0;
+      if ((rc = read_flags(c, &f))) return rc;
+      debug_dump(c, k, "reliable");
+    }
+    if (total > c.p.max_iter + 2 * k.poll) break;  // device limits iterations; host guard
+  }
+  state_out->resize(k.nsys);
+  LQCD_HIP_TRY(hipMemcpyAsync(state_out->data(), st, sizeof(SysState) * k.nsys,
+                              hipMemcpyDeviceToHost, s));
+  LQCD_HIP_TRY(hipStreamSynchronize(s));
+  if (f.error) {
+    set_error("solver hit a non-finite value or non-positive curvature");
+    return LQCD_ERR_NUMERIC;
+  }
+  return LQCD_OK;
+}
+
+// |b_j - (m^2 + sigma_s) x_js + D_eo D_oe x_js|^2 for every (j, s), FP64.
+int verify(const Ctx& c, Core& k, const double* sigma, std::vector<double>* res2) {
+  const int64_t vs = vstride(c);
+  int rc;
+  double* dres = c.at<double>(c.L.resn);
+  for (int s = 0; s < k.nshift; ++s) {
+    DslashCall e1 = fp64_call(c, k, 1);
+    e1.mode = DM_PLAIN;
+    e1.in = k.x + int64_t(s) * vs;
+    e1.in_stride = int64_t(k.nshift) * vs;
+    e1.out = c.ws + c.L.thi;
+    e1.out_stride = vs;
+    if ((rc = dslash_launch(e1, k.c64_oe, c.s))) return rc;
+    DslashCall e2 = fp64_call(c, k, 0);
+    e2.mode = DM_RES;
+    e2.r_prec = LQCD_F64;
+    e2.in = c.ws + c.L.thi;
+    e2.in_stride = vs;
+    e2.diag = k.x + int64_t(s) * vs;
+    e2.diag_stride = int64_t(k.nshift) * vs;
+    e2.b = k.b;
+    e2.b_stride = vs;
+    e2.r = nullptr;
+    e2.m2s_c = c.m2 + sigma[s];
+    e2.partials = c.at<double>(c.L.pres);
+    if ((rc = dslash_launch(e2, k.c64_eo, c.s))) return rc;
+    hipLaunchKernelGGL(k_reduce_vec, dim3(k.nsys), dim3(kVecBlock), 0, c.s,
+                       c.at<const double>(c.L.pres), k.nb64_eo, dres + int64_t(s) * k.nsys);
+    LQCD_LAUNCH_CHECK();
+  }
+  res2->resize(size_t(k.nsys) * k.nshift);
+  std::vector<double> tmp(size_t(k.nsys) * k.nshift);
+  LQCD_HIP_TRY(hipMemcpyAsync(tmp.data(), dres, tmp.size() * 8, hipMemcpyDeviceToHost, c.s));
+  LQCD_HIP_TRY(hipStreamSynchronize(c.s));
+  for (int s = 0; s < k.nshift; ++s)
+    for (int j = 0; j < k.nsys; ++j) (*res2)[size_t(j) * k.nshift + s] = tmp[size_t(s) * k.nsys + j];
+  return LQCD_OK;
+}
+
+int check_params(const lqcd_solver_params* p) {
+  if (!p) {
+    set_error("params is NULL");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (!(p->mass > 0.0) || !std::isfinite(p->mass)) {
+    set_error("mass = %g must be finite and > 0", p->mass);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (!(p->tol > 0.0 && p->tol < 1.0)) {
+    set_error("tol = %g must be in (0, 1)", p->tol);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (p->max_iter <= 0) {
+    set_error("max_iter = %d must be > 0", p->max_iter);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  int rc = check_prec_fmt(p->inner_prec, p->inner_fmt);
+  if (rc) return rc;
+  if (p->inner_prec == LQCD_F32 && !(p->reliable_delta > 0.0 && p->reliable_delta < 1.0)) {
+    set_error("reliable_delta = %g must be in (0, 1)", p->reliable_delta);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (p->inner_prec == LQCD_F32 && p->reliable_interval <= 0) {
+    set_error("reliable_interval = %d must be > 0 for mixed precision", p->reliable_interval);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (p->use_graph != 0 && p->use_graph != 1) {
+    set_error("use_graph must be 0 or 1");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (p->rhs_block != 0 && p->rhs_block != 1 && p->rhs_block != 2 && p->rhs_block != 4 &&
+      p->rhs_block != 8) {
+    set_error("rhs_block = %d must be 0, 1, 2, 4 or 8", p->rhs_block);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (p->poll_interval < 0 || p->max_refine < 0) {
+    set_error("poll_interval and max_refine must be >= 0");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  return LQCD_OK;
+}
+
+int poll_for(const lqcd_solver_params& p) {
+  int poll = p.poll_interval > 0 ? p.poll_interval : (p.inner_prec == LQCD_F32 ? 10 : 50);
+  if (p.inner_prec == LQCD_F32) {
+    const int ri = p.reliable_interval;
+    if (poll > ri) poll = ri;
+    while (ri % poll) --poll;  // a reliable update falls on a poll boundary
+  }
+  return poll;
+}
+
+// Shared driver of lqcd_cg (nshift = 1, x holds a guess) and lqcd_cg_multishift.
+int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U64,
+          const void* Uinner, int32_t nshift, const double* sigma, const void* b, void* x,
+          int32_t nrhs, bool guess, lqcd_solve_stats* stats, void* ws, size_t ws_bytes,
+          void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  clear_error();
+  int rc;
+  if ((rc = check_geom(geom)) || (rc = check_params(params)) || (rc = check_ptr(U64, "U64")) ||
+      (rc = check_ptr(b, "b")) || (rc = check_ptr(x, "x")) || (rc = check_nrhs(nrhs)))
+    return rc;
+  if (Uinner && (rc = check_ptr(Uinner, "Uinner"))) return rc;
+  if (!stats || !sigma) {
+    set_error("stats and sigma must be host arrays");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (nshift < 1 || nshift > kMaxShift) {
+    set_error("nshift = %d must be in [1, %d]", nshift, kMaxShift);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  for (int s = 0; s < nshift; ++s)
+    if (!(sigma[s] >= 0.0) || !std::isfinite(sigma[s])) {
+      set_error("sigma[%d] = %g must be finite and >= 0", s, sigma[s]);
+      return LQCD_ERR_INVALID_ARG;
+    }
+  if (b == x) {
+    set_error("b and x must not alias");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  Ctx c;
+  c.g = make_kgeom(geom);
+  c.p = *params;
+  c.iprec = params->inner_prec;
+  c.ifmt = params->inner_fmt;
+  c.U64 = U64;
+  c.L = make_layout(c.g, c.iprec, c.ifmt, nshift, nrhs);
+  if (!ws || ws_bytes < c.L.total) {
+    set_error("workspace of %zu bytes is too small: %zu needed", ws_bytes, c.L.total);
+    return LQCD_ERR_WORKSPACE;
+  }
+  if ((rc = check_ptr(ws, "ws"))) return rc;
+  c.ws = static_cast<char*>(ws);
+  c.s = (hipStream_t)stream;
+  c.nrhs_max = nrhs;
+  c.m2 = params->mass * params->mass;
+  c.rel_delta = params->reliable_delta;
+
+  std::lock_guard<std::mutex> lk(G().mu);
+  if (!c.L.has_links) {
+    c.Uin = U64;
+  } else if (Uinner) {
+    c.Uin = Uinner;
+  } else {
+    c.Uin = c.ws + c.L.links;
+    if ((rc = convert_links_async(c.g, U64, LQCD_F64, LQCD_LINKS18, c.ws + c.L.links, c.iprec,
+                                  c.ifmt, c.s)))
+      return rc;
+  }
+
+  int base = 0;
+  for (int s = 1; s < nshift; ++s)
+    if (sigma[s] < sigma[base]) base = s;
+
+  Core k{};
+  k.nsys = nrhs;
+  k.nshift = nshift;
+  k.base = base;
+  k.guess = guess;
+  k.b = static_cast<const double2*>(b);
+  k.x = static_cast<double2*>(x);
+  k.tol = params->tol;
+  k.poll = poll_for(c.p);
+  std::vector<double> m2s(nrhs, c.m2 + sigma[base]);
+  std::vector<double> delta(size_t(nrhs) * nshift);
+  for (int j = 0; j < nrhs; ++j)
+    for (int s = 0; s < nshift; ++s) delta[size_t(j) * nshift + s] = sigma[s] - sigma[base];
+  std::vector<SysState> main_state;
+  const int rc_core = core_solve(c, k, m2s.data(), delta.data(), &main_state);
+  if (rc_core && rc_core != LQCD_ERR_NUMERIC) return rc_core;
+
+  std::vector<int> refine_iters(size_t(nrhs) * nshift, 0);
+  std::vector<double> res2;
+  if ((rc = verify(c, k, sigma, &res2))) return rc;
+  auto failing = [&]() {
+    std::vector<int> f;
+    for (int j = 0; j < nrhs; ++j)
+      for (int s = 0; s < nshift; ++s) {
+        const double bn = main_state[j].bnorm2;
+        const double r2 = res2[size_t(j) * nshift + s];
+        if (!(r2 <= params->tol * params->tol * bn)) f.push_back(j * nshift + s);
+      }
+    return f;
+  };
+  int numeric = rc_core == LQCD_ERR_NUMERIC;
+  for (int round = 0; round < params->max_refine && !numeric; ++round) {
+    const std::vector<int> fail = failing();
+    if (fail.empty()) break;
+    const int64_t vs = vstride(c);
+    const size_t vbytes = size_t(vs) * 16;
+    for (size_t off = 0; off < fail.size(); off += size_t(nrhs)) {
+      const int nb = int(std::min(fail.size() - off, size_t(nrhs)));
+      std::vector<double> rm2s(nb), rdelta(nb, 0.0);
+      double2* xb = c.at<double2>(c.L.xb);
+      double2* bb = c.at<double2>(c.L.bb);
+      for (int q = 0; q < nb; ++q) {
+        const int js = fail[off + q], j = js / nshift, s = js % nshift;
+        LQCD_HIP_TRY(hipMemcpyAsync(xb + q * vs, k.x + int64_t(js) * vs, vbytes,
+                                    hipMemcpyDeviceToDevice, c.s));
+        LQCD_HIP_TRY(hipMemcpyAsync(bb + q * vs, k.b + int64_t(j) * vs, vbytes,
+                                    hipMemcpyDeviceToDevice, c.s));
+        rm2s[q] = c.m2 + sigma[s];
+      }
+      Core r{};
+      r.nsys = nb;
+      r.nshift = 1;
+      r.base = 0;
+      r.guess = true;
+      r.b = bb;
+      r.x = xb;
+      r.tol = 0.5 * params->tol;
+      r.poll = k.poll;
+      std::vector<SysState> rstate;
+      const int rc2 = core_solve(c, r, rm2s.data(), rdelta.data(), &rstate);
+      if (rc2 == LQCD_ERR_NUMERIC) numeric = 1;
+      else if (rc2) return rc2;
+      for (int q = 0; q < nb; ++q) {
+        const int js = fail[off + q];
+        LQCD_HIP_TRY(hipMemcpyAsync(k.x + int64_t(js) * vs, xb + q * vs, vbytes,
+                                    hipMemcpyDeviceToDevice, c.s));
+        refine_iters[js] += rstate[q].iters;
+      }
+    }
+    if ((rc = tune_core(c, k))) return rc;
+    if ((rc = verify(c, k, sigma, &res2))) return rc;
+  }
+
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool all_conv = true;
+  for (int j = 0; j < nrhs; ++j)
+    for (int s = 0; s < nshift; ++s) {
+      const size_t i = size_t(j) * nshift + s;
+      const double bn = main_state[j].bnorm2;
+      lqcd_solve_stats& o = stats[i];
+      o.iters = main_state[j].iters;
+      o.reliable_updates = main_state[j].nrel;
+      o.refine_iters = refine_iters[i];
+      o.true_rel_residual = bn > 0 ? std::sqrt(res2[i] / bn) : std::sqrt(res2[i]);
+      o.converged = o.true_rel_residual <= params->tol ? 1 : 0;
+      o.seconds = secs;
+      all_conv &= o.converged == 1;
+    }
+  if (numeric) {
+    set_error("solver hit a non-finite value or non-positive curvature");
+    return LQCD_ERR_NUMERIC;
+  }
+  if (!all_conv) {
+    set_error("true residual above tol for at least one system after max_iter / refinement");
+    return LQCD_ERR_NOT_CONVERGED;
+  }
+  return LQCD_OK;
+}
+
+}  // namespace
+
+void solver_release() {
+  std::lock_guard<std::mutex> lk(G().mu);
+  clear_graphs();
+  if (G().pinned) (void)hipHostFree(G().pinned);
+  G().pinned = nullptr;
+  G().pinned_bytes = 0;
+  if (G().cap) (void)hipStreamDestroy(G().cap);
+  G().cap = nullptr;
+}
+
+}  // namespace lqcd
+
+using namespace lqcd;
+
+extern "C" {
+
+void lqcd_solver_params_default(lqcd_solver_params* p) {
+  if (!p) return;
+  p->mass = 0.1;
+  p->tol = 1e-10;
+  p->max_iter = 10000;
+  p->inner_prec = LQCD_F64;
+  p->inner_fmt = LQCD_LINKS18;
+  p->reliable_interval = 100;
+  p->use_graph = 1;
+  p->rhs_block = 0;
+  p->poll_interval = 0;
+  p->max_refine = 3;
+  p->reliable_delta = 1e-3;
+}
+
+size_t lqcd_solver_workspace_bytes(const lqcd_geom* g, const lqcd_solver_params* p,
+                                   int32_t nshift, int32_t nrhs) {
+  if (check_geom(g) || check_params(p) || check_nrhs(nrhs) || nshift < 1 || nshift > kMaxShift)
+    return 0;
+  return make_layout(make_kgeom(g), p->inner_prec, p->inner_fmt, nshift, nrhs).total;
+}
+
+int lqcd_cg(const lqcd_geom* g, const lqcd_solver_params* p, const void* U64, const void* Uinner,
+            double sigma, const void* b, void* x, int32_t nrhs, lqcd_solve_stats* stats,
+            void* ws, size_t ws_bytes, void* stream) {
+  return solve(g, p, U64, Uinner, 1, &sigma, b, x, nrhs, true, stats, ws, ws_bytes, stream);
+}
+
+int lqcd_cg_multishift(const lqcd_geom* g, const lqcd_solver_params* p, const void* U64,
+                       const void* Uinner, int32_t nshift, const double* sigma, const void* b,
+                       void* x, int32_t nrhs, lqcd_solve_stats* stats, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return solve(g, p, U64, Uinner, nshift, sigma, b, x, nrhs, false, stats, ws, ws_bytes,
+               stream);
+}
+
+int lqcd_finalize(void) {
+  solver_release();
+  dslash_clear_tuning();
+  return LQCD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// STREAM-style copy and triad kernels: the achievable HBM bandwidth of the
+// device, measured next to the 8 TB/s specification so the hopping kernel's
+// bandwidth can be read against both.  16-byte vector accesses, grid-stride.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace lqcd {
+namespace {
+
+__global__ void __launch_bounds__(256) k_copy(const double2* __restrict__ a,
+                                              double2* __restrict__ b, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = a[i];
+}
+
+__global__ void __launch_bounds__(256) k_triad(const double2* __restrict__ a,
+                                               const double2* __restrict__ b,
+                                               double2* __restrict__ c, double s, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 x = a[i], y = b[i];
+    c[i] = make_double2(fma(s, y.x, x.x), fma(s, y.y, x.y));
+  }
+}
+
+}  // namespace
+}  // namespace lqcd
+
+using namespace lqcd;
+
+extern "C" {
+
+// Measures copy (2 streams) and triad (3 streams) bandwidth over `bytes` per
+// array, median of `reps` timed launches each; results in GB/s (1e9 B/s).
+// Allocates and frees its three arrays; synchronises the device.
+int lqcd_stream_bandwidth(size_t bytes, int32_t reps, double* copy_gbs, double* triad_gbs) {
+  clear_error();
+  if (bytes < 16 || reps < 1 || !copy_gbs || !triad_gbs) {
+    set_error("stream: bytes >= 16, reps >= 1 and non-null outputs required");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const int64_t n = int64_t(bytes / 16);
+  double2 *a = nullptr, *b = nullptr, *c = nullptr;
+  LQCD_HIP_TRY(hipMalloc(&a, n * 16));
+  LQCD_HIP_TRY(hipMalloc(&b, n * 16));
+  LQCD_HIP_TRY(hipMalloc(&c, n * 16));
+  LQCD_HIP_TRY(hipMemset(a, 0, n * 16));
+  LQCD_HIP_TRY(hipMemset(b, 0, n * 16));
+  hipEvent_t e0, e1;
+  LQCD_HIP_TRY(hipEventCreate(&e0));
+  LQCD_HIP_TRY(hipEventCreate(&e1));
+  const int grid = 256 * 32;
+  auto median_ms = [&](auto&& launch) {
+    launch();
+    float best[64];
+    const int r = reps > 64 ? 64 : reps;
+    for (int i = 0; i < r; ++i) {
+      (void)hipEventRecord(e0, nullptr);
+      launch();
+      (void)hipEventRecord(e1, nullptr);
+      (void)hipEventSynchronize(e1);
+      (void)hipEventElapsedTime(&best[i], e0, e1);
+    }
+    for (int i = 1; i < r; ++i)
+      for (int j = i; j > 0 && best[j] < best[j - 1]; --j) {
+        const float t = best[j];
+        best[j] = best[j - 1];
+        best[j - 1] = t;
+      }
+    return double(best[r / 2]);
+  };
+  const double tc = median_ms([&] {
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, nullptr, a, b, n);
+  });
+  const double tt = median_ms([&] {
+    hipLaunchKernelGGL(k_triad, dim3(grid), dim3(256), 0, nullptr, a, b, c, 1.5, n);
+  });
+  const hipError_t err = hipGetLastError();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  (void)hipFree(c);
+  if (err != hipSuccess) {
+    set_error("stream kernels failed: %s", hipGetErrorString(err));
+    return LQCD_ERR_HIP;
+  }
+  *copy_gbs = 2.0 * n * 16 / (tc * 1e-3) / 1e9;
+  *triad_gbs = 3.0 * n * 16 / (tt * 1e-3) / 1e9;
+  return LQCD_OK;
+}
+
+}  // extern "C"

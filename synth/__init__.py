@@ -23,12 +23,17 @@ production configurations, which are not available.
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+
 import numpy as np
 
 __all__ = [
     "volume", "site_coords", "site_parity", "rng",
     "links_unit", "links_exp", "links_haar", "haar_su3",
     "gaussian_field", "gaussian_even_source", "su3_algebra_directions",
+    "su3_algebra_coeffs", "su3_from_coeffs", "expi_coeffs",
     "rational_shifts", "rational_weights",
 ]
 
@@ -89,33 +94,68 @@ def _gaussian_hermitian(g: np.random.Generator, n: int) -> np.ndarray:
     return np.einsum("na,aij->nij", c, _gell_mann() / 2.0)
 
 
-def _expi_hermitian(H: np.ndarray, beta: float) -> np.ndarray:
-    """exp(i*beta*H) for a stack of Hermitian matrices, via eigendecomposition."""
-    w, v = np.linalg.eigh(H)
-    ph = np.exp(1j * beta * w)
-    return np.einsum("nij,nj,nkj->nik", v, ph, v.conj())
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_GEN_SRC = os.path.join(_HERE, "synth_gen.c")
+_GEN_LIB = os.path.join(_HERE, "libsynth_gen.so")
+_gen = None
+_CHUNK = 1 << 21
+
+
+def build(force: bool = True) -> str:
+    """Compile the generator helper (gcc, OpenMP)."""
+    if force or not os.path.exists(_GEN_LIB) or os.path.getmtime(_GEN_LIB) < os.path.getmtime(_GEN_SRC):
+        tmp = _GEN_LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o",
+                               tmp, _GEN_SRC, "-lm"])
+        os.replace(tmp, _GEN_LIB)
+    return _GEN_LIB
+
+
+def _lib():
+    global _gen
+    if _gen is None:
+        build(force=False)
+        lib = ctypes.CDLL(_GEN_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.synth_su3_from_gauss.argtypes = [dp, dp, ctypes.c_long]
+        lib.synth_su3_expi.argtypes = [dp, ctypes.c_double, dp, ctypes.c_long]
+        _gen = lib
+    return _gen
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 def links_exp(L, beta: float, seed: int) -> np.ndarray:
-    """Near-unit SU(3) links exp(i*beta*H), H Gaussian traceless Hermitian."""
+    """Near-unit SU(3) links exp(i*beta*H), H = sum_a c_a lambda_a / 2 with
+    c_a ~ N(0,1) (Gaussian traceless Hermitian).  The exponential is taken by
+    scaling and squaring in the C helper, rows re-orthonormalised to SU(3)."""
     V = volume(L)
     g = rng(seed)
-    H = _gaussian_hermitian(g, 4 * V)
-    return _expi_hermitian(H, beta).reshape(4, V, 3, 3)
+    out = np.empty((4 * V, 3, 3), np.complex128)
+    for lo in range(0, 4 * V, _CHUNK):
+        hi = min(4 * V, lo + _CHUNK)
+        c = np.ascontiguousarray(g.standard_normal((hi - lo, 8)))
+        _lib().synth_su3_expi(_dp(c), float(beta), _dp(out[lo:hi]), hi - lo)
+    return out.reshape(4, V, 3, 3)
 
 
 def haar_su3(g: np.random.Generator, n: int) -> np.ndarray:
-    """n Haar-distributed SU(3) matrices from the QR of complex Gaussians.
+    """n Haar-distributed SU(3) matrices.
 
-    The phases of R's diagonal are moved into Q (which makes Q Haar on U(3)),
-    then Q is divided by a cube root of det(Q) to land on SU(3).
+    Rows 0 and 1 are Gram-Schmidt orthonormalised complex Gaussian vectors
+    (the first two rows of a Haar U(3) matrix); row 2 = conj(row0 x row1)
+    fixes det = 1.  Completing the rows this way commutes with left
+    multiplication by SU(3), so the result is Haar on SU(3).
     """
-    Z = _complex_gauss(g, (n, 3, 3))
-    Q, R = np.linalg.qr(Z)
-    d = np.diagonal(R, axis1=1, axis2=2)
-    Q = Q * (d / np.abs(d))[:, None, :]
-    det = np.linalg.det(Q)
-    return Q / np.exp(1j * np.angle(det) / 3.0)[:, None, None]
+    out = np.empty((n, 3, 3), np.complex128)
+    for lo in range(0, n, _CHUNK):
+        hi = min(n, lo + _CHUNK)
+        # interleaved (re, im) standard normals; Gram-Schmidt ignores the scale
+        z = g.standard_normal((hi - lo, 18))
+        _lib().synth_su3_from_gauss(_dp(z), _dp(out[lo:hi]), hi - lo)
+    return out
 
 
 def links_haar(L, seed: int) -> np.ndarray:
@@ -135,14 +175,34 @@ def gaussian_even_source(L, n: int, seed: int) -> np.ndarray:
     return f
 
 
+def su3_algebra_coeffs(L, n: int, seed: int) -> np.ndarray:
+    """Gell-Mann coefficients ``[n][4][V][8]`` (N(0,1)) of n random su(3)
+    directions, one traceless anti-Hermitian T = i sum_a c_a lambda_a / 2 per link."""
+    return rng(seed).standard_normal((n, 4, volume(L), 8))
+
+
+def su3_from_coeffs(c: np.ndarray) -> np.ndarray:
+    """T = i sum_a c_a lambda_a / 2 for coefficient arrays ``[..., 8]``."""
+    return 1j * np.einsum("...a,aij->...ij", c, _gell_mann() / 2.0)
+
+
+def expi_coeffs(c: np.ndarray, beta: float) -> np.ndarray:
+    """exp(beta T) = exp(i beta sum_a c_a lambda_a / 2) for coefficients ``[..., 8]``."""
+    c2 = np.ascontiguousarray(c, dtype=np.float64).reshape(-1, 8)
+    out = np.empty((c2.shape[0], 3, 3), np.complex128)
+    for lo in range(0, c2.shape[0], _CHUNK):
+        hi = min(c2.shape[0], lo + _CHUNK)
+        _lib().synth_su3_expi(_dp(c2[lo:hi]), float(beta), _dp(out[lo:hi]), hi - lo)
+    return out.reshape(c.shape[:-1] + (3, 3))
+
+
 def su3_algebra_directions(L, n: int, seed: int) -> np.ndarray:
     """n random su(3) directions, one traceless anti-Hermitian matrix per link.
 
-    Shape ``[n][4][V][3][3]``; each matrix is i * sum_a c_a lambda_a / 2.
+    Shape ``[n][4][V][3][3]``; each matrix is i * sum_a c_a lambda_a / 2 with the
+    coefficients of su3_algebra_coeffs(L, n, seed).
     """
-    V = volume(L)
-    H = _gaussian_hermitian(rng(seed), n * 4 * V)
-    return (1j * H).reshape(n, 4, V, 3, 3)
+    return su3_from_coeffs(su3_algebra_coeffs(L, n, seed))
 
 
 def random_gauge_transform(L, seed: int) -> np.ndarray:

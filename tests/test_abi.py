@@ -1,0 +1,148 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function that include/lqcd.h declares,
+validate arguments on the host before any device work, and size its buffers
+as the paper's byte counts say.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lqcd.h")
+
+
+@pytest.fixture(scope="module")
+def lq():
+    import paper_1801_01473_amd as lq
+    return lq
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lqcd_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["lqcd_doe", "lqcd_deo", "lqcd_cg", "lqcd_cg_multishift",
+                     "lqcd_fermion_force", "lqcd_action", "lqcd_pack_links"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lq):
+    lib = ctypes.CDLL(lq.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(lq.EXPORTED)
+
+
+def test_status_strings(lq):
+    assert lq.status_string(0) == "LQCD_OK"
+    assert lq.status_string(5) == "LQCD_ERR_NOT_CONVERGED"
+    assert lq.status_string(99) == "LQCD_ERR_UNKNOWN"
+    assert lq.version() == 10000
+
+
+def _golden():
+    vals = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_byte_counts.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = int(v)
+    return vals
+
+
+def test_buffer_sizes_match_paper_byte_counts(lq):
+    gold = _golden()
+    L = (4, 6, 8, 10)
+    g = lq.Geometry(L)
+    Vh = g.Vh
+    # one parity of a FP64 spinor: 48 bytes per site
+    assert lq.spinor_bytes(g, lq.F64) == gold["spinor_fp64_bytes_per_site"] * Vh
+    assert lq.spinor_bytes(g, lq.F32) == 24 * Vh
+    # 12-real FP64 links: 4 directions x 12 doubles per site; a thickness-2
+    # slice costs 2 x that per unit of surface
+    per_site = lq.links_bytes(g, lq.F64, lq.LINKS12) // g.V
+    assert 2 * per_site == gold["gauge_12real_fp64_bytes_per_unit_surface_thickness2"]
+    assert lq.links_bytes(g, lq.F64, lq.LINKS18) == 4 * 18 * 8 * g.V
+    assert lq.links_bytes(g, lq.F32, lq.LINKS12) == 4 * 12 * 4 * g.V
+
+
+@pytest.mark.parametrize("L", [(3, 4, 4, 4), (4, 4, 4, 0), (4, 4, 4, 1), (4, -2, 4, 4)])
+def test_bad_geometry_is_rejected_before_device_work(lq, L):
+    g = lq.lqcd_geom()
+    for i in range(4):
+        g.L[i] = L[i]
+    g.antiperiodic_t = 1
+    assert lq._fn("lqcd_links_bytes")(ctypes.byref(g), 0, 0) == 0
+    st = lq._fn("lqcd_doe")(ctypes.byref(g), 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(32),
+                           ctypes.c_void_p(48), 1, None)
+    assert st == lq.ERR_INVALID_ARG
+    assert "extent" in lq.last_error()
+
+
+def test_bad_arguments_are_rejected(lq):
+    g = lq.Geometry((4, 4, 4, 4))
+    fn = lq._fn("lqcd_doe")
+    # NULL and misaligned pointers, bad enums, nrhs out of range
+    assert fn(g.c(), 0, 0, None, ctypes.c_void_p(32), ctypes.c_void_p(48), 1, None) == 1
+    assert fn(g.c(), 0, 0, ctypes.c_void_p(17), ctypes.c_void_p(32), ctypes.c_void_p(48), 1,
+              None) == 1
+    assert fn(g.c(), 2, 0, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48), 1,
+              None) == 1
+    assert fn(g.c(), 0, 3, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48), 1,
+              None) == 1
+    assert fn(g.c(), 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48), 0,
+              None) == 1
+    assert fn(g.c(), 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48), 65,
+              None) == 1
+    assert fn(g.c(), 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(32), 1,
+              None) == 1  # in == out
+
+
+def test_solver_parameter_validation(lq):
+    g = lq.Geometry((4, 4, 4, 4))
+    p = lq.solver_params(mass=0.1)
+    assert lq.solver_workspace_bytes(g, p, 12, 8) > 0
+    for bad in [dict(mass=0.0), dict(mass=-1.0), dict(tol=0.0), dict(tol=1.5), dict(max_iter=0),
+                dict(inner_prec=3), dict(inner_fmt=5), dict(rhs_block=3), dict(use_graph=2),
+                dict(inner_prec=1, reliable_interval=0), dict(max_refine=-1)]:
+        kw = dict(mass=0.1)
+        kw.update(bad)
+        q = lq.solver_params(**kw)
+        assert lq.solver_workspace_bytes(g, q, 1, 1) == 0, bad
+    assert lq.solver_workspace_bytes(g, p, 0, 1) == 0
+    assert lq.solver_workspace_bytes(g, p, 33, 1) == 0
+    assert lq.solver_workspace_bytes(g, p, 1, 65) == 0
+    # a too-small workspace is reported before any device work
+    stats = (lq.SolveStats * 1)()
+    sig = (ctypes.c_double * 1)(0.0)
+    st = lq._fn("lqcd_cg_multishift")(g.c(), ctypes.byref(p), ctypes.c_void_p(256), None, 1, sig,
+                                      ctypes.c_void_p(512), ctypes.c_void_p(1024), 1, stats,
+                                      ctypes.c_void_p(4096), 16, None)
+    assert st == lq.ERR_WORKSPACE
+    sig_bad = (ctypes.c_double * 2)(0.0, -1.0)
+    st = lq._fn("lqcd_cg_multishift")(g.c(), ctypes.byref(p), ctypes.c_void_p(256), None, 2,
+                                      sig_bad, ctypes.c_void_p(512), ctypes.c_void_p(1024), 1,
+                                      stats, ctypes.c_void_p(4096), 1 << 40, None)
+    assert st == lq.ERR_INVALID_ARG and "sigma" in lq.last_error()
+
+
+def test_force_and_action_validation(lq):
+    g = lq.Geometry((4, 4, 4, 4))
+    al = (ctypes.c_double * 2)(1.0, 2.0)
+    f = lq._fn("lqcd_fermion_force")
+    v = ctypes.c_void_p
+    assert f(g.c(), v(256), 1, 2, al, v(512), 2, 0, v(1024), None) == lq.ERR_INVALID_ARG
+    assert f(g.c(), v(256), 0, 2, al, v(512), 0, 0, v(1024), None) == lq.ERR_INVALID_ARG
+    assert f(g.c(), v(256), 1, 0, al, v(512), 0, 0, v(1024), None) == lq.ERR_INVALID_ARG
+    assert f(g.c(), v(256), 1, 2, al, v(512), 0, 0, v(512), None) == lq.ERR_INVALID_ARG
+    S = ctypes.c_double(0)
+    a = lq._fn("lqcd_action")
+    assert a(g.c(), 1, 2, 0.0, al, v(256), v(512), ctypes.byref(S), v(1024), 8,
+             None) == lq.ERR_WORKSPACE

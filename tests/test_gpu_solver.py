@@ -1,0 +1,184 @@
+"""GPU solver parity: every solution's true residual, recomputed by the CPU
+oracle's FP64 operator, must be <= 1e-10 relative, whatever the inner
+precision.  Solutions are also compared with the oracle's own solutions."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lq():
+    import paper_1801_01473_amd as lq
+    return lq
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def setup(lq, L, links, b_seed, nrhs=1):
+    g = lq.Geometry(L)
+    U64 = lq.pack_links(g, cu(links))
+    b_nat = synth.gaussian_even_source(L, nrhs, b_seed)
+    b = lq.pack_spinor(g, cu(b_nat), 0)
+    return g, U64, b_nat, b
+
+
+MODES = [dict(inner_prec=0, inner_fmt=0), dict(inner_prec=1, inner_fmt=1),
+         dict(inner_prec=1, inner_fmt=0), dict(inner_prec=0, inner_fmt=1)]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_cg_config1(lq, mode):
+    """4^4, exp(0.3iH) links, m = 0.1, Gaussian source, tol 1e-10."""
+    L = (4, 4, 4, 4)
+    U = synth.links_exp(L, 0.3, 101)
+    g, U64, b_nat, b = setup(lq, L, U, 201)
+    p = lq.solver_params(mass=0.1, tol=1e-10, **mode)
+    x, st, stats = lq.cg(g, p, U64, b)
+    xn = host(lq.unpack_spinor(g, x, 0))[0]
+    tr = oracle.true_residual(L, U, 0.1, 0.0, b_nat[0], xn)
+    assert tr <= 1e-10
+    assert stats[0]["converged"] == 1 and abs(stats[0]["true_rel_residual"] - tr) < 1e-11
+    xo, _, _, _ = oracle.cg(L, U, 0.1, 0.0, b_nat[0], tol=1e-12)
+    assert H.max_rel(xn, xo) < 1e-7
+
+
+def test_cg_free_field_converges_in_four_iterations(lq):
+    L = (4, 4, 4, 4)
+    g, U64, b_nat, b = setup(lq, L, synth.links_unit(L), 202)
+    p = lq.solver_params(mass=0.1, tol=1e-10)
+    x, st, stats = lq.cg(g, p, U64, b)
+    assert stats[0]["iters"] <= 5 and stats[0]["refine_iters"] == 0
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 2, 8), (8, 8, 8, 8)])
+@pytest.mark.parametrize("mode", MODES[:2])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_multishift_every_shift_true_residual(lq, L, mode, nrhs):
+    m = 0.02
+    U = synth.links_exp(L, 0.5, 103)
+    g, U64, b_nat, b = setup(lq, L, U, 203, nrhs)
+    sig = synth.rational_shifts(12)
+    p = lq.solver_params(mass=m, tol=1e-10, **mode)
+    X, st, stats = lq.cg_multishift(g, p, U64, sig, b)
+    Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(nrhs, len(sig), -1, 3)
+    for j in range(nrhs):
+        for s, sg in enumerate(sig):
+            tr = oracle.true_residual(L, U, m, sg, b_nat[j], Xn[j, s])
+            assert tr <= 1e-10, (j, s, tr)
+            assert stats[j][s]["converged"] == 1
+
+
+def test_multishift_matches_oracle_solutions(lq):
+    L = (4, 4, 4, 4)
+    m = 0.05
+    U = synth.links_haar(L, 104)
+    g, U64, b_nat, b = setup(lq, L, U, 204)
+    sig = np.array([0.0, 0.01, 0.1, 1.0])
+    p = lq.solver_params(mass=m, tol=1e-10)
+    X, st, stats = lq.cg_multishift(g, p, U64, sig, b)
+    Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0))
+    Xo, _, _, _ = oracle.cg_multishift(L, U, m, sig, b_nat[0], tol=1e-12)
+    for s in range(len(sig)):
+        assert H.max_rel(Xn[s], Xo[s]) < 1e-7
+
+
+def test_batched_rhs_match_single_rhs(lq):
+    L = (6, 4, 4, 6)
+    m = 0.05
+    U = synth.links_exp(L, 0.5, 105)
+    g, U64, b_nat, b = setup(lq, L, U, 205, 4)
+    sig = synth.rational_shifts(6, 1e-3, 1.0)
+    p = lq.solver_params(mass=m, tol=1e-10, inner_prec=1, inner_fmt=1)
+    Xb, _, _ = lq.cg_multishift(g, p, U64, sig, b)
+    for j in range(4):
+        Xs, _, _ = lq.cg_multishift(g, p, U64, sig, b[j:j + 1].contiguous())
+        d = (Xs[0] - Xb[j]).abs().max().item() / Xs[0].abs().max().item()
+        assert d < 1e-6
+
+
+@pytest.mark.parametrize("mode", MODES[:2])
+def test_determinism_and_graph_equivalence(lq, mode):
+    """Two runs are bitwise equal, with and without hipGraph replay."""
+    L = (8, 4, 6, 4)
+    U = synth.links_haar(L, 106)
+    g, U64, b_nat, b = setup(lq, L, U, 206, 2)
+    sig = synth.rational_shifts(5, 1e-3, 1.0)
+    p1 = lq.solver_params(mass=0.05, tol=1e-10, rhs_block=2, use_graph=1, **mode)
+    p0 = lq.solver_params(mass=0.05, tol=1e-10, rhs_block=2, use_graph=0, **mode)
+    X1, _, s1 = lq.cg_multishift(g, p1, U64, sig, b)
+    X2, _, s2 = lq.cg_multishift(g, p1, U64, sig, b)
+    X3, _, s3 = lq.cg_multishift(g, p0, U64, sig, b)
+    assert torch.equal(X1, X2) and torch.equal(X1, X3)
+    assert s1[0][0]["iters"] == s3[0][0]["iters"]
+
+
+def test_not_converged_reports_stats(lq):
+    L = (4, 4, 4, 4)
+    U = synth.links_haar(L, 107)
+    g, U64, b_nat, b = setup(lq, L, U, 207)
+    p = lq.solver_params(mass=0.05, tol=1e-10, max_iter=5, max_refine=0)
+    x, st, stats = lq.cg(g, p, U64, b, check=False)
+    assert st == lq.ERR_NOT_CONVERGED
+    assert stats[0]["iters"] == 5 and stats[0]["converged"] == 0
+    assert 1e-10 < stats[0]["true_rel_residual"] < 1.0
+    assert "true residual" in lq.last_error()
+
+
+def test_cg_initial_guess(lq):
+    L = (4, 4, 4, 4)
+    U = synth.links_exp(L, 0.3, 101)
+    g, U64, b_nat, b = setup(lq, L, U, 201)
+    p = lq.solver_params(mass=0.1, tol=1e-10)
+    x, _, s0 = lq.cg(g, p, U64, b)
+    x2, _, s1 = lq.cg(g, p, U64, b, x=x.clone())
+    assert s1[0]["iters"] <= 1 and s1[0]["converged"] == 1
+
+
+def test_zero_source_gives_zero_solution(lq):
+    L = (4, 4, 4, 4)
+    g = lq.Geometry(L)
+    U64 = lq.pack_links(g, cu(synth.links_haar(L, 1)))
+    b = torch.zeros((1, 3, g.Vh), dtype=torch.complex128, device="cuda")
+    X, st, stats = lq.cg_multishift(g, lq.solver_params(mass=0.1), U64, [0.0, 1.0], b)
+    assert st == 0 and X.abs().max().item() == 0.0 and stats[0][0]["iters"] == 0
+
+
+def test_cg_config2_24(lq):
+    """24^4 Haar links, m = 0.05, plain FP64 CG to 1e-10."""
+    L = (24, 24, 24, 24)
+    U = synth.links_haar(L, 102)
+    g, U64, b_nat, b = setup(lq, L, U, 202)
+    p = lq.solver_params(mass=0.05, tol=1e-10)
+    x, st, stats = lq.cg(g, p, U64, b)
+    xn = host(lq.unpack_spinor(g, x, 0))[0]
+    assert oracle.true_residual(L, U, 0.05, 0.0, b_nat[0], xn) <= 1e-10
+
+
+def test_multishift_config3_32_mixed(lq):
+    """32^4, exp(0.5iH), m = 0.02, 12 shifts in [1e-4, 10], FP32 12-real inner
+    with FP64 reliable updates every 100 iterations: every shift <= 1e-10."""
+    L = (32, 32, 32, 32)
+    m = 0.02
+    U = synth.links_exp(L, 0.5, 103)
+    g, U64, b_nat, b = setup(lq, L, U, 203)
+    sig = synth.rational_shifts(12)
+    p = lq.solver_params(mass=m, tol=1e-10, inner_prec=1, inner_fmt=1, reliable_interval=100)
+    X, st, stats = lq.cg_multishift(g, p, U64, sig, b)
+    assert st == 0
+    Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0))
+    for s, sg in enumerate(sig):
+        tr = oracle.true_residual(L, U, m, sg, b_nat[0], Xn[s])
+        assert tr <= 1e-10, (s, tr)
