@@ -1,0 +1,311 @@
+#!/usr/bin/env python3
+"""Benchmark of the staggered even/odd hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input:
+  1. pack the gauge field (FP64 18-real; the solver converts its FP32 12-real
+     inner copy itself),
+  2. mixed-precision multi-shift CG for every (right-hand side, shift) to a
+     true residual of 1e-10 (FP32 12-real inner iteration, FP64 reliable
+     updates, FP64 verification and batched refinement, hipGraph replay,
+     right-hand sides batched through each link load),
+  3. the rational action S_f,
+  4. the fermion force dS_f/dU on the solutions (projected to su(3)).
+Inputs (links, pseudofermions) are resident in HBM before the timed region.
+
+Workloads (seeded, synthetic; the paper's thermalised production lattices are
+not available):
+  c4  48^4, Haar SU(3) links, m = 0.02, 12 shifts in [1e-4, 10], 8 RHS  (default)
+  c3  32^4, links exp(0.5 i H), m = 0.02, 12 shifts, 1 RHS
+
+Printed: one JSON line with the step throughput (shift-solves/s), the
+time-to-1e-10 of the mixed batched solve next to sequential plain FP64 GPU
+solves of the same systems, D_oe/D_eo bandwidth against the 8 TB/s peak and a
+STREAM ceiling, the roofline of the dominant kernel measured with HIP events,
+and the CPU oracle timed on a bounded sample.
+
+--profile-kernels runs only the dominant kernel and a copy kernel of known
+size (for rocprofv3 counter collection) and exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dslash GB/s & % HBM peak; multishift-CG time-to-1e-10, mixed vs FP64, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c4": dict(L=(48, 48, 48, 48), links="haar", beta=None, link_seed=104, src_seed=204,
+               mass=0.02, nshift=12, nrhs=8,
+               name="48^4 (one GPU's share of 96^4), Haar SU(3) links, m=0.02, "
+                    "12 shifts log-spaced in [1e-4,10], 8 Gaussian RHS batched, FP32 12-real "
+                    "inner / FP64 outer, tol 1e-10; + rational action + fermion force"),
+    "c3": dict(L=(32, 32, 32, 32), links="exp", beta=0.5, link_seed=103, src_seed=203,
+               mass=0.02, nshift=12, nrhs=1,
+               name="32^4, links exp(0.5iH), m=0.02, 12 shifts log-spaced in [1e-4,10], 1 RHS, "
+                    "FP32 12-real inner / FP64 reliable updates, tol 1e-10; + action + force"),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(w):
+    import numpy as np
+    import synth
+    L = w["L"]
+    t0 = time.time()
+    if w["links"] == "haar":
+        U = synth.links_haar(L, w["link_seed"])
+    else:
+        U = synth.links_exp(L, w["beta"], w["link_seed"])
+    phi = synth.gaussian_even_source(L, w["nrhs"], w["src_seed"])
+    sig = synth.rational_shifts(w["nshift"])
+    al = synth.rational_weights(sig)
+    log(f"inputs generated in {time.time() - t0:.1f} s")
+    return U, phi, np.asarray(sig), np.asarray(al)
+
+
+def event_time_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def dslash_bytes_per_site(prec, fmt, nrhs):
+    """Algorithmic bytes per output site: every link once, each input spinor
+    once (perfect neighbour reuse), each output once."""
+    rb = 8 if prec == 0 else 4
+    links = 8 * (9 if fmt == 0 else 6) * 2 * rb
+    return links + nrhs * 2 * (3 * 2 * rb)
+
+
+def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, budget_s=20.0):
+    """Oracle multi-shift CG timed on a bounded sample: a few iterations on one
+    right-hand side of the same lattice, scaled to the GPU run's iteration
+    count and number of right-hand sides."""
+    import oracle
+    L = w["L"]
+    threads = len(os.sched_getaffinity(0))
+    oracle.set_threads(threads)
+    t0 = time.time()
+    oracle.cg_multishift(L, U, w["mass"], sig, phi[0], tol=1e-10, max_iter=1, verify=False)
+    t1 = time.time() - t0
+    n = max(1, min(4, int(budget_s / max(t1, 1e-3))))
+    t0 = time.time()
+    _, _, (its, _), _ = oracle.cg_multishift(L, U, w["mass"], sig, phi[0], tol=1e-10,
+                                             max_iter=n, verify=False)
+    tn = time.time() - t0
+    per_iter = (tn - t1) / max(n - 1, 1) if n > 1 else t1
+    est_solve = per_iter * gpu_iters_per_rhs * w["nrhs"]
+    value = w["nrhs"] * w["nshift"] / est_solve
+    return {
+        "value": value, "unit": "shift-solves/s", "cores": threads, "kind": "oracle",
+        "sample": (f"oracle FP64 multi-shift CG on 1 RHS x {w['nshift']} shifts of the same "
+                   f"{'x'.join(map(str, L))} lattice, {n} iterations ({per_iter:.2f} s/iter on "
+                   f"{threads} threads, {platform.processor() or platform.machine()}), scaled to the "
+                   f"GPU run's {gpu_iters_per_rhs} iterations per RHS x {w['nrhs']} RHS"),
+        "seconds_per_iteration": per_iter,
+        "estimated_solve_s": est_solve,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c4")
+    ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only run the dominant kernel and a copy kernel (for counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(halo exchange across GPUs is out of scope); run with --gpus 1", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1801_01473_amd as lq
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", flush=True)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    L = w["L"]
+    g = lq.Geometry(L)
+    nrhs, nshift = w["nrhs"], w["nshift"]
+    U, phi, sig, al = make_inputs(w)
+    U_dev = torch.from_numpy(U).to("cuda")
+    phi_p = lq.pack_spinor(g, torch.from_numpy(phi).to("cuda"), 0)
+    torch.cuda.synchronize()
+
+    params = lq.solver_params(mass=w["mass"], tol=1e-10, inner_prec=lq.F32,
+                              inner_fmt=lq.LINKS12, reliable_interval=100, use_graph=1)
+    dom = dict(prec=lq.F32, fmt=lq.LINKS12, nrhs=nrhs)
+
+    if args.profile_kernels:
+        U64 = lq.pack_links(g, U_dev)
+        Uin = lq.convert_links(g, U64, lq.F64, lq.LINKS18, dom["prec"], dom["fmt"])
+        x = torch.randn(nrhs, 3, g.Vh, dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            lq.doe(g, Uin, x, out=y)
+        cb, tb = lq.stream_bandwidth(1 << 30, 5)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_kernels": "done", "copy_bytes_per_array": 1 << 30}), flush=True)
+        return
+
+    state = {}
+
+    def step():
+        t0 = time.time()
+        U64 = lq.pack_links(g, U_dev)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        X, st, stats = lq.cg_multishift(g, params, U64, sig, phi_p)
+        t2 = time.time()
+        S = lq.action(g, 0.0, al, phi_p, X)
+        F = lq.fermion_force(g, U64, al, X, mode=0)
+        torch.cuda.synchronize()
+        t3 = time.time()
+        state.update(X=X, stats=stats, S=S, F=F, U64=U64,
+                     t_pack=t1 - t0, t_solve=t2 - t1, t_force=t3 - t2)
+
+    for i in range(args.warmup):
+        log(f"warmup step {i + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    solve_times, force_times = [], []
+    t_start = time.time()
+    for i in range(args.steps):
+        step()
+        solve_times.append(state["t_solve"])
+        force_times.append(state["t_force"])
+        log(f"step {i + 1}/{args.steps}: solve {state['t_solve']:.3f} s, "
+            f"action+force {state['t_force']:.3f} s")
+    torch.cuda.synchronize()
+    elapsed = time.time() - t_start
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = nrhs * nshift / (elapsed / args.steps)
+
+    stats = state["stats"]
+    max_tr = max(s["true_rel_residual"] for row in stats for s in row)
+    all_conv = all(s["converged"] == 1 for row in stats for s in row)
+    iters = [row[0]["iters"] for row in stats]
+    refine = sum(s["refine_iters"] for row in stats for s in row)
+    rel = [row[0]["reliable_updates"] for row in stats]
+
+    # time-to-1e-10: plain FP64 GPU multi-shift, one RHS at a time
+    fp64 = None
+    if not args.no_fp64_baseline:
+        p64 = lq.solver_params(mass=w["mass"], tol=1e-10, inner_prec=lq.F64,
+                               inner_fmt=lq.LINKS18, use_graph=1)
+        U64 = state["U64"]
+        lq.cg_multishift(g, p64, U64, sig, phi_p[0:1].contiguous())  # tune + graph
+        torch.cuda.synchronize()
+        t0 = time.time()
+        it64, tr64 = [], []
+        for j in range(nrhs):
+            _, _, s64 = lq.cg_multishift(g, p64, U64, sig, phi_p[j:j + 1].contiguous())
+            it64.append(s64[0][0]["iters"])
+            tr64.append(max(s["true_rel_residual"] for s in s64[0]))
+        torch.cuda.synchronize()
+        t64 = time.time() - t0
+        fp64 = dict(seconds=t64, iters=it64, max_true_residual=max(tr64))
+        log(f"FP64 sequential baseline: {t64:.3f} s")
+
+    # D_oe bandwidth (standalone, HIP events), STREAM ceiling
+    copy_gbs, triad_gbs = lq.stream_bandwidth(1 << 30, 20)
+    U64 = state["U64"]
+    dsl = {}
+    Uin = lq.convert_links(g, U64, lq.F64, lq.LINKS18, lq.F32, lq.LINKS12)
+    for name, (Ul, prec, fmt, n) in {
+            "fp64_18_1rhs": (U64, lq.F64, lq.LINKS18, 1),
+            "fp32_12_1rhs": (Uin, lq.F32, lq.LINKS12, 1),
+            f"fp32_12_{nrhs}rhs": (Uin, lq.F32, lq.LINKS12, nrhs)}.items():
+        cd = torch.complex128 if prec == lq.F64 else torch.complex64
+        x = torch.randn(n, 3, g.Vh, dtype=cd, device="cuda")
+        y = torch.empty_like(x)
+        ms = event_time_ms(lambda: lq.doe(g, Ul, x, out=y), 20)
+        byts = g.Vh * dslash_bytes_per_site(prec, fmt, n)
+        gbs = byts / (ms * 1e-3) / 1e9
+        flops = 570.0 * g.Vh * n
+        dsl[name] = dict(us=1000 * ms, GBps=gbs, frac_hbm_peak=gbs / HBM_PEAK_GBS,
+                         frac_stream_copy=gbs / copy_gbs, GFLOPs=flops / (ms * 1e-3) / 1e9)
+        del x, y
+    dkey = f"fp32_12_{nrhs}rhs"
+    roof = {
+        "kernel": f"k_dslash<float,6,B,DM_PLAIN> (D_oe, FP32 12-real, {nrhs} RHS, tuned B)",
+        "bound": "hbm",
+        "achieved": dsl[dkey]["GBps"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": dsl[dkey]["GBps"] / HBM_PEAK_GBS,
+        "traffic": None,
+        "algorithmic_bytes_per_launch": g.Vh * dslash_bytes_per_site(lq.F32, lq.LINKS12, nrhs),
+        "avg_launch_us": dsl[dkey]["us"],
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(w, U, phi, sig, int(round(np.mean(iters))))
+
+    mixed_solve = float(np.median(solve_times))
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "shift-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded; see DESIGN.md input recipe)",
+        "config": {"workload": w["name"], "lattice": list(L), "nrhs": nrhs, "nshift": nshift,
+                   "mass": w["mass"], "tol": 1e-10, "inner": "fp32 12-real",
+                   "reliable_interval": 100, "reliable_delta": 1e-3},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "time_to_1e10": {
+            "mixed_batched_s": mixed_solve,
+            "fp64_sequential_s": fp64["seconds"] if fp64 else None,
+            "speedup_mixed_vs_fp64": (fp64["seconds"] / mixed_solve) if fp64 else None,
+            "action_plus_force_s": float(np.median(force_times)),
+        },
+        "solver": {"iters_per_rhs": iters, "reliable_updates_per_rhs": rel,
+                   "refine_iters_total": refine, "max_true_rel_residual": max_tr,
+                   "all_converged": all_conv,
+                   "fp64_iters_per_rhs": fp64["iters"] if fp64 else None,
+                   "fp64_max_true_rel_residual": fp64["max_true_residual"] if fp64 else None},
+        "dslash": dsl,
+        "stream": {"copy_GBps": copy_gbs, "triad_GBps": triad_gbs},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

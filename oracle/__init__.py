@@ -58,7 +58,8 @@ def _load():
                            _dp, ctypes.c_double, ctypes.c_int, _ip, _dp]
     lib.orc_cg.restype = ctypes.c_int
     lib.orc_cg_multishift.argtypes = [_ip, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int,
-                                      _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp]
+                                      _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp,
+                                      ctypes.c_int]
     lib.orc_cg_multishift.restype = ctypes.c_int
     lib.orc_action.argtypes = [_ip, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
     lib.orc_action.restype = ctypes.c_double
@@ -154,8 +155,12 @@ def cg(L, U, mass, sigma, b, tol=1e-10, max_iter=10000, x0=None, antiperiodic=Tr
     return x, int(st), int(it.value), float(tr.value)
 
 
-def cg_multishift(L, U, mass, sigmas, b, tol=1e-10, max_iter=10000, antiperiodic=True):
-    """Returns (x [nshift][V][3], status, (ms_iters, refine_iters), true_res [nshift])."""
+def cg_multishift(L, U, mass, sigmas, b, tol=1e-10, max_iter=10000, antiperiodic=True,
+                  verify=True):
+    """Returns (x [nshift][V][3], status, (ms_iters, refine_iters), true_res [nshift]).
+
+    verify=False skips the final per-shift residual recomputation and CG
+    refinement (true_res is then NaN)."""
     V = _V(L)
     U = _c128(U, (4, V, 3, 3))
     b = _c128(b, (V, 3))
@@ -166,7 +171,7 @@ def cg_multishift(L, U, mass, sigmas, b, tol=1e-10, max_iter=10000, antiperiodic
     tr = np.zeros(ns, np.float64)
     st = _load().orc_cg_multishift(_geom(L), int(antiperiodic), _ptr(U), float(mass) ** 2, ns,
                                    _ptr(sig), _ptr(b), _ptr(x), float(tol), int(max_iter),
-                                   iters, _ptr(tr))
+                                   iters, _ptr(tr), 1 if verify else 0)
     return x, int(st), (int(iters[0]), int(iters[1])), tr
 
 

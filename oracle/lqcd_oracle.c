@@ -282,8 +282,10 @@ int orc_cg(const int *L, int anti, const double *Ud, double m2, double sigma,
  *   a_s = a zeta_s'/zeta_s,   b_s = b (zeta_s'/zeta_s)^2,
  *   x_s += a_s p_s,           p_s = zeta_s' r + b_s p_s.
  * A shift stops updating once |zeta_s'| ||r|| <= tol ||b||; the iteration stops
- * when the base shift converges.  Any shift whose recomputed residual is above
- * tol is then finished by plain CG started from its multi-shift solution.
+ * when the base shift converges.  With verify != 0, any shift whose recomputed
+ * residual is above tol is then finished by plain CG started from its
+ * multi-shift solution; with verify == 0 that last step (and the residual
+ * recomputation) is skipped and true_res is left as NaN.
  *
  * x is [nshift][V][3]; iters_out receives the multi-shift iteration count
  * (plus refinement iterations in iters_out[1]); true_res is [nshift].
@@ -291,7 +293,7 @@ int orc_cg(const int *L, int anti, const double *Ud, double m2, double sigma,
 int orc_cg_multishift(const int *L, int anti, const double *Ud, double m2,
                       int nshift, const double *sigma, const double *bd,
                       double *xd, double tol, int max_iter, int *iters_out,
-                      double *true_res)
+                      double *true_res, int verify)
 {
     const long V = volume_of(L);
     const long n = V * 3;
@@ -359,7 +361,8 @@ int orc_cg_multishift(const int *L, int anti, const double *Ud, double m2,
     iters_out[0] = it;
     iters_out[1] = 0;
     int status = 0;
-    for (int k = 0; k < nshift; ++k) {
+    for (int k = 0; k < nshift && !verify; ++k) true_res[k] = NAN;
+    for (int k = 0; k < nshift && verify; ++k) {
         double tr = orc_true_residual(L, anti, Ud, m2, sigma[k], bd, (const double *)(x + k * n));
         if (tr > tol) {
             int extra = 0;

@@ -47,6 +47,8 @@ struct DslashCfg {
   int block = 256;  // threads per workgroup (64, 128, 256)
   int rhs_block = 1;  // right-hand sides sharing one link load (1, 2, 4, 8)
   int xcd = 1;      // XCD-contiguous block remap
+  int tz = 0;       // site traversal: 0 lexicographic; n > 0 walks z in tiles of n
+                    // with t inside the tile loop (shorter +-t reuse distance)
 };
 
 // Number of workgroups along the site dimension for a configuration.

@@ -31,8 +31,25 @@ namespace lqcd {
 
 namespace {
 
+// Half index of the i-th site visited.  tz = 0: lexicographic (i = h).
+// tz > 0: x, y fastest, then z inside a tile of tz slices, then t, then the
+// z tile -- consecutive workgroups sweep t inside a thin z slab, so an input
+// site is reused as a +-t neighbour while still in L2.  Within a (z, t) plane
+// sites stay contiguous, so loads remain coalesced.
+__device__ __forceinline__ int site_of(const KGeom& g, int i, int tz) {
+  if (tz == 0) return i;
+  const int xy = g.Lxh * g.Ly;
+  const int inplane = i % xy;
+  int r = i / xy;
+  const int zi = r % tz;
+  r /= tz;
+  const int t = r % g.Lt;
+  const int z = (r / g.Lt) * tz + zi;
+  return inplane + xy * (z + g.Lz * t);
+}
+
 template <typename R, int NE, int B, int MODE, typename RO>
-__global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xcd) {
+__global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xcd, const int tz) {
   __shared__ double lds[B][4];
   if (a.halt && *a.halt) return;
   const KGeom& g = a.g;
@@ -48,7 +65,8 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
   if (!any) return;  // uniform over the block
 
   const int blk = xcd_block(blockIdx.x, gridDim.x, xcd);
-  const int h = blk * blockDim.x + threadIdx.x;
+  const int idx = blk * blockDim.x + threadIdx.x;
+  const int h = idx < a.g.Vh ? site_of(a.g, idx, tz) : idx;
   double nrm[B];
 #pragma unroll
   for (int b = 0; b < B; ++b) nrm[b] = 0.0;
@@ -179,7 +197,8 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
 template <typename R, int NE, int B, int MODE, typename RO>
 int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
   const dim3 grid(dslash_nblocks(c.g, cfg), (c.nrhs + B - 1) / B);
-  hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO>), grid, dim3(cfg.block), 0, st, c, cfg.xcd);
+  hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO>), grid, dim3(cfg.block), 0, st, c, cfg.xcd,
+                     cfg.tz);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
@@ -214,6 +233,10 @@ int launch_mode(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
 int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
   if (cfg.block != 64 && cfg.block != 128 && cfg.block != 256) {
     set_error("unsupported dslash block size %d", cfg.block);
+    return LQCD_ERR_UNSUPPORTED;
+  }
+  if (cfg.tz < 0 || (cfg.tz > 0 && c.g.Lz % cfg.tz != 0)) {
+    set_error("z tile %d must divide Lz = %d", cfg.tz, c.g.Lz);
     return LQCD_ERR_UNSUPPORTED;
   }
   if (c.mode == DM_RES) {
@@ -282,6 +305,15 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     }
   }
   DslashCfg best = default_cfg(c.nrhs, forced);
+  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz" pins the configuration (testing, profiling)
+  if (const char* e = std::getenv("LQCD_DSLASH_CFG")) {
+    DslashCfg f;
+    if (std::sscanf(e, "%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz) == 4) {
+      if (forced) f.rhs_block = forced;
+      *out = f;
+      return LQCD_OK;
+    }
+  }
   if (!tuning_enabled()) {
     *out = best;
     return LQCD_OK;
@@ -293,7 +325,11 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   for (int blk : {64, 128, 256})
     for (int b : {1, 2, 4, 8}) {
       if (forced ? b != forced : b > c.nrhs) continue;
-      for (int x : {0, 1}) cand.push_back(DslashCfg{blk, b, x});
+      for (int x : {0, 1})
+        for (int tz : {0, 2, 4, 8}) {
+          if (tz && (c.g.Lz % tz || tz >= c.g.Lz)) continue;
+          cand.push_back(DslashCfg{blk, b, x, tz});
+        }
     }
 
   const size_t vec = size_t(3) * c.g.Vh * 2 * (c.prec == LQCD_F32 ? 4 : 8);
@@ -337,9 +373,11 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
     if (tuning_verbose())
-      fprintf(stderr, "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d block=%d B=%d xcd=%d: %.2f us\n",
+      fprintf(stderr,
+              "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d block=%d B=%d xcd=%d tz=%d: "
+              "%.2f us\n",
               c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, cfg.block, cfg.rhs_block,
-              cfg.xcd, 1000.0 * ms / kReps);
+              cfg.xcd, cfg.tz, 1000.0 * ms / kReps);
     if (ms < best_ms) {
       best_ms = ms;
       best = cfg;

@@ -168,3 +168,24 @@ def test_hop_24_vs_oracle(lq, prec, fmt, tol):
     ev = lq.pack_spinor(g, cu(f[None]), 0, prec)
     got = host(lq.unpack_spinor(g, lq.doe(g, Up, ev), 1))[0]
     assert H.max_rel(got, oracle.doe(L, U, f)) <= tol
+
+
+@pytest.mark.parametrize("cfg", ["64,1,0,0", "128,2,1,2", "256,4,1,4", "64,8,0,2", "256,8,1,0",
+                                 "128,1,1,4"])
+@pytest.mark.parametrize("prec,fmt,tol", [(0, 0, 1e-13), (1, 1, 1e-6)])
+def test_every_launch_configuration(lq, cfg, prec, fmt, tol, monkeypatch):
+    """Each (workgroup, RHS block, XCD remap, z-tiled traversal) variant the
+    tuner may pick gives the oracle's result; ragged RHS count and a lattice
+    whose site count is not a multiple of the workgroup."""
+    monkeypatch.setenv("LQCD_DSLASH_CFG", cfg)
+    L = (6, 4, 8, 6)
+    g = lq.Geometry(L)
+    U = _links(L, "haar", 18)
+    f = synth.gaussian_field(L, 5, 19)
+    Up = lq.pack_links(g, cu(U), prec, fmt)
+    got = host(lq.unpack_spinor(g, lq.doe(g, Up, lq.pack_spinor(g, cu(f), 0, prec)), 1))
+    ref = np.stack([oracle.doe(L, U, f[j]) for j in range(5)])
+    assert H.max_rel(got, ref) <= tol
+    got = host(lq.unpack_spinor(g, lq.deo(g, Up, lq.pack_spinor(g, cu(f), 1, prec)), 0))
+    ref = np.stack([oracle.deo(L, U, f[j]) for j in range(5)])
+    assert H.max_rel(got, ref) <= tol
