@@ -287,7 +287,7 @@ def main():
         "data": "synthetic (seeded; see DESIGN.md input recipe)",
         "config": {"workload": w["name"], "lattice": list(L), "nrhs": nrhs, "nshift": nshift,
                    "mass": w["mass"], "tol": 1e-10, "inner": "fp32 12-real",
-                   "reliable_interval": 100, "reliable_delta": 1e-3},
+                   "reliable_interval": 100, "reliable_delta": 1e-3, "mixed_switch": 1e-3},
         "roofline": roof,
         "cpu_baseline": cpu,
         "time_to_1e10": {

@@ -164,6 +164,8 @@ typedef struct {
     int32_t poll_interval;     /* iterations between host convergence checks, 0 = auto */
     int32_t max_refine;        /* rounds of per-shift refinement allowed, >= 0       */
     double reliable_delta;     /* mixed: also update when |r| fell by this factor    */
+    double mixed_switch;       /* mixed multi-shift: iterate in FP64 until |r| <=
+                                  mixed_switch |b|, then in FP32 (0: FP32 throughout) */
 } lqcd_solver_params;
 
 typedef struct {
@@ -177,7 +179,7 @@ typedef struct {
 
 /* Fills p with defaults: tol 1e-10, max_iter 10000, F64 inner, LINKS18,
  * reliable_interval 100, use_graph 1, rhs_block 0, poll 0, max_refine 3,
- * reliable_delta 1e-3. */
+ * reliable_delta 1e-3, mixed_switch 1e-3. */
 void lqcd_solver_params_default(lqcd_solver_params *p);
 
 /* Device workspace that lqcd_cg / lqcd_cg_multishift need for these sizes. */
@@ -199,7 +201,10 @@ size_t lqcd_solver_workspace_bytes(const lqcd_geom *g, const lqcd_solver_params 
  * believes it has converged, the FP32 correction is added into the FP64
  * solution and the residual is recomputed in FP64 (Sec. 6: the production
  * split, single precision for MD and double for the accept step).
- * Dot products, norms and the CG scalars are always FP64.
+ * Dot products, norms and the CG scalars are always FP64.  A mixed multi-shift
+ * solve first iterates in FP64 until the base residual is below mixed_switch
+ * |b|: FP32 rounding then only perturbs the shifted systems at that scale,
+ * which keeps their final refinement short.
  * Returns LQCD_ERR_NOT_CONVERGED if any system misses tol within max_iter
  * (x holds the best iterate, stats are filled).
  */

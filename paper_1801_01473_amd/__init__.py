@@ -58,6 +58,7 @@ class SolverParams(ctypes.Structure):
         ("reliable_interval", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("rhs_block", ctypes.c_int32), ("poll_interval", ctypes.c_int32),
         ("max_refine", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
+        ("mixed_switch", ctypes.c_double),
     ]
 
 

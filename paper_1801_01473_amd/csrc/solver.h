@@ -29,7 +29,7 @@ struct alignas(16) SysState {
   int conv;        // converged on the FP64 recomputed residual
   int err;         // non-finite or non-positive curvature seen
   int restart;     // directions are rebuilt from the recomputed residual
-  int pad_;
+  int lowres;      // residual below the FP64 -> FP32 switch level
   double zeta[kMaxShift], zeta_old[kMaxShift], zeta_new[kMaxShift];
   double a_s[kMaxShift], b_s[kMaxShift], delta[kMaxShift];
   int active[kMaxShift];  // shift still iterating
@@ -42,8 +42,8 @@ static_assert(sizeof(SysState) % 8 == 0, "state stride must be a whole number of
 struct alignas(16) GlobalFlags {
   int all_done;
   int error;
-  int rel_req;  // some system's residual fell by the reliable-update factor
-  int pad;
+  int rel_req;     // some system's residual fell by the reliable-update factor
+  int phase_done;  // every system is below the switch level or done
 };
 
 constexpr int kStateStrideD = int(sizeof(SysState) / sizeof(double));

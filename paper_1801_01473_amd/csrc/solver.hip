@@ -146,10 +146,10 @@ __global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restr
 // params = [m2s per system][delta per (system, shift)]
 __global__ void __launch_bounds__(kScalarThreads) k_sc_init(
     SysState* __restrict__ st, GlobalFlags* __restrict__ gf, int nsys, int nshift,
-    const double* __restrict__ params, double tol2, const double* part_b, int nb_b,
+    const double* __restrict__ params, double tol2, double sw2, const double* part_b, int nb_b,
     const double* part_r, int nb_r, const double* part_p, int nb_p) {
   __shared__ double lds[kScalarThreads / 64];
-  int all_done = 1, err = 0;
+  int all_done = 1, err = 0, phase_done = 1;
   for (int j = 0; j < nsys; ++j) {
     const double bn = wg_sum(part_b + int64_t(j) * nb_b, nb_b, lds);
     const double rr = wg_sum(part_r + int64_t(j) * nb_r, nb_r, lds);
@@ -183,7 +183,9 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_init(
       S.conv = rr <= S.target2 ? 1 : 0;
       S.done = (S.conv || S.err) ? 1 : 0;
       S.live = !S.done;
+      S.lowres = rr <= sw2 * bn ? 1 : 0;
       all_done &= S.done;
+      phase_done &= (S.done | S.lowres);
       err |= S.err;
     }
   }
@@ -191,97 +193,105 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_init(
     gf->all_done = all_done;
     gf->error = err;
     gf->rel_req = 0;
+    gf->phase_done = phase_done;
   }
 }
 
-// K2: step length of the base system and the shifted zetas
+// K2: step length of the base system and the shifted zetas; one workgroup
+// per system (blockIdx.x), each reducing its own partials in fixed order.
 __global__ void __launch_bounds__(kScalarThreads) k_sc_alpha(SysState* __restrict__ st,
                                                               GlobalFlags* __restrict__ gf,
-                                                              int nsys, int nshift,
-                                                              const double* part_t, int nb_t,
-                                                              const double* part_p, int nb_p) {
+                                                              int nshift, const double* part_t,
+                                                              int nb_t, const double* part_p,
+                                                              int nb_p) {
   __shared__ double lds[kScalarThreads / 64];
-  for (int j = 0; j < nsys; ++j) {
-    const double tt = wg_sum(part_t + int64_t(j) * nb_t, nb_t, lds);
-    const double pp = wg_sum(part_p + int64_t(j) * nb_p, nb_p, lds);
-    if (threadIdx.x != 0) continue;
-    SysState& S = st[j];
+  const int j = blockIdx.x;
+  const double tt = wg_sum(part_t + int64_t(j) * nb_t, nb_t, lds);
+  const double pp = wg_sum(part_p + int64_t(j) * nb_p, nb_p, lds);
+  if (threadIdx.x != 0) return;
+  SysState& S = st[j];
+  S.upd_any = 0;
+  S.restart = 0;
+  for (int s = 0; s < nshift; ++s) S.upd[s] = 0;
+  if (S.done) return;
+  const double pAp = S.m2s * pp + tt;  // <p, (m2s - D_eo D_oe) p>
+  S.pp = pp;
+  if (!(pAp > 0.0) || !finite_d(pAp)) {
+    S.err = 1;
+    S.done = 1;
+    S.live = 0;
+    gf->error = 1;
+    return;
+  }
+  const double a = S.rho / pAp;
+  S.a = a;
+  for (int s = 0; s < nshift; ++s) {
+    if (!S.active[s]) continue;
+    const double z = S.zeta[s], zo = S.zeta_old[s];
+    const double zn =
+        z * zo * S.a_old / (a * S.b_old * (zo - z) + zo * S.a_old * (1.0 + S.delta[s] * a));
+    S.zeta_new[s] = zn;
+    S.a_s[s] = a * zn / z;
+    S.upd[s] = 1;
+  }
+  S.upd_any = 1;
+}
+
+// K4: beta, shifted betas, freezing, convergence; one workgroup per system.
+// The global flags are derived afterwards by k_sc_flags.
+__global__ void __launch_bounds__(kScalarThreads) k_sc_beta(SysState* __restrict__ st,
+                                                             GlobalFlags* __restrict__ gf,
+                                                             int nshift, const double* part_r,
+                                                             int nb_r, int max_iter,
+                                                             double rel_delta2, double sw2) {
+  __shared__ double lds[kScalarThreads / 64];
+  const int j = blockIdx.x;
+  const double rr = wg_sum(part_r + int64_t(j) * nb_r, nb_r, lds);
+  if (threadIdx.x != 0) return;
+  SysState& S = st[j];
+  if (!S.upd_any) return;
+  if (!finite_d(rr)) {
+    S.err = 1;
+    S.done = 1;
+    S.live = 0;
     S.upd_any = 0;
-    S.restart = 0;
-    for (int s = 0; s < nshift; ++s) S.upd[s] = 0;
-    if (S.done) continue;
-    const double pAp = S.m2s * pp + tt;  // <p, (m2s - D_eo D_oe) p>
-    S.pp = pp;
-    if (!(pAp > 0.0) || !finite_d(pAp)) {
-      S.err = 1;
-      S.done = 1;
-      S.live = 0;
-      gf->error = 1;
-      continue;
-    }
-    const double a = S.rho / pAp;
-    S.a = a;
-    for (int s = 0; s < nshift; ++s) {
-      if (!S.active[s]) continue;
-      const double z = S.zeta[s], zo = S.zeta_old[s];
-      const double zn =
-          z * zo * S.a_old / (a * S.b_old * (zo - z) + zo * S.a_old * (1.0 + S.delta[s] * a));
-      S.zeta_new[s] = zn;
-      S.a_s[s] = a * zn / z;
-      S.upd[s] = 1;
-    }
-    S.upd_any = 1;
+    gf->error = 1;
+    return;
+  }
+  const double beta = rr / S.rho;
+  for (int s = 0; s < nshift; ++s) {
+    if (!S.upd[s]) continue;
+    const double ratio = S.zeta_new[s] / S.zeta[s];
+    S.b_s[s] = beta * ratio * ratio;
+    S.zeta_old[s] = S.zeta[s];
+    S.zeta[s] = S.zeta_new[s];
+    S.dirty[s] = 1;
+    if (S.zeta_new[s] * S.zeta_new[s] * rr <= S.target2) S.active[s] = 0;
+  }
+  S.a_old = S.a;
+  S.b_old = beta;
+  S.rho = rr;
+  S.iters += 1;
+  if (rr < rel_delta2 * S.r2ref) gf->rel_req = 1;
+  if (rr <= sw2 * S.bnorm2) S.lowres = 1;
+  if (rr <= S.target2 || S.iters >= max_iter) {
+    S.done = 1;
+    S.live = 0;
+    S.conv = rr <= S.target2 ? 1 : 0;
   }
 }
 
-// K4: beta, shifted betas, freezing, convergence
-__global__ void __launch_bounds__(kScalarThreads) k_sc_beta(SysState* __restrict__ st,
-                                                             GlobalFlags* __restrict__ gf,
-                                                             int nsys, int nshift,
-                                                             const double* part_r, int nb_r,
-                                                             int max_iter, double rel_delta2) {
-  __shared__ double lds[kScalarThreads / 64];
-  int all_done = 1, rel_req = 0;
+// all_done / phase_done over every system
+__global__ void k_sc_flags(const SysState* __restrict__ st, GlobalFlags* __restrict__ gf,
+                           int nsys) {
+  if (threadIdx.x != 0) return;
+  int all_done = 1, phase_done = 1;
   for (int j = 0; j < nsys; ++j) {
-    const double rr = wg_sum(part_r + int64_t(j) * nb_r, nb_r, lds);
-    if (threadIdx.x != 0) continue;
-    SysState& S = st[j];
-    if (S.upd_any) {
-      if (!finite_d(rr)) {
-        S.err = 1;
-        S.done = 1;
-        S.live = 0;
-        S.upd_any = 0;
-        gf->error = 1;
-      } else {
-        const double beta = rr / S.rho;
-        for (int s = 0; s < nshift; ++s) {
-          if (!S.upd[s]) continue;
-          const double ratio = S.zeta_new[s] / S.zeta[s];
-          S.b_s[s] = beta * ratio * ratio;
-          S.zeta_old[s] = S.zeta[s];
-          S.zeta[s] = S.zeta_new[s];
-          S.dirty[s] = 1;
-          if (S.zeta_new[s] * S.zeta_new[s] * rr <= S.target2) S.active[s] = 0;
-        }
-        S.a_old = S.a;
-        S.b_old = beta;
-        S.rho = rr;
-        S.iters += 1;
-        if (rr < rel_delta2 * S.r2ref) rel_req = 1;
-        if (rr <= S.target2 || S.iters >= max_iter) {
-          S.done = 1;
-          S.live = 0;
-          S.conv = rr <= S.target2 ? 1 : 0;
-        }
-      }
-    }
-    all_done &= S.done;
+    all_done &= st[j].done;
+    phase_done &= (st[j].done | st[j].lowres);
   }
-  if (threadIdx.x == 0) {
-    gf->all_done = all_done;
-    if (rel_req) gf->rel_req = 1;
-  }
+  gf->all_done = all_done;
+  gf->phase_done = phase_done;
 }
 
 // K5: x_s += a_s p_s ; p_s = zeta_s r + beta_s p_s for the shifts updated this iteration
@@ -439,6 +449,46 @@ __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __re
   if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = pn;
 }
 
+// FP64 Krylov state -> FP32: r, every shift's p; x_lo = 0; partials of |p_base|^2
+__global__ void __launch_bounds__(kVecBlock) k_to_fp32(const double2* __restrict__ r64,
+                                                       const double2* __restrict__ p64,
+                                                       float2* __restrict__ r32,
+                                                       float2* __restrict__ p32,
+                                                       float2* __restrict__ xlo, int nshift,
+                                                       int base, int Vh,
+                                                       double* __restrict__ part) {
+  __shared__ double lds[kVecBlock / 64];
+  const int j = blockIdx.y;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  double pn = 0.0;
+  if (h < Vh) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t ir = (int64_t(j) * 3 + c) * Vh + h;
+      r32[ir] = make_float2(float(r64[ir].x), float(r64[ir].y));
+      for (int s = 0; s < nshift; ++s) {
+        const int64_t i = ((int64_t(j) * nshift + s) * 3 + c) * Vh + h;
+        const float2 pv = make_float2(float(p64[i].x), float(p64[i].y));
+        p32[i] = pv;
+        xlo[i] = make_float2(0.f, 0.f);
+        if (s == base) pn += cnorm2<float>(pv);
+      }
+    }
+  }
+  pn = block_sum(pn, lds);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = pn;
+}
+
+// After the FP64 phase: the FP64 solutions are current, the next reliable
+// update is measured from here.
+__global__ void k_sc_phase2(SysState* __restrict__ st, int nsys, int nshift) {
+  if (threadIdx.x != 0) return;
+  for (int j = 0; j < nsys; ++j) {
+    st[j].r2ref = st[j].rho;
+    for (int s = 0; s < nshift; ++s) st[j].dirty[s] = 0;
+  }
+}
+
 // out[v] = sum_b part[v][b], fixed order, one workgroup per vector
 __global__ void __launch_bounds__(kVecBlock) k_reduce_vec(const double* __restrict__ part, int nb,
                                                           double* __restrict__ out) {
@@ -455,12 +505,17 @@ __global__ void __launch_bounds__(kVecBlock) k_reduce_vec(const double* __restri
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t r, t, p, xlo, thi, bb, xb, st, gf, params, pt, pr, pp, pb, pres, resn, links, total;
-  bool has_xlo, has_links;
+  size_t r, t, p, xlo, r64, t64, p64, thi, bb, xb, st, gf, params, pt, pr, pp, pb, pres, resn,
+      links, links_pre, total;
+  bool has_xlo, has_pre, has_links;
 };
 
-Layout make_layout(const KGeom& g, int iprec, int ifmt, int nshift, int nrhs) {
+// Workspace layout.  Mixed precision keeps FP32 iteration vectors and FP32
+// partial solutions, plus FP64 iteration vectors for the FP64 opening phase
+// when mixed_switch > 0.
+Layout make_layout(const KGeom& g, const lqcd_solver_params& p, int nshift, int nrhs) {
   Layout L{};
+  const int iprec = p.inner_prec, ifmt = p.inner_fmt;
   const size_t ri = iprec == LQCD_F32 ? 4 : 8;
   const size_t vin = size_t(3) * g.Vh * 2 * ri;
   const size_t v64 = size_t(3) * g.Vh * 16;
@@ -476,6 +531,10 @@ Layout make_layout(const KGeom& g, int iprec, int ifmt, int nshift, int nrhs) {
   L.p = take(size_t(nrhs) * nshift * vin);
   L.has_xlo = iprec == LQCD_F32;
   L.xlo = L.has_xlo ? take(size_t(nrhs) * nshift * vin) : 0;
+  L.has_pre = iprec == LQCD_F32 && p.mixed_switch > 0.0 && nshift > 1;
+  L.r64 = L.has_pre ? take(nrhs * v64) : 0;
+  L.t64 = L.has_pre ? take(nrhs * v64) : 0;
+  L.p64 = L.has_pre ? take(size_t(nrhs) * nshift * v64) : 0;
   L.thi = take(nrhs * v64);
   L.bb = take(nrhs * v64);
   L.xb = take(nrhs * v64);
@@ -490,14 +549,17 @@ Layout make_layout(const KGeom& g, int iprec, int ifmt, int nshift, int nrhs) {
   L.resn = take(size_t(nrhs) * nshift * 8);
   L.has_links = !(iprec == LQCD_F64 && ifmt == LQCD_LINKS18);
   L.links = L.has_links ? take(size_t(8) * link_elems(ifmt) * g.Vh * 2 * ri) : 0;
+  // the FP64 opening phase streams FP64 links in the inner format (12-real:
+  // a third fewer link bytes than the 18-real copy used for residuals)
+  L.links_pre = (L.has_pre && ifmt == LQCD_LINKS12) ? take(size_t(8) * 6 * g.Vh * 16) : 0;
   L.total = off;
   return L;
 }
 
-// Process-wide resources: pinned host staging, capture stream, graph cache.
 // Pinned staging: [0, kPinnedParams) receives the flag word, parameters follow.
 constexpr size_t kPinnedParams = 256;
 
+// Process-wide resources: pinned host staging, capture stream, graph cache.
 struct Global {
   std::mutex mu;
   void* pinned = nullptr;
@@ -537,24 +599,37 @@ struct Ctx {
   char* ws;
   Layout L;
   hipStream_t s;
-  int nrhs_max;
   double m2;
-  double rel_delta;  // reliable update when |r| fell by this factor
   template <typename T>
   T* at(size_t off) const {
     return reinterpret_cast<T*>(ws + off);
   }
 };
 
-// One run of the Krylov iteration on nsys independent systems.
+// One way of running the Krylov iteration: its arithmetic, links, vectors and
+// stencil configurations.
+struct Phase {
+  int prec = LQCD_F64, fmt = LQCD_LINKS18;
+  const void* U = nullptr;
+  size_t r = 0, t = 0, p = 0;  // workspace offsets of r, t (odd), p_s
+  void* x = nullptr;           // solution accumulator: FP64 solutions or FP32 partial sums
+  DslashCfg c_oe, c_eo;
+  int nb_oe = 0, nb_eo = 0;
+  double rel_d2 = 0.0;  // reliable-update trigger (0: never)
+  double sw2 = 0.0;     // FP64 -> FP32 switch level (0: never)
+};
+
+// One run of the iteration on nsys independent systems.
 struct Core {
   int nsys, nshift, base;
   bool guess;
   const double2* b;  // [nsys][3][Vh] FP64
   double2* x;        // [nsys][nshift][3][Vh] FP64
   double tol;
-  DslashCfg c_oe, c_eo, c64_oe, c64_eo;
-  int nb_oe, nb_eo, nb64_eo, nbv;
+  Phase main, pre;   // pre: FP64 opening phase of a mixed multi-shift solve
+  bool two_phase;
+  DslashCfg c64_oe, c64_eo;  // FP64 18-real: residuals and verification
+  int nb64_eo, nbv;
   int poll;
 };
 
@@ -562,14 +637,20 @@ bool is_mixed(const Ctx& c) { return c.iprec == LQCD_F32; }
 
 int64_t vstride(const Ctx& c) { return int64_t(3) * c.g.Vh; }
 
-DslashCall inner_call(const Ctx& c, const Core& k, int out_par) {
+size_t cbytes(int prec) { return prec == LQCD_F32 ? 8 : 16; }  // bytes per complex
+
+char* vec_at(const Ctx& c, size_t off, int prec, int64_t index) {
+  return c.ws + off + size_t(index) * vstride(c) * cbytes(prec);
+}
+
+DslashCall phase_call(const Ctx& c, const Core& k, const Phase& ph, int out_par) {
   DslashCall d;
   d.g = c.g;
   d.out_par = out_par;
-  d.prec = c.iprec;
-  d.fmt = c.ifmt;
+  d.prec = ph.prec;
+  d.fmt = ph.fmt;
   d.nrhs = k.nsys;
-  d.U = c.Uin;
+  d.U = ph.U;
   return d;
 }
 
@@ -584,41 +665,35 @@ DslashCall fp64_call(const Ctx& c, const Core& k, int out_par) {
   return d;
 }
 
-size_t inner_real(const Ctx& c) { return c.iprec == LQCD_F32 ? 8 : 16; }  // bytes per complex
-
-char* inner_vec(const Ctx& c, size_t off, int64_t index) {
-  return c.ws + off + size_t(index) * vstride(c) * inner_real(c);
-}
-
-int launch_iteration(const Ctx& c, const Core& k, hipStream_t s) {
+int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s) {
   SysState* st = c.at<SysState>(c.L.st);
   GlobalFlags* gf = c.at<GlobalFlags>(c.L.gf);
   const int64_t vs = vstride(c);
   int rc;
   // K1: t = D_oe p_base
-  DslashCall d1 = inner_call(c, k, 1);
+  DslashCall d1 = phase_call(c, k, ph, 1);
   d1.mode = DM_PLAIN;
-  d1.in = inner_vec(c, c.L.p, k.base);
+  d1.in = vec_at(c, ph.p, ph.prec, k.base);
   d1.in_stride = int64_t(k.nshift) * vs;
-  d1.out = c.ws + c.L.t;
+  d1.out = c.ws + ph.t;
   d1.out_stride = vs;
   d1.live = &st->live;
   d1.live_stride = kStateStrideI;
   d1.halt = &gf->all_done;
   d1.partials = c.at<double>(c.L.pt);
-  if ((rc = dslash_launch(d1, k.c_oe, s))) return rc;
+  if ((rc = dslash_launch(d1, ph.c_oe, s))) return rc;
   // K2
-  hipLaunchKernelGGL(k_sc_alpha, dim3(1), dim3(kScalarThreads), 0, s, st, gf, k.nsys, k.nshift,
-                     c.at<double>(c.L.pt), k.nb_oe, c.at<double>(c.L.pp), k.nbv);
+  hipLaunchKernelGGL(k_sc_alpha, dim3(k.nsys), dim3(kScalarThreads), 0, s, st, gf, k.nshift,
+                     c.at<double>(c.L.pt), ph.nb_oe, c.at<double>(c.L.pp), k.nbv);
   LQCD_LAUNCH_CHECK();
   // K3: r -= a (m2s p - D_eo t)
-  DslashCall d3 = inner_call(c, k, 0);
+  DslashCall d3 = phase_call(c, k, ph, 0);
   d3.mode = DM_CG;
-  d3.in = c.ws + c.L.t;
+  d3.in = c.ws + ph.t;
   d3.in_stride = vs;
-  d3.diag = inner_vec(c, c.L.p, k.base);
+  d3.diag = vec_at(c, ph.p, ph.prec, k.base);
   d3.diag_stride = int64_t(k.nshift) * vs;
-  d3.r = c.ws + c.L.r;
+  d3.r = c.ws + ph.r;
   d3.r_stride = vs;
   d3.m2s = &st->m2s;
   d3.m2s_stride = kStateStrideD;
@@ -628,27 +703,28 @@ int launch_iteration(const Ctx& c, const Core& k, hipStream_t s) {
   d3.live_stride = kStateStrideI;
   d3.halt = &gf->all_done;
   d3.partials = c.at<double>(c.L.pr);
-  if ((rc = dslash_launch(d3, k.c_eo, s))) return rc;
+  if ((rc = dslash_launch(d3, ph.c_eo, s))) return rc;
   // K4
-  const double d2 = is_mixed(c) ? c.rel_delta * c.rel_delta : 0.0;
-  hipLaunchKernelGGL(k_sc_beta, dim3(1), dim3(kScalarThreads), 0, s, st, gf, k.nsys, k.nshift,
-                     c.at<double>(c.L.pr), k.nb_eo, c.p.max_iter, d2);
+  hipLaunchKernelGGL(k_sc_beta, dim3(k.nsys), dim3(kScalarThreads), 0, s, st, gf, k.nshift,
+                     c.at<double>(c.L.pr), ph.nb_eo, c.p.max_iter, ph.rel_d2, ph.sw2);
+  LQCD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_sc_flags, dim3(1), dim3(64), 0, s, st, gf, k.nsys);
   LQCD_LAUNCH_CHECK();
   // K5
   const dim3 grid(k.nbv, k.nsys);
-  if (is_mixed(c))
+  if (ph.prec == LQCD_F32)
     hipLaunchKernelGGL((k_ms_update<float, float>), grid, dim3(kVecBlock), 0, s, st,
-                       c.at<const float2>(c.L.r), c.at<float2>(c.L.p), c.at<float2>(c.L.xlo),
-                       k.nshift, k.base, c.g.Vh, c.at<double>(c.L.pp));
+                       c.at<const float2>(ph.r), c.at<float2>(ph.p), (float2*)ph.x, k.nshift,
+                       k.base, c.g.Vh, c.at<double>(c.L.pp));
   else
     hipLaunchKernelGGL((k_ms_update<double, double>), grid, dim3(kVecBlock), 0, s, st,
-                       c.at<const double2>(c.L.r), c.at<double2>(c.L.p), k.x, k.nshift, k.base,
-                       c.g.Vh, c.at<double>(c.L.pp));
+                       c.at<const double2>(ph.r), c.at<double2>(ph.p), (double2*)ph.x, k.nshift,
+                       k.base, c.g.Vh, c.at<double>(c.L.pp));
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
 
-// r = b - A_{sigma_0} x_base in FP64 (stored in inner precision), partials into part
+// r = b - A_{sigma_0} x_base in FP64 (stored in the main phase's precision)
 int launch_residual(const Ctx& c, const Core& k, const double* m2s, int m2s_stride,
                     const int* live, double* part, hipStream_t s) {
   const int64_t vs = vstride(c);
@@ -664,14 +740,14 @@ int launch_residual(const Ctx& c, const Core& k, const double* m2s, int m2s_stri
   if ((rc = dslash_launch(e1, k.c64_oe, s))) return rc;
   DslashCall e2 = fp64_call(c, k, 0);
   e2.mode = DM_RES;
-  e2.r_prec = c.iprec;
+  e2.r_prec = k.main.prec;
   e2.in = c.ws + c.L.thi;
   e2.in_stride = vs;
   e2.diag = k.x + int64_t(k.base) * vs;
   e2.diag_stride = int64_t(k.nshift) * vs;
   e2.b = k.b;
   e2.b_stride = vs;
-  e2.r = c.ws + c.L.r;
+  e2.r = c.ws + k.main.r;
   e2.r_stride = vs;
   e2.m2s = m2s;
   e2.m2s_stride = m2s_stride;
@@ -701,29 +777,35 @@ int launch_reliable(const Ctx& c, const Core& k, hipStream_t s) {
   return LQCD_OK;
 }
 
-std::string graph_key(const Ctx& c, const Core& k) {
+std::string graph_key(const Ctx& c, const Core& k, const Phase& ph) {
   std::string key;
   auto add = [&](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
   add(&c.g, sizeof(c.g));
-  add(&c.iprec, sizeof(int));
-  add(&c.ifmt, sizeof(int));
-  add(&c.Uin, sizeof(void*));
   add(&c.ws, sizeof(void*));
   add(&c.L.total, sizeof(size_t));
   add(&c.p.max_iter, sizeof(int));
   add(&k.nsys, sizeof(int));
   add(&k.nshift, sizeof(int));
   add(&k.base, sizeof(int));
-  add(&k.x, sizeof(void*));
-  add(&k.c_oe, sizeof(DslashCfg));
-  add(&k.c_eo, sizeof(DslashCfg));
+  add(&k.nbv, sizeof(int));
   add(&k.poll, sizeof(int));
+  add(&ph.prec, sizeof(int));
+  add(&ph.fmt, sizeof(int));
+  add(&ph.U, sizeof(void*));
+  add(&ph.r, sizeof(size_t));
+  add(&ph.t, sizeof(size_t));
+  add(&ph.p, sizeof(size_t));
+  add(&ph.x, sizeof(void*));
+  add(&ph.c_oe, sizeof(DslashCfg));
+  add(&ph.c_eo, sizeof(DslashCfg));
+  add(&ph.rel_d2, sizeof(double));
+  add(&ph.sw2, sizeof(double));
   return key;
 }
 
-int iteration_graph(const Ctx& c, const Core& k, hipGraphExec_t* out) {
+int iteration_graph(const Ctx& c, const Core& k, const Phase& ph, hipGraphExec_t* out) {
   Global& gl = G();
-  const std::string key = graph_key(c, k);
+  const std::string key = graph_key(c, k, ph);
   auto it = gl.graphs.find(key);
   if (it != gl.graphs.end()) {
     *out = it->second;
@@ -733,7 +815,7 @@ int iteration_graph(const Ctx& c, const Core& k, hipGraphExec_t* out) {
   if (!gl.cap) LQCD_HIP_TRY(hipStreamCreateWithFlags(&gl.cap, hipStreamNonBlocking));
   LQCD_HIP_TRY(hipStreamBeginCapture(gl.cap, hipStreamCaptureModeThreadLocal));
   int rc = LQCD_OK;
-  for (int i = 0; i < k.poll && rc == LQCD_OK; ++i) rc = launch_iteration(c, k, gl.cap);
+  for (int i = 0; i < k.poll && rc == LQCD_OK; ++i) rc = launch_iteration(c, k, ph, gl.cap);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(gl.cap, &graph);
   if (rc != LQCD_OK) {
@@ -765,15 +847,16 @@ bool debug_enabled() {
 void debug_dump(const Ctx& c, const Core& k, const char* where) {
   if (!debug_enabled()) return;
   std::vector<SysState> h(k.nsys);
-  if (hipMemcpy(h.data(), c.at<SysState>(c.L.st), sizeof(SysState) * k.nsys,
+  if (hipStreamSynchronize(c.s) != hipSuccess ||
+      hipMemcpy(h.data(), c.at<SysState>(c.L.st), sizeof(SysState) * k.nsys,
                 hipMemcpyDeviceToHost) != hipSuccess)
     return;
   for (int j = 0; j < k.nsys; ++j)
     fprintf(stderr,
-            "[lqcd debug] %s sys %d: it=%d done=%d conv=%d err=%d rel=%d nrel=%d rho=%.3e "
+            "[lqcd debug] %s sys %d: it=%d done=%d conv=%d err=%d lowres=%d nrel=%d rho=%.3e "
             "pp=%.3e a=%.3e target2=%.3e m2s=%.3e\n",
-            where, j, h[j].iters, h[j].done, h[j].conv, h[j].err, h[j].rel, h[j].nrel, h[j].rho,
-            h[j].pp, h[j].a, h[j].target2, h[j].m2s);
+            where, j, h[j].iters, h[j].done, h[j].conv, h[j].err, h[j].lowres, h[j].nrel,
+            h[j].rho, h[j].pp, h[j].a, h[j].target2, h[j].m2s);
 }
 
 int read_flags(const Ctx& c, GlobalFlags* host) {
@@ -788,22 +871,87 @@ int read_flags(const Ctx& c, GlobalFlags* host) {
   return LQCD_OK;
 }
 
-int tune_core(const Ctx& c, Core& k) {
+int tune_phase(const Ctx& c, const Core& k, Phase& ph) {
   int rc;
-  DslashCall t = inner_call(c, k, 1);
-  if ((rc = dslash_tuned(t, c.p.rhs_block, c.s, &k.c_oe))) return rc;
+  DslashCall t = phase_call(c, k, ph, 1);
+  if ((rc = dslash_tuned(t, c.p.rhs_block, c.s, &ph.c_oe))) return rc;
   t.out_par = 0;
   t.mode = DM_CG;
-  if ((rc = dslash_tuned(t, c.p.rhs_block, c.s, &k.c_eo))) return rc;
+  if ((rc = dslash_tuned(t, c.p.rhs_block, c.s, &ph.c_eo))) return rc;
+  ph.nb_oe = dslash_nblocks(c.g, ph.c_oe);
+  ph.nb_eo = dslash_nblocks(c.g, ph.c_eo);
+  return LQCD_OK;
+}
+
+// Fills the phases of k for this context and tunes every stencil they use.
+int setup_core(const Ctx& c, Core& k) {
+  int rc;
+  const bool mixed = is_mixed(c);
+  Phase& m = k.main;
+  m.prec = c.iprec;
+  m.fmt = c.ifmt;
+  m.U = c.Uin;
+  m.r = c.L.r;
+  m.t = c.L.t;
+  m.p = c.L.p;
+  m.x = mixed ? static_cast<void*>(c.ws + c.L.xlo) : static_cast<void*>(k.x);
+  m.rel_d2 = mixed ? c.p.reliable_delta * c.p.reliable_delta : 0.0;
+  m.sw2 = 0.0;
+  k.two_phase = mixed && c.L.has_pre && !k.guess && k.nshift > 1;
+  if (k.two_phase) {
+    Phase& q = k.pre;
+    q.prec = LQCD_F64;
+    q.fmt = c.ifmt;
+    q.U = c.ifmt == LQCD_LINKS12 ? static_cast<const void*>(c.ws + c.L.links_pre) : c.U64;
+    q.r = c.L.r64;
+    q.t = c.L.t64;
+    q.p = c.L.p64;
+    q.x = k.x;
+    q.rel_d2 = 0.0;
+    q.sw2 = c.p.mixed_switch * c.p.mixed_switch;
+    if ((rc = tune_phase(c, k, q))) return rc;
+  }
+  if ((rc = tune_phase(c, k, m))) return rc;
   DslashCall f = fp64_call(c, k, 1);
   if ((rc = dslash_tuned(f, 0, c.s, &k.c64_oe))) return rc;
   f.out_par = 0;
   f.mode = DM_RES;
   if ((rc = dslash_tuned(f, 0, c.s, &k.c64_eo))) return rc;
-  k.nb_oe = dslash_nblocks(c.g, k.c_oe);
-  k.nb_eo = dslash_nblocks(c.g, k.c_eo);
   k.nb64_eo = dslash_nblocks(c.g, k.c64_eo);
   k.nbv = (c.g.Vh + kVecBlock - 1) / kVecBlock;
+  return LQCD_OK;
+}
+
+// Replays blocks of `poll` iterations of phase ph until every system is done
+// (or, for the FP64 opening phase, below the switch level).  With reliable
+// updates the FP64 residual is recomputed when requested, every
+// reliable_interval iterations, and before accepting convergence.
+int run_phase(const Ctx& c, const Core& k, const Phase& ph, bool reliable, bool stop_on_switch,
+              int* iters_run, GlobalFlags* f) {
+  int rc;
+  hipGraphExec_t exec = nullptr;
+  if (c.p.use_graph && (rc = iteration_graph(c, k, ph, &exec))) return rc;
+  const int ri = std::max(1, c.p.reliable_interval);
+  int since_rel = 0;
+  while (!f->all_done && !f->error && !(stop_on_switch && f->phase_done)) {
+    if (exec) {
+      LQCD_HIP_TRY(hipGraphLaunch(exec, c.s));
+    } else {
+      for (int i = 0; i < k.poll; ++i)
+        if ((rc = launch_iteration(c, k, ph, c.s))) return rc;
+    }
+    *iters_run += k.poll;
+    since_rel += k.poll;
+    if ((rc = read_flags(c, f))) return rc;
+    debug_dump(c, k, ph.prec == LQCD_F32 ? "poll32" : "poll64");
+    if (reliable && !f->error && (f->rel_req || f->all_done || since_rel >= ri)) {
+      if ((rc = launch_reliable(c, k, c.s))) return rc;
+      since_rel = 0;
+      if ((rc = read_flags(c, f))) return rc;
+      debug_dump(c, k, "reliable");
+    }
+    if (*iters_run > c.p.max_iter + 2 * k.poll) break;  // device limits iterations; host guard
+  }
   return LQCD_OK;
 }
 
@@ -811,7 +959,7 @@ int tune_core(const Ctx& c, Core& k) {
 int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delta_host,
                std::vector<SysState>* state_out) {
   int rc;
-  if ((rc = tune_core(c, k))) return rc;
+  if ((rc = setup_core(c, k))) return rc;
   const hipStream_t s = c.s;
   SysState* st = c.at<SysState>(c.L.st);
   GlobalFlags* gf = c.at<GlobalFlags>(c.L.gf);
@@ -831,65 +979,61 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
   hipLaunchKernelGGL(k_norm2_f64, gv, dim3(kVecBlock), 0, s, k.b, vstride(c), c.g.Vh,
                      c.at<double>(c.L.pb));
   LQCD_LAUNCH_CHECK();
+  const Phase& first = k.two_phase ? k.pre : k.main;
   int nb_r = k.nbv;
   if (k.guess) {
     if ((rc = launch_residual(c, k, dparams, 1, nullptr, c.at<double>(c.L.pr), s))) return rc;
     nb_r = k.nb64_eo;
-  } else if (mixed) {
+  } else if (first.prec == LQCD_F32) {
     hipLaunchKernelGGL(k_copy_to_inner<float>, gv, dim3(kVecBlock), 0, s, k.b,
-                       c.at<float2>(c.L.r), c.g.Vh, c.at<double>(c.L.pr));
+                       c.at<float2>(first.r), c.g.Vh, c.at<double>(c.L.pr));
   } else {
     hipLaunchKernelGGL(k_copy_to_inner<double>, gv, dim3(kVecBlock), 0, s, k.b,
-                       c.at<double2>(c.L.r), c.g.Vh, c.at<double>(c.L.pr));
+                       c.at<double2>(first.r), c.g.Vh, c.at<double>(c.L.pr));
   }
   LQCD_LAUNCH_CHECK();
-  if (mixed) {
+  if (first.prec == LQCD_F32) {
     if (!k.guess) {
       const int64_t n = int64_t(k.nsys) * k.nshift * vstride(c);
       hipLaunchKernelGGL(k_zero<double2>, dim3(2048), dim3(kVecBlock), 0, s, k.x, n);
       LQCD_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL((k_init_dirs<float, float>), gv, dim3(kVecBlock), 0, s,
-                       c.at<const float2>(c.L.r), c.at<float2>(c.L.p), c.at<float2>(c.L.xlo),
+                       c.at<const float2>(first.r), c.at<float2>(first.p), (float2*)first.x,
                        k.nshift, 1, c.g.Vh, c.at<double>(c.L.pp));
   } else {
     hipLaunchKernelGGL((k_init_dirs<double, double>), gv, dim3(kVecBlock), 0, s,
-                       c.at<const double2>(c.L.r), c.at<double2>(c.L.p), k.x, k.nshift,
+                       c.at<const double2>(first.r), c.at<double2>(first.p), k.x, k.nshift,
                        k.guess ? 0 : 1, c.g.Vh, c.at<double>(c.L.pp));
   }
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_sc_init, dim3(1), dim3(kScalarThreads), 0, s, st, gf, k.nsys, k.nshift,
-                     dparams, k.tol * k.tol, c.at<double>(c.L.pb), k.nbv,
+                     dparams, k.tol * k.tol, first.sw2, c.at<double>(c.L.pb), k.nbv,
                      c.at<double>(c.L.pr), nb_r, c.at<double>(c.L.pp), k.nbv);
   LQCD_LAUNCH_CHECK();
 
-  hipGraphExec_t exec = nullptr;
-  if (c.p.use_graph) {
-    if ((rc = iteration_graph(c, k, &exec))) return rc;
-  }
-  const int ri = std::max(1, c.p.reliable_interval);
-  int since_rel = 0, total = 0;
+  int iters_run = 0;
   GlobalFlags f{};
   if ((rc = read_flags(c, &f))) return rc;
   debug_dump(c, k, "init");
-  while (!f.all_done && !f.error) {
-    if (exec) {
-      LQCD_HIP_TRY(hipGraphLaunch(exec, s));
-    } else {
-      for (int i = 0; i < k.poll; ++i)
-        if ((rc = launch_iteration(c, k, s))) return rc;
+  if (k.two_phase) {
+    // FP64 opening phase until every system's residual is below mixed_switch |b|
+    if ((rc = run_phase(c, k, k.pre, false, true, &iters_run, &f))) return rc;
+    if (!f.all_done && !f.error) {
+      hipLaunchKernelGGL(k_to_fp32, gv, dim3(kVecBlock), 0, s, c.at<const double2>(c.L.r64),
+                         c.at<const double2>(c.L.p64), c.at<float2>(c.L.r), c.at<float2>(c.L.p),
+                         c.at<float2>(c.L.xlo), k.nshift, k.base, c.g.Vh,
+                         c.at<double>(c.L.pp));
+      LQCD_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_sc_phase2, dim3(1), dim3(64), 0, s, st, k.nsys, k.nshift);
+      LQCD_LAUNCH_CHECK();
+      debug_dump(c, k, "switch");
     }
-    total += k.poll;
-    since_rel += k.poll;
-    if ((rc = read_flags(c, &f))) return rc;
-    debug_dump(c, k, "poll");
-    if (mixed && !f.error && (f.rel_req || f.all_done || since_rel >= ri)) {
-      if ((rc = launch_reliable(c, k, s))) return rc;
-      since_rel = 0;
-      if ((rc = read_flags(c, &f))) return rc;
-      debug_dump(c, k, "reliable");
-    }
-    if (total > c.p.max_iter + 2 * k.poll) break;  // device limits iterations; host guard
+  }
+  if ((rc = run_phase(c, k, k.main, mixed, false, &iters_run, &f))) return rc;
+  // a mixed solve that stopped on the iteration limit still folds its FP32 sums in
+  if (mixed && !f.error) {
+    if ((rc = launch_reliable(c, k, s))) return rc;
   }
   state_out->resize(k.nsys);
   LQCD_HIP_TRY(hipMemcpyAsync(state_out->data(), st, sizeof(SysState) * k.nsys,
@@ -964,6 +1108,10 @@ int check_params(const lqcd_solver_params* p) {
     set_error("reliable_delta = %g must be in (0, 1)", p->reliable_delta);
     return LQCD_ERR_INVALID_ARG;
   }
+  if (p->inner_prec == LQCD_F32 && !(p->mixed_switch >= 0.0 && p->mixed_switch < 1.0)) {
+    set_error("mixed_switch = %g must be in [0, 1)", p->mixed_switch);
+    return LQCD_ERR_INVALID_ARG;
+  }
   if (p->inner_prec == LQCD_F32 && p->reliable_interval <= 0) {
     set_error("reliable_interval = %d must be > 0 for mixed precision", p->reliable_interval);
     return LQCD_ERR_INVALID_ARG;
@@ -985,13 +1133,7 @@ int check_params(const lqcd_solver_params* p) {
 }
 
 int poll_for(const lqcd_solver_params& p) {
-  int poll = p.poll_interval > 0 ? p.poll_interval : (p.inner_prec == LQCD_F32 ? 10 : 50);
-  if (p.inner_prec == LQCD_F32) {
-    const int ri = p.reliable_interval;
-    if (poll > ri) poll = ri;
-    while (ri % poll) --poll;  // a reliable update falls on a poll boundary
-  }
-  return poll;
+  return p.poll_interval > 0 ? p.poll_interval : (p.inner_prec == LQCD_F32 ? 10 : 50);
 }
 
 // Shared driver of lqcd_cg (nshift = 1, x holds a guess) and lqcd_cg_multishift.
@@ -1029,7 +1171,7 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
   c.iprec = params->inner_prec;
   c.ifmt = params->inner_fmt;
   c.U64 = U64;
-  c.L = make_layout(c.g, c.iprec, c.ifmt, nshift, nrhs);
+  c.L = make_layout(c.g, *params, nshift, nrhs);
   if (!ws || ws_bytes < c.L.total) {
     set_error("workspace of %zu bytes is too small: %zu needed", ws_bytes, c.L.total);
     return LQCD_ERR_WORKSPACE;
@@ -1037,9 +1179,7 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
   if ((rc = check_ptr(ws, "ws"))) return rc;
   c.ws = static_cast<char*>(ws);
   c.s = (hipStream_t)stream;
-  c.nrhs_max = nrhs;
   c.m2 = params->mass * params->mass;
-  c.rel_delta = params->reliable_delta;
 
   std::lock_guard<std::mutex> lk(G().mu);
   if (!c.L.has_links) {
@@ -1050,6 +1190,12 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
     c.Uin = c.ws + c.L.links;
     if ((rc = convert_links_async(c.g, U64, LQCD_F64, LQCD_LINKS18, c.ws + c.L.links, c.iprec,
                                   c.ifmt, c.s)))
+      return rc;
+  }
+
+  if (c.L.links_pre) {
+    if ((rc = convert_links_async(c.g, U64, LQCD_F64, LQCD_LINKS18, c.ws + c.L.links_pre,
+                                  LQCD_F64, LQCD_LINKS12, c.s)))
       return rc;
   }
 
@@ -1077,10 +1223,12 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
   std::vector<int> refine_iters(size_t(nrhs) * nshift, 0);
   std::vector<double> res2;
   if ((rc = verify(c, k, sigma, &res2))) return rc;
+  // failing (rhs, shift) systems, shift-major so that a batch holds systems
+  // with the same shift, which converge at the same rate
   auto failing = [&]() {
     std::vector<int> f;
-    for (int j = 0; j < nrhs; ++j)
-      for (int s = 0; s < nshift; ++s) {
+    for (int s = 0; s < nshift; ++s)
+      for (int j = 0; j < nrhs; ++j) {
         const double bn = main_state[j].bnorm2;
         const double r2 = res2[size_t(j) * nshift + s];
         if (!(r2 <= params->tol * params->tol * bn)) f.push_back(j * nshift + s);
@@ -1126,9 +1274,14 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
         refine_iters[js] += rstate[q].iters;
       }
     }
-    if ((rc = tune_core(c, k))) return rc;
     if ((rc = verify(c, k, sigma, &res2))) return rc;
   }
+  if (debug_enabled())
+    for (int j = 0; j < nrhs; ++j)
+      for (int s = 0; s < nshift; ++s)
+        fprintf(stderr, "[lqcd debug] final rhs %d shift %d: rel residual %.3e refine %d\n", j, s,
+                std::sqrt(res2[size_t(j) * nshift + s] / main_state[j].bnorm2),
+                refine_iters[size_t(j) * nshift + s]);
 
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1188,13 +1341,14 @@ void lqcd_solver_params_default(lqcd_solver_params* p) {
   p->poll_interval = 0;
   p->max_refine = 3;
   p->reliable_delta = 1e-3;
+  p->mixed_switch = 1e-3;
 }
 
 size_t lqcd_solver_workspace_bytes(const lqcd_geom* g, const lqcd_solver_params* p,
                                    int32_t nshift, int32_t nrhs) {
   if (check_geom(g) || check_params(p) || check_nrhs(nrhs) || nshift < 1 || nshift > kMaxShift)
     return 0;
-  return make_layout(make_kgeom(g), p->inner_prec, p->inner_fmt, nshift, nrhs).total;
+  return make_layout(make_kgeom(g), *p, nshift, nrhs).total;
 }
 
 int lqcd_cg(const lqcd_geom* g, const lqcd_solver_params* p, const void* U64, const void* Uinner,
