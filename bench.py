@@ -170,6 +170,10 @@ def main():
         y = torch.empty_like(x)
         for _ in range(5):
             lq.doe(g, Uin, x, out=y)
+        x64 = torch.randn(1, 3, g.Vh, dtype=torch.complex128, device="cuda")
+        y64 = torch.empty_like(x64)
+        for _ in range(5):
+            lq.doe(g, U64, x64, out=y64)
         cb, tb = lq.stream_bandwidth(1 << 30, 5)
         torch.cuda.synchronize()
         print(json.dumps({"profile_kernels": "done", "copy_bytes_per_array": 1 << 30}), flush=True)
@@ -209,6 +213,12 @@ def main():
     value = nrhs * nshift / (elapsed / args.steps)
 
     stats = state["stats"]
+    # algorithmic bytes of the multi-shift update kernel in the timed solve
+    # (per even site: r read once, x_s and p_s read and written per updated shift)
+    k5_fp64 = g.Vh * sum(row[0]["iters_fp64"] * 48 + row[0]["shift_updates_fp64"] * 192
+                         for row in stats)
+    k5_fp32 = g.Vh * sum((row[0]["iters"] - row[0]["iters_fp64"]) * 24
+                         + row[0]["shift_updates_fp32"] * 96 for row in stats)
     max_tr = max(s["true_rel_residual"] for row in stats for s in row)
     all_conv = all(s["converged"] == 1 for row in stats for s in row)
     iters = [row[0]["iters"] for row in stats]
@@ -296,7 +306,13 @@ def main():
             "speedup_mixed_vs_fp64": (fp64["seconds"] / mixed_solve) if fp64 else None,
             "action_plus_force_s": float(np.median(force_times)),
         },
-        "solver": {"iters_per_rhs": iters, "reliable_updates_per_rhs": rel,
+        "solver": {"iters_per_rhs": iters,
+                   "fp64_phase_iters_per_rhs": [row[0]["iters_fp64"] for row in stats],
+                   "shift_updates_fp64": sum(row[0]["shift_updates_fp64"] for row in stats),
+                   "shift_updates_fp32": sum(row[0]["shift_updates_fp32"] for row in stats),
+                   "ms_update_algorithmic_GB": {"fp64_phase": k5_fp64 / 1e9,
+                                                "fp32_phase": k5_fp32 / 1e9},
+                   "reliable_updates_per_rhs": rel,
                    "refine_iters_total": refine, "max_true_rel_residual": max_tr,
                    "all_converged": all_conv,
                    "fp64_iters_per_rhs": fp64["iters"] if fp64 else None,

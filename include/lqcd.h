@@ -175,6 +175,10 @@ typedef struct {
     int32_t converged;         /* 1 if the true residual is <= tol                   */
     double true_rel_residual;  /* ||b - (A+sigma) x|| / ||b||, FP64, FP64-18 links   */
     double seconds;            /* wall time of the whole call                        */
+    int32_t iters_fp64;        /* of iters, those run in FP64 arithmetic             */
+    int32_t pad_;
+    int64_t shift_updates_fp64; /* main solve: sum over FP64 iterations of updated shifts */
+    int64_t shift_updates_fp32; /* the same over FP32 iterations                      */
 } lqcd_solve_stats;
 
 /* Fills p with defaults: tol 1e-10, max_iter 10000, F64 inner, LINKS18,

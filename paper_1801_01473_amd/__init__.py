@@ -67,10 +67,12 @@ class SolveStats(ctypes.Structure):
         ("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
         ("refine_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
         ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+        ("iters_fp64", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("shift_updates_fp64", ctypes.c_int64), ("shift_updates_fp32", ctypes.c_int64),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
 _vp = ctypes.c_void_p

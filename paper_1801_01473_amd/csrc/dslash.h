@@ -49,7 +49,19 @@ struct DslashCfg {
   int xcd = 1;      // XCD-contiguous block remap
   int tz = 0;       // site traversal: 0 lexicographic; n > 0 walks z in tiles of n
                     // with t inside the tile loop (shorter +-t reuse distance)
+  int nt = 0;       // 1: links loaded non-temporally (they are used once)
+  int occ = 0;      // >0: cap resident waves per SIMD (dynamic LDS reservation), which
+                    // shrinks the set of sites in flight so neighbours stay in L2
 };
+
+// Dynamic LDS a workgroup reserves so that at most occ waves per SIMD are resident.
+inline int dslash_lds_bytes(const DslashCfg& c) {
+  if (c.occ <= 0) return 0;
+  const int waves = c.block / 64;                 // per workgroup
+  const int wg_per_cu = (4 * c.occ) / waves;      // 4 SIMDs per CU
+  if (wg_per_cu < 1) return -1;
+  return (160 * 1024) / wg_per_cu / 1024 * 1024;  // 160 KiB of LDS per CU
+}
 
 // Number of workgroups along the site dimension for a configuration.
 inline int dslash_nblocks(const KGeom& g, const DslashCfg& c) {

@@ -48,7 +48,7 @@ __device__ __forceinline__ int site_of(const KGeom& g, int i, int tz) {
   return inplane + xy * (z + g.Lz * t);
 }
 
-template <typename R, int NE, int B, int MODE, typename RO>
+template <typename R, int NE, int B, int MODE, typename RO, int NT>
 __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xcd, const int tz) {
   __shared__ double lds[B][4];
   if (a.halt && *a.halt) return;
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
       }
       {
         Su3<R> u;
-        load_link<R, NE>(Uout + int64_t(mu) * NE * g.Vh, h, g.Vh, u);
+        load_link<R, NE, NT>(Uout + int64_t(mu) * NE * g.Vh, h, g.Vh, u);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
           if (!lv[b]) continue;
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
       }
       {
         Su3<R> u;
-        load_link<R, NE>(Uin + int64_t(mu) * NE * g.Vh, bwd[mu], g.Vh, u);
+        load_link<R, NE, NT>(Uin + int64_t(mu) * NE * g.Vh, bwd[mu], g.Vh, u);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
           if (!lv[b]) continue;
@@ -197,8 +197,17 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
 template <typename R, int NE, int B, int MODE, typename RO>
 int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
   const dim3 grid(dslash_nblocks(c.g, cfg), (c.nrhs + B - 1) / B);
-  hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO>), grid, dim3(cfg.block), 0, st, c, cfg.xcd,
-                     cfg.tz);
+  const int lds = dslash_lds_bytes(cfg);
+  if (lds < 0) {
+    set_error("occupancy cap %d is below one workgroup of %d threads", cfg.occ, cfg.block);
+    return LQCD_ERR_UNSUPPORTED;
+  }
+  if (cfg.nt)
+    hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, 1>), grid, dim3(cfg.block), lds, st, c,
+                       cfg.xcd, cfg.tz);
+  else
+    hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, 0>), grid, dim3(cfg.block), lds, st, c,
+                       cfg.xcd, cfg.tz);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
@@ -305,10 +314,12 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     }
   }
   DslashCfg best = default_cfg(c.nrhs, forced);
-  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz" pins the configuration (testing, profiling)
+  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ]" pins the configuration (testing,
+  // profiling)
   if (const char* e = std::getenv("LQCD_DSLASH_CFG")) {
     DslashCfg f;
-    if (std::sscanf(e, "%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz) == 4) {
+    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz, &f.nt,
+                    &f.occ) >= 4) {
       if (forced) f.rhs_block = forced;
       *out = f;
       return LQCD_OK;
@@ -321,6 +332,8 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
 
   // Candidates are timed in plain mode on private scratch fields with the
   // caller's links, so no caller data is touched.
+  // Stage 1: workgroup size, RHS block, XCD remap, traversal.  Stage 2: the
+  // three fastest of stage 1 with streaming link loads and occupancy caps.
   std::vector<DslashCfg> cand;
   for (int blk : {64, 128, 256})
     for (int b : {1, 2, 4, 8}) {
@@ -328,7 +341,7 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
       for (int x : {0, 1})
         for (int tz : {0, 2, 4, 8}) {
           if (tz && (c.g.Lz % tz || tz >= c.g.Lz)) continue;
-          cand.push_back(DslashCfg{blk, b, x, tz});
+          cand.push_back(DslashCfg{blk, b, x, tz, 0, 0});
         }
     }
 
@@ -336,7 +349,8 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   void* scratch = nullptr;
   LQCD_HIP_TRY(hipStreamSynchronize(st));
   LQCD_HIP_TRY(hipMalloc(&scratch, 2 * vec * c.nrhs));
-  LQCD_HIP_TRY(hipMemsetAsync(scratch, 0, 2 * vec * c.nrhs, st));
+  // non-zero data (0x3f bytes: ~0.75 in FP32, ~5e-4 in FP64) so timings match real fields
+  LQCD_HIP_TRY(hipMemsetAsync(scratch, 0x3f, 2 * vec * c.nrhs, st));
   hipEvent_t e0, e1;
   LQCD_HIP_TRY(hipEventCreate(&e0));
   LQCD_HIP_TRY(hipEventCreate(&e1));
@@ -359,8 +373,14 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
 
   float best_ms = 1e30f;
   int rc = LQCD_OK;
-  for (const DslashCfg& cfg : cand) {
-    if ((rc = dslash_launch(t, cfg, st)) != LQCD_OK) break;  // warm-up
+  std::vector<std::pair<float, DslashCfg>> timed;
+  const size_t stage1 = cand.size();
+  for (size_t ci = 0; ci < cand.size(); ++ci) {
+    const DslashCfg cfg = cand[ci];
+    if (dslash_launch(t, cfg, st) != LQCD_OK) {  // warm-up; skip what cannot launch
+      clear_error();
+      continue;
+    }
     constexpr int kReps = 4;
     (void)hipEventRecord(e0, st);
     for (int i = 0; i < kReps; ++i) dslash_launch(t, cfg, st);
@@ -372,15 +392,34 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     }
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
+    timed.push_back({ms, cfg});
     if (tuning_verbose())
       fprintf(stderr,
-              "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d block=%d B=%d xcd=%d tz=%d: "
-              "%.2f us\n",
+              "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d block=%d B=%d xcd=%d tz=%d "
+              "nt=%d occ=%d: %.2f us\n",
               c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, cfg.block, cfg.rhs_block,
-              cfg.xcd, cfg.tz, 1000.0 * ms / kReps);
+              cfg.xcd, cfg.tz, cfg.nt, cfg.occ, 1000.0 * ms / kReps);
     if (ms < best_ms) {
       best_ms = ms;
       best = cfg;
+    }
+    if (ci + 1 == stage1) {  // stage 2: the best three of stage 1, streamed / capped
+      std::vector<std::pair<float, DslashCfg>> s1 = timed;
+      std::sort(s1.begin(), s1.end(),
+                [](const std::pair<float, DslashCfg>& a, const std::pair<float, DslashCfg>& b) {
+                  return a.first < b.first;
+                });
+      for (size_t k = 0; k < s1.size() && k < 3; ++k)
+        for (int nt : {0, 1})
+          for (int occ : {0, 2, 3, 4}) {
+            if (!nt && !occ) continue;
+            DslashCfg v = s1[k].second;
+            v.nt = nt;
+            v.occ = occ;
+            const int lds = dslash_lds_bytes(v);
+            if (lds < 0 || lds > 64 * 1024) continue;
+            cand.push_back(v);
+          }
     }
   }
   (void)hipEventDestroy(e0);

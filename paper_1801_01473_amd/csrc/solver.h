@@ -30,6 +30,9 @@ struct alignas(16) SysState {
   int err;         // non-finite or non-positive curvature seen
   int restart;     // directions are rebuilt from the recomputed residual
   int lowres;      // residual below the FP64 -> FP32 switch level
+  int iters64;     // iterations run in FP64 arithmetic
+  int pad_;
+  long long upd64, upd32;  // shift updates applied (sum over iterations of updated shifts)
   double zeta[kMaxShift], zeta_old[kMaxShift], zeta_new[kMaxShift];
   double a_s[kMaxShift], b_s[kMaxShift], delta[kMaxShift];
   int active[kMaxShift];  // shift still iterating

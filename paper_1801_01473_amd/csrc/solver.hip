@@ -171,6 +171,9 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_init(
       S.r2ref = rr;
       S.rho_iter = rr;
       S.restart = 0;
+      S.iters64 = 0;
+      S.upd64 = 0;
+      S.upd32 = 0;
       S.err = finite_d(rr) && finite_d(bn) ? 0 : 1;
       for (int s = 0; s < kMaxShift; ++s) {
         S.zeta[s] = S.zeta_old[s] = S.zeta_new[s] = 1.0;
@@ -243,7 +246,8 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_beta(SysState* __restrict
                                                              GlobalFlags* __restrict__ gf,
                                                              int nshift, const double* part_r,
                                                              int nb_r, int max_iter,
-                                                             double rel_delta2, double sw2) {
+                                                             double rel_delta2, double sw2,
+                                                             int fp64) {
   __shared__ double lds[kScalarThreads / 64];
   const int j = blockIdx.x;
   const double rr = wg_sum(part_r + int64_t(j) * nb_r, nb_r, lds);
@@ -259,8 +263,10 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_beta(SysState* __restrict
     return;
   }
   const double beta = rr / S.rho;
+  int nupd = 0;
   for (int s = 0; s < nshift; ++s) {
     if (!S.upd[s]) continue;
+    ++nupd;
     const double ratio = S.zeta_new[s] / S.zeta[s];
     S.b_s[s] = beta * ratio * ratio;
     S.zeta_old[s] = S.zeta[s];
@@ -272,6 +278,12 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_beta(SysState* __restrict
   S.b_old = beta;
   S.rho = rr;
   S.iters += 1;
+  if (fp64) {
+    S.iters64 += 1;
+    S.upd64 += nupd;
+  } else {
+    S.upd32 += nupd;
+  }
   if (rr < rel_delta2 * S.r2ref) gf->rel_req = 1;
   if (rr <= sw2 * S.bnorm2) S.lowres = 1;
   if (rr <= S.target2 || S.iters >= max_iter) {
@@ -706,7 +718,8 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   if ((rc = dslash_launch(d3, ph.c_eo, s))) return rc;
   // K4
   hipLaunchKernelGGL(k_sc_beta, dim3(k.nsys), dim3(kScalarThreads), 0, s, st, gf, k.nshift,
-                     c.at<double>(c.L.pr), ph.nb_eo, c.p.max_iter, ph.rel_d2, ph.sw2);
+                     c.at<double>(c.L.pr), ph.nb_eo, c.p.max_iter, ph.rel_d2, ph.sw2,
+                     ph.prec == LQCD_F64 ? 1 : 0);
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_sc_flags, dim3(1), dim3(64), 0, s, st, gf, k.nsys);
   LQCD_LAUNCH_CHECK();
@@ -1292,6 +1305,9 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
       const double bn = main_state[j].bnorm2;
       lqcd_solve_stats& o = stats[i];
       o.iters = main_state[j].iters;
+      o.iters_fp64 = main_state[j].iters64;
+      o.shift_updates_fp64 = main_state[j].upd64;
+      o.shift_updates_fp32 = main_state[j].upd32;
       o.reliable_updates = main_state[j].nrel;
       o.refine_iters = refine_iters[i];
       o.true_rel_residual = bn > 0 ? std::sqrt(res2[i] / bn) : std::sqrt(res2[i]);

@@ -15,6 +15,19 @@ __global__ void __launch_bounds__(256) k_copy(const double2* __restrict__ a,
     b[i] = a[i];
 }
 
+// one pass, four 16-byte elements per thread, lane-contiguous
+__global__ void __launch_bounds__(256) k_copy4(const double2* __restrict__ a,
+                                               double2* __restrict__ b, int64_t n) {
+  const int64_t base = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  double2 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + 256 * k < n) v[k] = a[base + 256 * k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + 256 * k < n) b[base + 256 * k] = v[k];
+}
+
 __global__ void __launch_bounds__(256) k_triad(const double2* __restrict__ a,
                                                const double2* __restrict__ b,
                                                double2* __restrict__ c, double s, int64_t n) {
@@ -71,9 +84,14 @@ int lqcd_stream_bandwidth(size_t bytes, int32_t reps, double* copy_gbs, double* 
       }
     return double(best[r / 2]);
   };
-  const double tc = median_ms([&] {
+  const double tc1 = median_ms([&] {
     hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, nullptr, a, b, n);
   });
+  const double tc4 = median_ms([&] {
+    hipLaunchKernelGGL(k_copy4, dim3(unsigned((n + 1023) / 1024)), dim3(256), 0, nullptr, a, b,
+                       n);
+  });
+  const double tc = tc1 < tc4 ? tc1 : tc4;  // a ceiling: the faster copy form
   const double tt = median_ms([&] {
     hipLaunchKernelGGL(k_triad, dim3(grid), dim3(256), 0, nullptr, a, b, c, 1.5, n);
   });

@@ -23,12 +23,26 @@ __device__ __forceinline__ void reconstruct_row2(Su3<R>& u) {
   u.e[8] = conj_of<R>(csub<R>(cmul<R>(u.e[0], u.e[4]), cmul<R>(u.e[1], u.e[3])));
 }
 
-// Load the link with half index h from a packed [NE][Vh] block.
-template <typename R, int NE>
+template <typename R> struct NativeVec2;
+template <> struct NativeVec2<float> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct NativeVec2<double> { typedef double T __attribute__((ext_vector_type(2))); };
+
+// Non-temporal (streaming) load of one complex number: data read exactly once
+// should not evict data that neighbouring sites will read again.
+template <typename R>
+__device__ __forceinline__ cplx<R> load_nt(const cplx<R>* p) {
+  const auto v = __builtin_nontemporal_load(reinterpret_cast<const typename NativeVec2<R>::T*>(p));
+  return mk<R>(v.x, v.y);
+}
+
+// Load the link with half index h from a packed [NE][Vh] block; NT selects
+// streaming loads (every link is read once per application).
+template <typename R, int NE, int NT = 0>
 __device__ __forceinline__ void load_link(const cplx<R>* __restrict__ base, int h, int Vh,
                                           Su3<R>& u) {
 #pragma unroll
-  for (int e = 0; e < NE; ++e) u.e[e] = base[int64_t(e) * Vh + h];
+  for (int e = 0; e < NE; ++e)
+    u.e[e] = NT ? load_nt<R>(base + int64_t(e) * Vh + h) : base[int64_t(e) * Vh + h];
   if (NE == 6) reconstruct_row2<R>(u);
 }
 

@@ -146,8 +146,8 @@ def haar_su3(g: np.random.Generator, n: int) -> np.ndarray:
 
     Rows 0 and 1 are Gram-Schmidt orthonormalised complex Gaussian vectors
     (the first two rows of a Haar U(3) matrix); row 2 = conj(row0 x row1)
-    fixes det = 1.  Completing the rows this way commutes with left
-    multiplication by SU(3), so the result is Haar on SU(3).
+    fixes det = 1.  Completing the rows this way commutes with right
+    multiplication by SU(3) (Z -> Z V), so the result is right-invariant, i.e. Haar on SU(3).
     """
     out = np.empty((n, 3, 3), np.complex128)
     for lo in range(0, n, _CHUNK):
