@@ -52,6 +52,9 @@ struct DslashCfg {
   int nt = 0;       // 1: links loaded non-temporally (they are used once)
   int occ = 0;      // >0: cap resident waves per SIMD (dynamic LDS reservation), which
                     // shrinks the set of sites in flight so neighbours stay in L2
+  int ilv = 0;      // 1: the RHS groups of one site block are consecutive workgroups (links
+                    // then come from L2 after the first group, and fewer distinct sites are
+                    // in flight); 0: RHS groups along the second grid dimension
 };
 
 // Dynamic LDS a workgroup reserves so that at most occ waves per SIMD are resident.

@@ -49,11 +49,16 @@ __device__ __forceinline__ int site_of(const KGeom& g, int i, int tz) {
 }
 
 template <typename R, int NE, int B, int MODE, typename RO, int NT>
-__global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xcd, const int tz) {
+__global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xcd, const int tz,
+                                                const int ngroups, const int ilv) {
   __shared__ double lds[B][4];
   if (a.halt && *a.halt) return;
   const KGeom& g = a.g;
-  const int rhs0 = blockIdx.y * B;
+  // workgroup -> (site block, RHS group)
+  const int nblk = ilv ? gridDim.x / ngroups : gridDim.x;
+  const int lb = xcd_block(blockIdx.x, gridDim.x, xcd);
+  const int blk = ilv ? lb / ngroups : lb;
+  const int rhs0 = (ilv ? lb % ngroups : blockIdx.y) * B;
   bool lv[B];
   bool any = false;
 #pragma unroll
@@ -64,7 +69,6 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
   }
   if (!any) return;  // uniform over the block
 
-  const int blk = xcd_block(blockIdx.x, gridDim.x, xcd);
   const int idx = blk * blockDim.x + threadIdx.x;
   const int h = idx < a.g.Vh ? site_of(a.g, idx, tz) : idx;
   double nrm[B];
@@ -189,14 +193,17 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const double sum = block_sum(nrm[b], lds[b]);
-      if (threadIdx.x == 0 && lv[b]) a.partials[int64_t(rhs0 + b) * gridDim.x + blk] = sum;
+      if (threadIdx.x == 0 && lv[b]) a.partials[int64_t(rhs0 + b) * nblk + blk] = sum;
     }
   }
 }
 
 template <typename R, int NE, int B, int MODE, typename RO>
 int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
-  const dim3 grid(dslash_nblocks(c.g, cfg), (c.nrhs + B - 1) / B);
+  const int ngroups = (c.nrhs + B - 1) / B;
+  const int nb = dslash_nblocks(c.g, cfg);
+  const int ilv = (cfg.ilv && ngroups > 1) ? 1 : 0;
+  const dim3 grid = ilv ? dim3(nb * ngroups, 1) : dim3(nb, ngroups);
   const int lds = dslash_lds_bytes(cfg);
   if (lds < 0) {
     set_error("occupancy cap %d is below one workgroup of %d threads", cfg.occ, cfg.block);
@@ -204,10 +211,10 @@ int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
   }
   if (cfg.nt)
     hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, 1>), grid, dim3(cfg.block), lds, st, c,
-                       cfg.xcd, cfg.tz);
+                       cfg.xcd, cfg.tz, ngroups, ilv);
   else
     hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, 0>), grid, dim3(cfg.block), lds, st, c,
-                       cfg.xcd, cfg.tz);
+                       cfg.xcd, cfg.tz, ngroups, ilv);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
@@ -303,6 +310,17 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     set_error("rhs_block must be 0 (tuned), 1, 2, 4 or 8, got %d", forced);
     return LQCD_ERR_INVALID_ARG;
   }
+  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv]" pins the configuration (testing,
+  // profiling)
+  if (const char* e = std::getenv("LQCD_DSLASH_CFG")) {
+    DslashCfg f;
+    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz, &f.nt,
+                    &f.occ, &f.ilv) >= 4) {
+      if (forced) f.rhs_block = forced;
+      *out = f;
+      return LQCD_OK;
+    }
+  }
   const TuneKey key{c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, c.prec, c.fmt, c.nrhs, forced,
                     c.mode == DM_RES ? 1 : 0};
   {
@@ -314,17 +332,6 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     }
   }
   DslashCfg best = default_cfg(c.nrhs, forced);
-  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ]" pins the configuration (testing,
-  // profiling)
-  if (const char* e = std::getenv("LQCD_DSLASH_CFG")) {
-    DslashCfg f;
-    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz, &f.nt,
-                    &f.occ) >= 4) {
-      if (forced) f.rhs_block = forced;
-      *out = f;
-      return LQCD_OK;
-    }
-  }
   if (!tuning_enabled()) {
     *out = best;
     return LQCD_OK;
@@ -341,7 +348,10 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
       for (int x : {0, 1})
         for (int tz : {0, 2, 4, 8}) {
           if (tz && (c.g.Lz % tz || tz >= c.g.Lz)) continue;
-          cand.push_back(DslashCfg{blk, b, x, tz, 0, 0});
+          for (int ilv : {0, 1}) {
+            if (ilv && b >= c.nrhs) continue;  // a single RHS group has nothing to interleave
+            cand.push_back(DslashCfg{blk, b, x, tz, 0, 0, ilv});
+          }
         }
     }
 
@@ -396,9 +406,9 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     if (tuning_verbose())
       fprintf(stderr,
               "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d block=%d B=%d xcd=%d tz=%d "
-              "nt=%d occ=%d: %.2f us\n",
+              "nt=%d occ=%d ilv=%d: %.2f us\n",
               c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, cfg.block, cfg.rhs_block,
-              cfg.xcd, cfg.tz, cfg.nt, cfg.occ, 1000.0 * ms / kReps);
+              cfg.xcd, cfg.tz, cfg.nt, cfg.occ, cfg.ilv, 1000.0 * ms / kReps);
     if (ms < best_ms) {
       best_ms = ms;
       best = cfg;
@@ -430,6 +440,12 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = best;
   }
+  if (tuning_verbose())
+    fprintf(stderr,
+            "[lqcd tune] chosen L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d: block=%d B=%d xcd=%d tz=%d "
+            "nt=%d occ=%d ilv=%d (%.2f us)\n",
+            c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, best.block, best.rhs_block,
+            best.xcd, best.tz, best.nt, best.occ, best.ilv, 1000.0 * best_ms / 4);
   *out = best;
   return LQCD_OK;
 }

@@ -182,3 +182,40 @@ def test_multishift_config3_32_mixed(lq):
     for s, sg in enumerate(sig):
         tr = oracle.true_residual(L, U, m, sg, b_nat[0], Xn[s])
         assert tr <= 1e-10, (s, tr)
+
+
+def test_phase_counters_and_two_phase_switch(lq):
+    """Mixed multi-shift runs an FP64 opening phase then FP32; the counters
+    report it consistently, and an FP64 solve reports all its work as FP64."""
+    L = (8, 8, 8, 8)
+    U = synth.links_exp(L, 0.5, 108)
+    g, U64, b_nat, b = setup(lq, L, U, 208, 2)
+    sig = synth.rational_shifts(6, 1e-3, 1.0)
+    pm = lq.solver_params(mass=0.05, tol=1e-10, inner_prec=1, inner_fmt=1, mixed_switch=1e-3)
+    X, st, stats = lq.cg_multishift(g, pm, U64, sig, b)
+    for row in stats:
+        s0 = row[0]
+        assert 0 < s0["iters_fp64"] < s0["iters"]
+        assert s0["iters_fp64"] <= s0["shift_updates_fp64"] <= s0["iters_fp64"] * len(sig)
+        n32 = s0["iters"] - s0["iters_fp64"]
+        assert n32 <= s0["shift_updates_fp32"] <= n32 * len(sig)
+    p64 = lq.solver_params(mass=0.05, tol=1e-10)
+    X64, st, s64 = lq.cg_multishift(g, p64, U64, sig, b)
+    for row in s64:
+        assert row[0]["iters_fp64"] == row[0]["iters"] and row[0]["shift_updates_fp32"] == 0
+    # both reach the same solutions within the tolerance
+    d = (X - X64).abs().max().item() / X64.abs().max().item()
+    assert d < 1e-6
+    # FP32 throughout (no opening phase) also meets the bar, through refinement
+    p0 = lq.solver_params(mass=0.05, tol=1e-10, inner_prec=1, inner_fmt=1, mixed_switch=0.0)
+    X0, st, s0 = lq.cg_multishift(g, p0, U64, sig, b)
+    Xn = host(lq.unpack_spinor(g, X0.reshape(-1, 3, g.Vh), 0)).reshape(2, len(sig), -1, 3)
+    for j in range(2):
+        for s, sg in enumerate(sig):
+            assert oracle.true_residual(L, U, 0.05, sg, b_nat[j], Xn[j, s]) <= 1e-10
+        assert s0[j][0]["iters_fp64"] == 0
+
+
+def test_stream_bandwidth_reports(lq):
+    c, t = lq.stream_bandwidth(1 << 26, 3)
+    assert c > 100.0 and t > 100.0
