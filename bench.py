@@ -23,8 +23,9 @@ solves of the same systems, D_oe/D_eo bandwidth against the 8 TB/s peak and a
 STREAM ceiling, the roofline of the dominant kernel measured with HIP events,
 and the CPU oracle timed on a bounded sample.
 
---profile-kernels runs only the dominant kernel and a copy kernel of known
-size (for rocprofv3 counter collection) and exits.
+--profile-kernels runs one warm mixed solve of the workload, standalone D_oe
+launches and a copy kernel of known size (for rocprofv3 counter collection)
+and exits.
 """
 from __future__ import annotations
 
@@ -96,6 +97,43 @@ def dslash_bytes_per_site(prec, fmt, nrhs):
     return links + nrhs * 2 * (3 * 2 * rb)
 
 
+def kernel_table(g, nrhs, stats, ktimes):
+    """Per-kernel average launch time (HIP events) and algorithmic bandwidth of
+    the main solve's kernels.  Bytes per even/odd site and launch, all RHS live:
+      D_oe            links + nrhs (in + out)
+      D_eo + CG       links + nrhs (t in + p in + r in + r out)
+      shift update    per RHS: r in + per updated shift (x in/out + p in/out),
+                      from the device's count of updated shifts."""
+    Vh = g.Vh
+    iters64 = sum(row[0]["iters_fp64"] for row in stats)
+    iters32 = sum(row[0]["iters"] - row[0]["iters_fp64"] for row in stats)
+    upd64 = sum(row[0]["shift_updates_fp64"] for row in stats)
+    upd32 = sum(row[0]["shift_updates_fp32"] for row in stats)
+    links = {"f64": 8 * 6 * 16, "f32": 8 * 6 * 8}  # 12-real links
+    spin = {"f64": 48, "f32": 24}
+    out = {}
+    for cls, (n, ms) in ktimes.items():
+        if "_refine" in cls or not cls.endswith(f"_n{nrhs}"):
+            continue
+        prec = "f64" if "_f64" in cls else "f32"
+        if cls.startswith("dslash_oe"):
+            per_launch = Vh * (links[prec] + nrhs * 2 * spin[prec])
+            kern = f"k_dslash D_oe {prec} 12-real"
+        elif cls.startswith("dslash_eo_cg"):
+            per_launch = Vh * (links[prec] + nrhs * 4 * spin[prec])
+            kern = f"k_dslash D_eo+CG update {prec} 12-real"
+        else:
+            its, upd = (iters64, upd64) if prec == "f64" else (iters32, upd32)
+            total = Vh * (its * spin[prec] + upd * 4 * spin[prec])
+            per_launch = total / max(n, 1)
+            kern = f"k_ms_update {prec}"
+        avg_us = 1000.0 * ms / max(n, 1)
+        gbs = per_launch / (avg_us * 1e-6) / 1e9
+        out[cls] = dict(kernel=kern, launches=n, total_ms=ms, avg_us=avg_us,
+                        bytes_per_launch=per_launch, GBps=gbs, frac_hbm_peak=gbs / HBM_PEAK_GBS)
+    return out
+
+
 def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, budget_s=20.0):
     """Oracle multi-shift CG timed on a bounded sample: a few iterations on one
     right-hand side of the same lattice, scaled to the GPU run's iteration
@@ -135,7 +173,7 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
-                    help="only run the dominant kernel and a copy kernel (for counters)")
+                    help="one solve + standalone D_oe + copy kernel, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -165,6 +203,11 @@ def main():
 
     if args.profile_kernels:
         U64 = lq.pack_links(g, U_dev)
+        lq.cg_multishift(g, params, U64, sig, phi_p)  # tuning + graph capture
+        torch.cuda.synchronize()
+        log("profiled solve")
+        _, _, pst = lq.cg_multishift(g, params, U64, sig, phi_p)
+        torch.cuda.synchronize()
         Uin = lq.convert_links(g, U64, lq.F64, lq.LINKS18, dom["prec"], dom["fmt"])
         x = torch.randn(nrhs, 3, g.Vh, dtype=torch.complex64, device="cuda")
         y = torch.empty_like(x)
@@ -176,7 +219,15 @@ def main():
             lq.doe(g, U64, x64, out=y64)
         cb, tb = lq.stream_bandwidth(1 << 30, 5)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_kernels": "done", "copy_bytes_per_array": 1 << 30}), flush=True)
+        k5_64 = g.Vh * sum(r[0]["iters_fp64"] * 48 + r[0]["shift_updates_fp64"] * 192
+                           for r in pst)
+        k5_32 = g.Vh * sum((r[0]["iters"] - r[0]["iters_fp64"]) * 24
+                           + r[0]["shift_updates_fp32"] * 96 for r in pst)
+        print(json.dumps({"profile_kernels": "done", "copy_bytes_per_array": 1 << 30,
+                          "profiled_solve_iters_fp64": [r[0]["iters_fp64"] for r in pst],
+                          "profiled_solve_iters": [r[0]["iters"] for r in pst],
+                          "ms_update_algorithmic_bytes": {"fp64": k5_64, "fp32": k5_32}}),
+              flush=True)
         return
 
     state = {}
@@ -225,6 +276,14 @@ def main():
     refine = sum(s["refine_iters"] for row in stats for s in row)
     rel = [row[0]["reliable_updates"] for row in stats]
 
+    # per-kernel timing of the same solve (HIP events around each launch, no graph)
+    lq.kernel_timing(True)
+    _, _, tstats = lq.cg_multishift(g, params, state["U64"], sig, phi_p)
+    lq.kernel_timing(False)
+    ktimes = lq.kernel_timing()
+    kernels = kernel_table(g, nrhs, tstats, ktimes)
+    dominant = max(kernels, key=lambda k: kernels[k]["total_ms"])
+
     # time-to-1e-10: plain FP64 GPU multi-shift, one RHS at a time
     fp64 = None
     if not args.no_fp64_baseline:
@@ -263,17 +322,18 @@ def main():
         dsl[name] = dict(us=1000 * ms, GBps=gbs, frac_hbm_peak=gbs / HBM_PEAK_GBS,
                          frac_stream_copy=gbs / copy_gbs, GFLOPs=flops / (ms * 1e-3) / 1e9)
         del x, y
-    dkey = f"fp32_12_{nrhs}rhs"
+    kd = kernels[dominant]
     roof = {
-        "kernel": f"k_dslash<float,6,B,DM_PLAIN> (D_oe, FP32 12-real, {nrhs} RHS, tuned B)",
+        "kernel": f"{dominant} ({kd['kernel']})",
         "bound": "hbm",
-        "achieved": dsl[dkey]["GBps"],
+        "achieved": kd["GBps"],
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": dsl[dkey]["GBps"] / HBM_PEAK_GBS,
+        "frac": kd["GBps"] / HBM_PEAK_GBS,
         "traffic": None,
-        "algorithmic_bytes_per_launch": g.Vh * dslash_bytes_per_site(lq.F32, lq.LINKS12, nrhs),
-        "avg_launch_us": dsl[dkey]["us"],
+        "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
+        "avg_launch_us": kd["avg_us"],
+        "share_of_solve_kernel_time": kd["total_ms"] / sum(v["total_ms"] for v in kernels.values()),
     }
 
     cpu = None
@@ -317,6 +377,7 @@ def main():
                    "all_converged": all_conv,
                    "fp64_iters_per_rhs": fp64["iters"] if fp64 else None,
                    "fp64_max_true_rel_residual": fp64["max_true_residual"] if fp64 else None},
+        "kernels": kernels,
         "dslash": dsl,
         "stream": {"copy_GBps": copy_gbs, "triad_GBps": triad_gbs},
     }

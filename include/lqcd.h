@@ -277,6 +277,20 @@ int lqcd_action(const lqcd_geom *g, int32_t npf, int32_t nshift, double alpha0,
  */
 int lqcd_stream_bandwidth(size_t bytes, int32_t reps, double *copy_gbs, double *triad_gbs);
 
+/*
+ * Kernel timing (instrumentation of the solvers; not needed to use them).
+ * While enabled, lqcd_cg / lqcd_cg_multishift launch without graph replay
+ * and bracket every D_oe, fused D_eo + residual update and multi-shift
+ * update launch with HIP events on the caller's stream; durations accumulate
+ * per kernel class, named "<kernel>_<f64|f32>[_refine]_n<systems>".
+ * lqcd_kernel_timing_enable(1) clears the totals and enables, (0) disables.
+ * lqcd_kernel_timing_get reads class `index` (0-based, in first-seen order);
+ * it returns LQCD_ERR_INVALID_ARG past the last class.
+ */
+int lqcd_kernel_timing_enable(int32_t on);
+int lqcd_kernel_timing_get(int32_t index, char *name, size_t name_len, int64_t *launches,
+                           double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -111,6 +111,9 @@ _SIGS = {
     "lqcd_action": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp,
                                    ctypes.c_size_t, _vp]),
     "lqcd_stream_bandwidth": (ctypes.c_int, [ctypes.c_size_t, _i32, _dp, _dp]),
+    "lqcd_kernel_timing_enable": (ctypes.c_int, [_i32]),
+    "lqcd_kernel_timing_get": (ctypes.c_int, [_i32, ctypes.c_char_p, ctypes.c_size_t,
+                                              ctypes.POINTER(ctypes.c_int64), _dp]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -387,6 +390,23 @@ def stream_bandwidth(nbytes: int = 1 << 30, reps: int = 20):
     t = ctypes.c_double(0.0)
     _check(_fn("lqcd_stream_bandwidth")(int(nbytes), int(reps), ctypes.byref(c), ctypes.byref(t)))
     return float(c.value), float(t.value)
+
+
+def kernel_timing(enable: bool | None = None):
+    """Enable/disable the solvers' per-kernel event timing, or (enable=None)
+    return {class: (launches, total_ms)} accumulated so far."""
+    if enable is not None:
+        _check(_fn("lqcd_kernel_timing_enable")(1 if enable else 0))
+        return None
+    out = {}
+    buf = ctypes.create_string_buffer(128)
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    i = 0
+    while _fn("lqcd_kernel_timing_get")(i, buf, 128, ctypes.byref(n), ctypes.byref(ms)) == OK:
+        out[buf.value.decode()] = (int(n.value), float(ms.value))
+        i += 1
+    return out
 
 
 class FermionAction(torch.autograd.Function):

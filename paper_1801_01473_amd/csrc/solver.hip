@@ -602,6 +602,78 @@ void clear_graphs() {
   G().graphs.clear();
 }
 
+// Kernel timing (instrumentation): when enabled, D_oe, D_eo and multi-shift
+// update launches are bracketed by HIP events on their stream and their
+// durations accumulate per kernel class.  Solves then run without graphs.
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Pending {
+    hipEvent_t a, b;
+    std::string cls;
+  };
+  std::vector<Pending> pending;
+  std::vector<std::string> order;
+  std::map<std::string, std::pair<int64_t, double>> acc;  // launches, total ms
+};
+Timing& T() {
+  static Timing t;
+  return t;
+}
+
+bool timing_on() {
+  std::lock_guard<std::mutex> lk(T().mu);
+  return T().on;
+}
+
+hipEvent_t timing_event() {
+  Timing& t = T();
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records the start event of a timed launch (nullptr when timing is off).
+hipEvent_t timing_begin(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(T().mu);
+  if (!T().on) return nullptr;
+  hipEvent_t e = timing_event();
+  if (e) (void)hipEventRecord(e, s);
+  return e;
+}
+
+void timing_end(hipEvent_t a, hipStream_t s, const std::string& cls) {
+  if (!a) return;
+  std::lock_guard<std::mutex> lk(T().mu);
+  hipEvent_t b = timing_event();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  T().pending.push_back({a, b, cls});
+}
+
+// Folds completed event pairs into the totals (the stream has been synchronised).
+void timing_resolve() {
+  std::lock_guard<std::mutex> lk(T().mu);
+  Timing& t = T();
+  for (auto& p : t.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      if (!t.acc.count(p.cls)) t.order.push_back(p.cls);
+      t.acc[p.cls].first += 1;
+      t.acc[p.cls].second += ms;
+    }
+    t.pool.push_back(p.a);
+    t.pool.push_back(p.b);
+  }
+  t.pending.clear();
+}
+
 struct Ctx {
   KGeom g;
   lqcd_solver_params p;
@@ -693,7 +765,11 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   d1.live_stride = kStateStrideI;
   d1.halt = &gf->all_done;
   d1.partials = c.at<double>(c.L.pt);
+  const std::string tag = std::string(ph.prec == LQCD_F32 ? "_f32" : "_f64") +
+                          (k.guess ? "_refine" : "") + "_n" + std::to_string(k.nsys);
+  hipEvent_t ev = timing_begin(s);
   if ((rc = dslash_launch(d1, ph.c_oe, s))) return rc;
+  timing_end(ev, s, "dslash_oe" + tag);
   // K2
   hipLaunchKernelGGL(k_sc_alpha, dim3(k.nsys), dim3(kScalarThreads), 0, s, st, gf, k.nshift,
                      c.at<double>(c.L.pt), ph.nb_oe, c.at<double>(c.L.pp), k.nbv);
@@ -715,7 +791,9 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   d3.live_stride = kStateStrideI;
   d3.halt = &gf->all_done;
   d3.partials = c.at<double>(c.L.pr);
+  ev = timing_begin(s);
   if ((rc = dslash_launch(d3, ph.c_eo, s))) return rc;
+  timing_end(ev, s, "dslash_eo_cg" + tag);
   // K4
   hipLaunchKernelGGL(k_sc_beta, dim3(k.nsys), dim3(kScalarThreads), 0, s, st, gf, k.nshift,
                      c.at<double>(c.L.pr), ph.nb_eo, c.p.max_iter, ph.rel_d2, ph.sw2,
@@ -725,6 +803,7 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   LQCD_LAUNCH_CHECK();
   // K5
   const dim3 grid(k.nbv, k.nsys);
+  ev = timing_begin(s);
   if (ph.prec == LQCD_F32)
     hipLaunchKernelGGL((k_ms_update<float, float>), grid, dim3(kVecBlock), 0, s, st,
                        c.at<const float2>(ph.r), c.at<float2>(ph.p), (float2*)ph.x, k.nshift,
@@ -734,6 +813,7 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
                        c.at<const double2>(ph.r), c.at<double2>(ph.p), (double2*)ph.x, k.nshift,
                        k.base, c.g.Vh, c.at<double>(c.L.pp));
   LQCD_LAUNCH_CHECK();
+  timing_end(ev, s, "ms_update" + tag);
   return LQCD_OK;
 }
 
@@ -881,6 +961,7 @@ int read_flags(const Ctx& c, GlobalFlags* host) {
                               hipMemcpyDeviceToHost, c.s));
   LQCD_HIP_TRY(hipStreamSynchronize(c.s));
   *host = *hf;
+  timing_resolve();
   return LQCD_OK;
 }
 
@@ -943,7 +1024,7 @@ int run_phase(const Ctx& c, const Core& k, const Phase& ph, bool reliable, bool 
               int* iters_run, GlobalFlags* f) {
   int rc;
   hipGraphExec_t exec = nullptr;
-  if (c.p.use_graph && (rc = iteration_graph(c, k, ph, &exec))) return rc;
+  if (c.p.use_graph && !timing_on() && (rc = iteration_graph(c, k, ph, &exec))) return rc;
   const int ri = std::max(1, c.p.reliable_interval);
   int since_rel = 0;
   while (!f->all_done && !f->error && !(stop_on_switch && f->phase_done)) {
@@ -1328,7 +1409,19 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
 
 }  // namespace
 
+void timing_release() {
+  std::lock_guard<std::mutex> lk(T().mu);
+  for (auto& p : T().pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  T().pending.clear();
+  for (hipEvent_t e : T().pool) (void)hipEventDestroy(e);
+  T().pool.clear();
+}
+
 void solver_release() {
+  timing_release();
   std::lock_guard<std::mutex> lk(G().mu);
   clear_graphs();
   if (G().pinned) (void)hipHostFree(G().pinned);
@@ -1379,6 +1472,40 @@ int lqcd_cg_multishift(const lqcd_geom* g, const lqcd_solver_params* p, const vo
                        size_t ws_bytes, void* stream) {
   return solve(g, p, U64, Uinner, nshift, sigma, b, x, nrhs, false, stats, ws, ws_bytes,
                stream);
+}
+
+int lqcd_kernel_timing_enable(int32_t on) {
+  clear_error();
+  if (on != 0 && on != 1) {
+    set_error("lqcd_kernel_timing_enable: on must be 0 or 1");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(T().mu);
+  T().on = on == 1;
+  if (on) {
+    T().acc.clear();
+    T().order.clear();
+  }
+  return LQCD_OK;
+}
+
+int lqcd_kernel_timing_get(int32_t index, char* name, size_t name_len, int64_t* launches,
+                           double* total_ms) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(T().mu);
+  if (index < 0 || size_t(index) >= T().order.size()) {
+    set_error("kernel timing index %d out of range (%zu classes)", index, T().order.size());
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (!name || name_len == 0 || !launches || !total_ms) {
+    set_error("kernel timing outputs must be non-null");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const std::string& cls = T().order[index];
+  std::snprintf(name, name_len, "%s", cls.c_str());
+  *launches = T().acc[cls].first;
+  *total_ms = T().acc[cls].second;
+  return LQCD_OK;
 }
 
 int lqcd_finalize(void) {

@@ -219,3 +219,30 @@ def test_phase_counters_and_two_phase_switch(lq):
 def test_stream_bandwidth_reports(lq):
     c, t = lq.stream_bandwidth(1 << 26, 3)
     assert c > 100.0 and t > 100.0
+
+
+def test_kernel_timing_instrumentation(lq):
+    """Timing mode brackets every D_oe, D_eo and shift-update launch of the
+    main solve with events; counts match the iteration counts and the
+    solution equals the graph-replayed one bitwise."""
+    L = (8, 8, 4, 4)
+    U = synth.links_exp(L, 0.5, 109)
+    g, U64, b_nat, b = setup(lq, L, U, 209, 2)
+    sig = synth.rational_shifts(4, 1e-2, 1.0)
+    p = lq.solver_params(mass=0.1, tol=1e-10, inner_prec=1, inner_fmt=1)
+    Xg, _, sg = lq.cg_multishift(g, p, U64, sig, b)
+    lq.kernel_timing(True)
+    Xt, _, st = lq.cg_multishift(g, p, U64, sig, b)
+    lq.kernel_timing(False)
+    kt = lq.kernel_timing()
+    assert torch.equal(Xg, Xt)
+    n64 = kt["ms_update_f64_n2"][0]
+    n32 = kt["ms_update_f32_n2"][0]
+    it64 = st[0][0]["iters_fp64"]
+    # launches come in blocks of the poll interval, so there can be a few more than iterations
+    assert n64 >= it64 and n32 >= st[0][0]["iters"] - it64
+    assert kt["dslash_oe_f64_n2"][0] == n64 and kt["dslash_eo_cg_f32_n2"][0] == n32
+    assert all(ms > 0 for _, ms in kt.values())
+    lq.kernel_timing(True)
+    assert lq.kernel_timing() == {}
+    lq.kernel_timing(False)
