@@ -97,18 +97,37 @@ def dslash_bytes_per_site(prec, fmt, nrhs):
     return links + nrhs * 2 * (3 * 2 * rb)
 
 
+def shift_update_bytes(Vh, stats):
+    """Algorithmic bytes of the shift-update kernels of a solve, per precision
+    and kernel, from the device's counters (per even site, spinor = 3 complex):
+      per-iteration update (window 1): r in + per updated shift x, p in and out
+      base update (window > 1): r in, p in and out, ring slot out per iteration
+      window flush: each ring slot in + per materialised shift x, p in and out"""
+    spin = {"f64": 48, "f32": 24}
+    its = {"f64": sum(r[0]["iters_fp64"] for r in stats),
+           "f32": sum(r[0]["iters"] - r[0]["iters_fp64"] for r in stats)}
+    out = {}
+    for prec, sfx in (("f64", "fp64"), ("f32", "fp32")):
+        sp = spin[prec]
+        if stats[0][0]["shift_window"] > 1:
+            out["base_update_" + prec] = Vh * its[prec] * 4 * sp
+            out["ms_flush_" + prec] = Vh * sum(r[0]["flush_slots_" + sfx] * sp
+                                               + r[0]["flush_shifts_" + sfx] * 4 * sp
+                                               for r in stats)
+        else:
+            upd = sum(r[0]["shift_updates_" + sfx] for r in stats)
+            out["ms_update_" + prec] = Vh * (its[prec] * sp + upd * 4 * sp)
+    return out
+
+
 def kernel_table(g, nrhs, stats, ktimes):
     """Per-kernel average launch time (HIP events) and algorithmic bandwidth of
     the main solve's kernels.  Bytes per even/odd site and launch, all RHS live:
       D_oe            links + nrhs (in + out)
       D_eo + CG       links + nrhs (t in + p in + r in + r out)
-      shift update    per RHS: r in + per updated shift (x in/out + p in/out),
-                      from the device's count of updated shifts."""
+      shift updates   from the device's counters, see shift_update_bytes."""
     Vh = g.Vh
-    iters64 = sum(row[0]["iters_fp64"] for row in stats)
-    iters32 = sum(row[0]["iters"] - row[0]["iters_fp64"] for row in stats)
-    upd64 = sum(row[0]["shift_updates_fp64"] for row in stats)
-    upd32 = sum(row[0]["shift_updates_fp32"] for row in stats)
+    upd_bytes = shift_update_bytes(Vh, stats)
     links = {"f64": 8 * 6 * 16, "f32": 8 * 6 * 8}  # 12-real links
     spin = {"f64": 48, "f32": 24}
     out = {}
@@ -123,10 +142,12 @@ def kernel_table(g, nrhs, stats, ktimes):
             per_launch = Vh * (links[prec] + nrhs * 4 * spin[prec])
             kern = f"k_dslash D_eo+CG update {prec} 12-real"
         else:
-            its, upd = (iters64, upd64) if prec == "f64" else (iters32, upd32)
-            total = Vh * (its * spin[prec] + upd * 4 * spin[prec])
-            per_launch = total / max(n, 1)
-            kern = f"k_ms_update {prec}"
+            base = cls.rsplit("_n", 1)[0]
+            if base not in upd_bytes:
+                continue
+            per_launch = upd_bytes[base] / max(n, 1)
+            kern = {"ms_update": "k_ms_update", "base_update": "k_base_update",
+                    "ms_flush": "k_ms_flush"}[base.rsplit("_", 1)[0]] + f" {prec}"
         avg_us = 1000.0 * ms / max(n, 1)
         gbs = per_launch / (avg_us * 1e-6) / 1e9
         out[cls] = dict(kernel=kern, launches=n, total_ms=ms, avg_us=avg_us,
@@ -219,14 +240,11 @@ def main():
             lq.doe(g, U64, x64, out=y64)
         cb, tb = lq.stream_bandwidth(1 << 30, 5)
         torch.cuda.synchronize()
-        k5_64 = g.Vh * sum(r[0]["iters_fp64"] * 48 + r[0]["shift_updates_fp64"] * 192
-                           for r in pst)
-        k5_32 = g.Vh * sum((r[0]["iters"] - r[0]["iters_fp64"]) * 24
-                           + r[0]["shift_updates_fp32"] * 96 for r in pst)
         print(json.dumps({"profile_kernels": "done", "copy_bytes_per_array": 1 << 30,
                           "profiled_solve_iters_fp64": [r[0]["iters_fp64"] for r in pst],
                           "profiled_solve_iters": [r[0]["iters"] for r in pst],
-                          "ms_update_algorithmic_bytes": {"fp64": k5_64, "fp32": k5_32}}),
+                          "shift_window": pst[0][0]["shift_window"],
+                          "shift_update_algorithmic_bytes": shift_update_bytes(g.Vh, pst)}),
               flush=True)
         return
 
@@ -264,12 +282,6 @@ def main():
     value = nrhs * nshift / (elapsed / args.steps)
 
     stats = state["stats"]
-    # algorithmic bytes of the multi-shift update kernel in the timed solve
-    # (per even site: r read once, x_s and p_s read and written per updated shift)
-    k5_fp64 = g.Vh * sum(row[0]["iters_fp64"] * 48 + row[0]["shift_updates_fp64"] * 192
-                         for row in stats)
-    k5_fp32 = g.Vh * sum((row[0]["iters"] - row[0]["iters_fp64"]) * 24
-                         + row[0]["shift_updates_fp32"] * 96 for row in stats)
     max_tr = max(s["true_rel_residual"] for row in stats for s in row)
     all_conv = all(s["converged"] == 1 for row in stats for s in row)
     iters = [row[0]["iters"] for row in stats]
@@ -370,8 +382,9 @@ def main():
                    "fp64_phase_iters_per_rhs": [row[0]["iters_fp64"] for row in stats],
                    "shift_updates_fp64": sum(row[0]["shift_updates_fp64"] for row in stats),
                    "shift_updates_fp32": sum(row[0]["shift_updates_fp32"] for row in stats),
-                   "ms_update_algorithmic_GB": {"fp64_phase": k5_fp64 / 1e9,
-                                                "fp32_phase": k5_fp32 / 1e9},
+                   "shift_window": stats[0][0]["shift_window"],
+                   "shift_update_algorithmic_GB": {
+                       k: v / 1e9 for k, v in shift_update_bytes(g.Vh, stats).items()},
                    "reliable_updates_per_rhs": rel,
                    "refine_iters_total": refine, "max_true_rel_residual": max_tr,
                    "all_converged": all_conv,

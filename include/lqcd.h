@@ -163,6 +163,8 @@ typedef struct {
     int32_t rhs_block;         /* right-hand sides per D_oe/D_eo link load, 0 = tuned */
     int32_t poll_interval;     /* iterations between host convergence checks, 0 = auto */
     int32_t max_refine;        /* rounds of per-shift refinement allowed, >= 0       */
+    int32_t shift_window;      /* multi-shift: iterations between materialisations of
+                                  the shifted x_s, p_s (1..31; 1 = every iteration) */
     double reliable_delta;     /* mixed: also update when |r| fell by this factor    */
     double mixed_switch;       /* mixed multi-shift: iterate in FP64 until |r| <=
                                   mixed_switch |b|, then in FP32 (0: FP32 throughout) */
@@ -176,14 +178,19 @@ typedef struct {
     double true_rel_residual;  /* ||b - (A+sigma) x|| / ||b||, FP64, FP64-18 links   */
     double seconds;            /* wall time of the whole call                        */
     int32_t iters_fp64;        /* of iters, those run in FP64 arithmetic             */
-    int32_t pad_;
+    int32_t shift_window;      /* window length used by the main solve (1: none)     */
     int64_t shift_updates_fp64; /* main solve: sum over FP64 iterations of updated shifts */
     int64_t shift_updates_fp32; /* the same over FP32 iterations                      */
+    int64_t flush_shifts_fp64; /* main solve: sum over FP64 window flushes of the
+                                  shifts materialised                               */
+    int64_t flush_shifts_fp32; /* the same over FP32 window flushes                  */
+    int64_t flush_slots_fp64;  /* sum over FP64 window flushes of residuals combined */
+    int64_t flush_slots_fp32;  /* the same over FP32 window flushes                  */
 } lqcd_solve_stats;
 
 /* Fills p with defaults: tol 1e-10, max_iter 10000, F64 inner, LINKS18,
  * reliable_interval 100, use_graph 1, rhs_block 0, poll 0, max_refine 3,
- * reliable_delta 1e-3, mixed_switch 1e-3. */
+ * shift_window 10, reliable_delta 1e-3, mixed_switch 1e-3. */
 void lqcd_solver_params_default(lqcd_solver_params *p);
 
 /* Device workspace that lqcd_cg / lqcd_cg_multishift need for these sizes. */
@@ -224,7 +231,14 @@ int lqcd_cg(const lqcd_geom *g, const lqcd_solver_params *p, const void *U64_pac
  *   b       packed even FP64 [nrhs][3][Vh]
  *   x       packed even FP64 [nrhs][nshift][3][Vh] (output; not read)
  *   stats   host [nrhs][nshift]
- * A shift stops updating once its collinear residual is below tol.  After
+ * A shift stops updating once its collinear residual is below tol.
+ * Deferred shift updates: only the base direction is formed every iteration;
+ * each shifted x_s, p_s is a linear combination of its value at the start of
+ * a window and of the base residuals of the window (the recurrences of
+ * Sec. 2 are linear in them), so the shifted vectors are read and written
+ * once per window of shift_window iterations (reduced to a divisor of the
+ * poll interval) instead of every iteration.  The window's residuals are kept
+ * in the workspace.  After
  * the base system converges, the FP64 true residual of every (j, i) is
  * computed; systems above tol are refined together by warm-started CG on
  * their residuals, up to max_refine rounds.  All right-hand sides share each

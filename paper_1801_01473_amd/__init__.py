@@ -57,7 +57,8 @@ class SolverParams(ctypes.Structure):
         ("inner_prec", ctypes.c_int32), ("inner_fmt", ctypes.c_int32),
         ("reliable_interval", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("rhs_block", ctypes.c_int32), ("poll_interval", ctypes.c_int32),
-        ("max_refine", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
+        ("max_refine", ctypes.c_int32), ("shift_window", ctypes.c_int32),
+        ("reliable_delta", ctypes.c_double),
         ("mixed_switch", ctypes.c_double),
     ]
 
@@ -67,12 +68,14 @@ class SolveStats(ctypes.Structure):
         ("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
         ("refine_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
         ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-        ("iters_fp64", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("iters_fp64", ctypes.c_int32), ("shift_window", ctypes.c_int32),
         ("shift_updates_fp64", ctypes.c_int64), ("shift_updates_fp32", ctypes.c_int64),
+        ("flush_shifts_fp64", ctypes.c_int64), ("flush_shifts_fp32", ctypes.c_int64),
+        ("flush_slots_fp64", ctypes.c_int64), ("flush_slots_fp32", ctypes.c_int64),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _vp = ctypes.c_void_p

@@ -13,6 +13,12 @@
 //       convergence and iteration limits
 //   K5  for every active shift: x_s += a_s p_s ; p_s = zeta_s r + beta_s p_s
 //                                      + FP64 partials of |p_0|^2
+// With deferred shift updates (multi-shift, window W > 1) K5 only forms the
+// base direction p = r + beta p and files r in a ring of W residuals; K4 also
+// advances, per shift, the coefficients that express x_s and p_s in terms of
+// p_s at the window start and the ring, and every W iterations K6 applies
+//       x_s += sum_q cx_sq v_q ,  p_s = sum_q cp_sq v_q   (v_0 = p_s, v_q = ring)
+// reading each shifted vector once per window instead of every iteration.
 // All reductions are two-stage and in fixed order, so results do not depend
 // on scheduling.  Kernels skip systems (and whole launches) that are done,
 // so a block of iterations can be replayed as one captured hipGraph.
@@ -117,10 +123,12 @@ __global__ void __launch_bounds__(kVecBlock) k_copy_to_inner(const double2* __re
 }
 
 // p_s = r for every shift, optionally x_s = 0; partials of |r|^2 (= |p|^2)
+// (pc, when given: the base direction of deferred shift updates, also = r)
 template <typename RI, typename RX>
 __global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restrict__ r,
                                                          cplx<RI>* __restrict__ p,
-                                                         cplx<RX>* __restrict__ x, int nshift,
+                                                         cplx<RX>* __restrict__ x,
+                                                         cplx<RI>* __restrict__ pc, int nshift,
                                                          int zero_x, int Vh,
                                                          double* __restrict__ part) {
   __shared__ double lds[kVecBlock / 64];
@@ -132,6 +140,7 @@ __global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restr
     for (int c = 0; c < 3; ++c) {
       const cplx<RI> z = r[(int64_t(j) * 3 + c) * Vh + h];
       s += cnorm2<RI>(z);
+      if (pc) pc[(int64_t(j) * 3 + c) * Vh + h] = z;
       for (int k = 0; k < nshift; ++k) {
         const int64_t i = ((int64_t(j) * nshift + k) * 3 + c) * Vh + h;
         p[i] = z;
@@ -172,8 +181,11 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_init(
       S.rho_iter = rr;
       S.restart = 0;
       S.iters64 = 0;
+      S.wpos = 0;
       S.upd64 = 0;
       S.upd32 = 0;
+      S.fsh64 = S.fsh32 = 0;
+      S.fsl64 = S.fsl32 = 0;
       S.err = finite_d(rr) && finite_d(bn) ? 0 : 1;
       for (int s = 0; s < kMaxShift; ++s) {
         S.zeta[s] = S.zeta_old[s] = S.zeta_new[s] = 1.0;
@@ -182,6 +194,7 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_init(
         S.active[s] = s < nshift ? 1 : 0;
         S.upd[s] = 0;
         S.dirty[s] = 0;
+        S.wdirty[s] = 0;
       }
       S.conv = rr <= S.target2 ? 1 : 0;
       S.done = (S.conv || S.err) ? 1 : 0;
@@ -241,55 +254,98 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_alpha(SysState* __restric
 }
 
 // K4: beta, shifted betas, freezing, convergence; one workgroup per system.
-// The global flags are derived afterwards by k_sc_flags.
+// The global flags are derived afterwards by k_sc_flags.  With deferred
+// shift updates (wc != nullptr) the whole workgroup then advances the window
+// coefficients of the updated shifts, one thread per coefficient:
+//   x_s += a_s p_s   ->  cx_s += a_s cp_s
+//   p_s  = zeta_s r + b_s p_s  ->  cp_s = b_s cp_s, cp_s[n+1] = zeta_s
+// where index n+1 is the residual after this iteration (ring slot n).
 __global__ void __launch_bounds__(kScalarThreads) k_sc_beta(SysState* __restrict__ st,
                                                              GlobalFlags* __restrict__ gf,
                                                              int nshift, const double* part_r,
                                                              int nb_r, int max_iter,
                                                              double rel_delta2, double sw2,
-                                                             int fp64) {
+                                                             int fp64, WinCoef* __restrict__ wc,
+                                                             int win) {
   __shared__ double lds[kScalarThreads / 64];
+  __shared__ double sh_a[kMaxShift], sh_b[kMaxShift], sh_z[kMaxShift];
+  __shared__ int sh_u[kMaxShift];
+  __shared__ int sh_n;
   const int j = blockIdx.x;
   const double rr = wg_sum(part_r + int64_t(j) * nb_r, nb_r, lds);
-  if (threadIdx.x != 0) return;
-  SysState& S = st[j];
-  if (!S.upd_any) return;
-  if (!finite_d(rr)) {
-    S.err = 1;
-    S.done = 1;
-    S.live = 0;
-    S.upd_any = 0;
-    gf->error = 1;
-    return;
+  if (threadIdx.x == 0) {
+    sh_n = -1;
+    SysState& S = st[j];
+    bool go = S.upd_any != 0;
+    if (go && !finite_d(rr)) {
+      S.err = 1;
+      S.done = 1;
+      S.live = 0;
+      S.upd_any = 0;
+      gf->error = 1;
+      go = false;
+    }
+    if (go && wc && S.wpos >= win) {  // the window was not flushed in time
+      S.err = 1;
+      S.done = 1;
+      S.live = 0;
+      S.upd_any = 0;
+      gf->error = 1;
+      go = false;
+    }
+    if (go) {
+      const double beta = rr / S.rho;
+      int nupd = 0;
+      for (int s = 0; s < nshift; ++s) {
+        sh_u[s] = S.upd[s];
+        if (!S.upd[s]) continue;
+        ++nupd;
+        const double ratio = S.zeta_new[s] / S.zeta[s];
+        S.b_s[s] = beta * ratio * ratio;
+        S.zeta_old[s] = S.zeta[s];
+        S.zeta[s] = S.zeta_new[s];
+        S.dirty[s] = 1;
+        S.wdirty[s] |= wc ? 1 : 0;
+        sh_a[s] = S.a_s[s];
+        sh_b[s] = S.b_s[s];
+        sh_z[s] = S.zeta[s];
+        if (S.zeta_new[s] * S.zeta_new[s] * rr <= S.target2) S.active[s] = 0;
+      }
+      S.a_old = S.a;
+      S.b_old = beta;
+      S.rho = rr;
+      S.iters += 1;
+      if (fp64) {
+        S.iters64 += 1;
+        S.upd64 += nupd;
+      } else {
+        S.upd32 += nupd;
+      }
+      if (rr < rel_delta2 * S.r2ref) gf->rel_req = 1;
+      if (rr <= sw2 * S.bnorm2) S.lowres = 1;
+      if (rr <= S.target2 || S.iters >= max_iter) {
+        S.done = 1;
+        S.live = 0;
+        S.conv = rr <= S.target2 ? 1 : 0;
+      }
+      if (wc) {
+        sh_n = S.wpos;
+        S.wpos += 1;
+      }
+    }
   }
-  const double beta = rr / S.rho;
-  int nupd = 0;
-  for (int s = 0; s < nshift; ++s) {
-    if (!S.upd[s]) continue;
-    ++nupd;
-    const double ratio = S.zeta_new[s] / S.zeta[s];
-    S.b_s[s] = beta * ratio * ratio;
-    S.zeta_old[s] = S.zeta[s];
-    S.zeta[s] = S.zeta_new[s];
-    S.dirty[s] = 1;
-    if (S.zeta_new[s] * S.zeta_new[s] * rr <= S.target2) S.active[s] = 0;
-  }
-  S.a_old = S.a;
-  S.b_old = beta;
-  S.rho = rr;
-  S.iters += 1;
-  if (fp64) {
-    S.iters64 += 1;
-    S.upd64 += nupd;
-  } else {
-    S.upd32 += nupd;
-  }
-  if (rr < rel_delta2 * S.r2ref) gf->rel_req = 1;
-  if (rr <= sw2 * S.bnorm2) S.lowres = 1;
-  if (rr <= S.target2 || S.iters >= max_iter) {
-    S.done = 1;
-    S.live = 0;
-    S.conv = rr <= S.target2 ? 1 : 0;
+  __syncthreads();
+  const int n = sh_n;
+  if (n < 0) return;
+  const int s = threadIdx.x / kWinRow, q = threadIdx.x % kWinRow;
+  if (s >= nshift || !sh_u[s]) return;
+  WinCoef& C = wc[j];
+  if (q <= n) {
+    const double cp = C.cp[s][q];
+    C.cx[s][q] = fma(sh_a[s], cp, C.cx[s][q]);
+    C.cp[s][q] = sh_b[s] * cp;
+  } else if (q == n + 1) {
+    C.cp[s][q] = sh_z[s];
   }
 }
 
@@ -344,6 +400,122 @@ __global__ void __launch_bounds__(kVecBlock) k_ms_update(const SysState* __restr
   }
   pn = block_sum(pn, lds);
   if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = pn;
+}
+
+// K5 with deferred shift updates: p = zeta_0 r + beta_0 p for the base
+// direction only (zeta_0 = 1), r filed in ring slot wpos - 1; partials of |p|^2.
+template <typename RI>
+__global__ void __launch_bounds__(kVecBlock) k_base_update(const SysState* __restrict__ st,
+                                                           const cplx<RI>* __restrict__ r,
+                                                           cplx<RI>* __restrict__ pc,
+                                                           cplx<RI>* __restrict__ ring, int win,
+                                                           int base, int Vh,
+                                                           double* __restrict__ part) {
+  __shared__ double lds[kVecBlock / 64];
+  const int j = blockIdx.y;
+  const SysState& S = st[j];
+  if (!S.upd_any) return;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = S.wpos - 1;  // in [0, win): k_sc_beta stops a system before overflow
+  double pn = 0.0;
+  if (h < Vh) {
+    const RI zs = RI(S.zeta[base]), bs = RI(S.b_s[base]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = (int64_t(j) * 3 + c) * Vh + h;
+      const cplx<RI> rv = r[i];
+      cplx<RI> pv = pc[i];
+      pv.x = fma(zs, rv.x, bs * pv.x);
+      pv.y = fma(zs, rv.y, bs * pv.y);
+      pc[i] = pv;
+      ring[((int64_t(j) * win + slot) * 3 + c) * Vh + h] = rv;
+      pn += cnorm2<RI>(pv);
+    }
+  }
+  pn = block_sum(pn, lds);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = pn;
+}
+
+// K6: applies the window of every system that has one open (wpos > 0) to the
+// shifts updated in it; WM >= window length bounds the unrolled ring.
+template <typename RI, typename RX, int WM>
+__global__ void __launch_bounds__(kVecBlock) k_ms_flush(const SysState* __restrict__ st,
+                                                        const WinCoef* __restrict__ wc,
+                                                        const cplx<RI>* __restrict__ ring,
+                                                        cplx<RI>* __restrict__ p,
+                                                        cplx<RX>* __restrict__ x, int nshift,
+                                                        int win, int Vh) {
+  const int j = blockIdx.y;
+  const SysState& S = st[j];
+  const int n = S.wpos < win ? S.wpos : win;
+  if (n <= 0) return;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= Vh) return;
+  const WinCoef& C = wc[j];
+#pragma unroll 1
+  for (int c = 0; c < 3; ++c) {
+    cplx<RI> v[WM];
+#pragma unroll
+    for (int q = 0; q < WM; ++q)
+      if (q < n) v[q] = ring[((int64_t(j) * win + q) * 3 + c) * Vh + h];
+    for (int s = 0; s < nshift; ++s) {
+      if (!S.wdirty[s]) continue;
+      const int64_t o = ((int64_t(j) * nshift + s) * 3 + c) * Vh + h;
+      const cplx<RI> p0 = p[o];
+      const RX cx0 = RX(C.cx[s][0]);
+      const RI cp0 = RI(C.cp[s][0]);
+      RX dx = cx0 * RX(p0.x), dy = cx0 * RX(p0.y);
+      RI px = cp0 * p0.x, py = cp0 * p0.y;
+#pragma unroll
+      for (int q = 0; q < WM; ++q) {
+        if (q < n) {
+          const RX a = RX(C.cx[s][q + 1]);
+          const RI b = RI(C.cp[s][q + 1]);
+          dx = fma(a, RX(v[q].x), dx);
+          dy = fma(a, RX(v[q].y), dy);
+          px = fma(b, v[q].x, px);
+          py = fma(b, v[q].y, py);
+        }
+      }
+      cplx<RX> xv = x[o];
+      xv.x += dx;
+      xv.y += dy;
+      x[o] = xv;
+      p[o] = mk<RI>(px, py);
+    }
+  }
+}
+
+// Closes the window of every system that has one open (init: of every
+// system): coefficients back to x_s += 0, p_s = p_s; counts the flush.
+__global__ void __launch_bounds__(kScalarThreads) k_sc_win_reset(SysState* __restrict__ st,
+                                                                  WinCoef* __restrict__ wc,
+                                                                  int nshift, int fp64,
+                                                                  int init) {
+  __shared__ int sh_go;
+  const int j = blockIdx.x;
+  SysState& S = st[j];
+  if (threadIdx.x == 0) sh_go = init || S.wpos > 0;
+  __syncthreads();
+  if (!sh_go) return;
+  const int s = threadIdx.x / kWinRow, q = threadIdx.x % kWinRow;
+  wc[j].cx[s][q] = 0.0;
+  wc[j].cp[s][q] = q == 0 ? 1.0 : 0.0;
+  if (threadIdx.x == 0) {
+    if (!init) {
+      long long ns = 0;
+      for (int k = 0; k < nshift; ++k) ns += S.wdirty[k];
+      if (fp64) {
+        S.fsh64 += ns;
+        S.fsl64 += S.wpos;
+      } else {
+        S.fsh32 += ns;
+        S.fsl32 += S.wpos;
+      }
+    }
+    S.wpos = 0;
+    for (int k = 0; k < kMaxShift; ++k) S.wdirty[k] = 0;
+  }
 }
 
 __global__ void k_sc_rel_begin(SysState* __restrict__ st, GlobalFlags* __restrict__ gf, int nsys,
@@ -432,10 +604,12 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_reliable(SysState* __rest
 }
 
 // p_s = zeta_s r for the shifts of restarted systems, partials of |p_base|^2
+// (and the base direction pc of deferred shift updates, when given)
 template <typename RI>
 __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __restrict__ st,
                                                             const cplx<RI>* __restrict__ r,
-                                                            cplx<RI>* __restrict__ p, int nshift,
+                                                            cplx<RI>* __restrict__ p,
+                                                            cplx<RI>* __restrict__ pc, int nshift,
                                                             int base, int Vh,
                                                             double* __restrict__ part) {
   __shared__ double lds[kVecBlock / 64];
@@ -453,7 +627,10 @@ __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __re
         const RI z = RI(S.zeta[s]);
         const cplx<RI> pv = mk<RI>(z * rv.x, z * rv.y);
         p[((int64_t(j) * nshift + s) * 3 + c) * Vh + h] = pv;
-        if (s == base) pn += cnorm2<RI>(pv);
+        if (s == base) {
+          pn += cnorm2<RI>(pv);
+          if (pc) pc[(int64_t(j) * 3 + c) * Vh + h] = pv;
+        }
       }
     }
   }
@@ -462,10 +639,13 @@ __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __re
 }
 
 // FP64 Krylov state -> FP32: r, every shift's p; x_lo = 0; partials of |p_base|^2
+// (with deferred shift updates the base direction is pc64 -> pc32)
 __global__ void __launch_bounds__(kVecBlock) k_to_fp32(const double2* __restrict__ r64,
                                                        const double2* __restrict__ p64,
+                                                       const double2* __restrict__ pc64,
                                                        float2* __restrict__ r32,
                                                        float2* __restrict__ p32,
+                                                       float2* __restrict__ pc32,
                                                        float2* __restrict__ xlo, int nshift,
                                                        int base, int Vh,
                                                        double* __restrict__ part) {
@@ -478,12 +658,17 @@ __global__ void __launch_bounds__(kVecBlock) k_to_fp32(const double2* __restrict
     for (int c = 0; c < 3; ++c) {
       const int64_t ir = (int64_t(j) * 3 + c) * Vh + h;
       r32[ir] = make_float2(float(r64[ir].x), float(r64[ir].y));
+      if (pc64) {
+        const float2 pv = make_float2(float(pc64[ir].x), float(pc64[ir].y));
+        pc32[ir] = pv;
+        pn += cnorm2<float>(pv);
+      }
       for (int s = 0; s < nshift; ++s) {
         const int64_t i = ((int64_t(j) * nshift + s) * 3 + c) * Vh + h;
         const float2 pv = make_float2(float(p64[i].x), float(p64[i].y));
         p32[i] = pv;
         xlo[i] = make_float2(0.f, 0.f);
-        if (s == base) pn += cnorm2<float>(pv);
+        if (s == base && !pc64) pn += cnorm2<float>(pv);
       }
     }
   }
@@ -518,9 +703,25 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t r, t, p, xlo, r64, t64, p64, thi, bb, xb, st, gf, params, pt, pr, pp, pb, pres, resn,
-      links, links_pre, total;
+      links, links_pre, pc, pc64, ring, wc, total;
   bool has_xlo, has_pre, has_links;
+  int win;  // window of deferred shift updates of the main solve (1: none)
 };
+
+int poll_for(const lqcd_solver_params& p) {
+  return p.poll_interval > 0 ? p.poll_interval : (p.inner_prec == LQCD_F32 ? 10 : 50);
+}
+
+// Window length of deferred shift updates: shift_window reduced to a divisor
+// of the poll interval, so that every replayed block of iterations ends with
+// all windows closed; 1 (no deferral) for a single shift.
+int window_for(const lqcd_solver_params& p, int nshift) {
+  if (nshift < 2) return 1;
+  const int poll = poll_for(p);
+  int w = std::max(1, std::min(p.shift_window, kMaxWin));
+  while (w > 1 && poll % w != 0) --w;
+  return w;
+}
 
 // Workspace layout.  Mixed precision keeps FP32 iteration vectors and FP32
 // partial solutions, plus FP64 iteration vectors for the FP64 opening phase
@@ -564,6 +765,15 @@ Layout make_layout(const KGeom& g, const lqcd_solver_params& p, int nshift, int 
   // the FP64 opening phase streams FP64 links in the inner format (12-real:
   // a third fewer link bytes than the 18-real copy used for residuals)
   L.links_pre = (L.has_pre && ifmt == LQCD_LINKS12) ? take(size_t(8) * 6 * g.Vh * 16) : 0;
+  // deferred shift updates: base directions and the residual ring, shared by
+  // the FP64 opening phase and the main phase (the ring is empty at the switch)
+  L.win = window_for(p, nshift);
+  if (L.win > 1) {
+    L.pc = take(nrhs * vin);
+    L.pc64 = L.has_pre ? take(nrhs * v64) : 0;
+    L.ring = take(size_t(nrhs) * L.win * (L.has_pre ? v64 : vin));
+    L.wc = take(size_t(nrhs) * sizeof(WinCoef));
+  }
   L.total = off;
   return L;
 }
@@ -696,6 +906,7 @@ struct Phase {
   int prec = LQCD_F64, fmt = LQCD_LINKS18;
   const void* U = nullptr;
   size_t r = 0, t = 0, p = 0;  // workspace offsets of r, t (odd), p_s
+  size_t pc = 0;               // base direction (deferred shift updates)
   void* x = nullptr;           // solution accumulator: FP64 solutions or FP32 partial sums
   DslashCfg c_oe, c_eo;
   int nb_oe = 0, nb_eo = 0;
@@ -715,6 +926,7 @@ struct Core {
   DslashCfg c64_oe, c64_eo;  // FP64 18-real: residuals and verification
   int nb64_eo, nbv;
   int poll;
+  int win;  // deferred shift updates when > 1
 };
 
 bool is_mixed(const Ctx& c) { return c.iprec == LQCD_F32; }
@@ -749,16 +961,47 @@ DslashCall fp64_call(const Ctx& c, const Core& k, int out_par) {
   return d;
 }
 
-int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s) {
+// K6 and the window reset: applies every open window of deferred shift updates.
+int launch_flush(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s) {
+  SysState* st = c.at<SysState>(c.L.st);
+  WinCoef* wc = c.at<WinCoef>(c.L.wc);
+  const dim3 grid(k.nbv, k.nsys);
+  const std::string tag = std::string(ph.prec == LQCD_F32 ? "_f32" : "_f64") + "_n" +
+                          std::to_string(k.nsys);
+  hipEvent_t ev = timing_begin(s);
+#define LQCD_FLUSH(RI, WM)                                                                     \
+  hipLaunchKernelGGL((k_ms_flush<RI, RI, WM>), grid, dim3(kVecBlock), 0, s, st, wc,            \
+                     c.at<const cplx<RI>>(c.L.ring), c.at<cplx<RI>>(ph.p),                     \
+                     static_cast<cplx<RI>*>(ph.x), k.nshift, k.win, c.g.Vh)
+  if (ph.prec == LQCD_F32) {
+    if (k.win <= 8) LQCD_FLUSH(float, 8);
+    else if (k.win <= 16) LQCD_FLUSH(float, 16);
+    else LQCD_FLUSH(float, 32);
+  } else {
+    if (k.win <= 8) LQCD_FLUSH(double, 8);
+    else if (k.win <= 16) LQCD_FLUSH(double, 16);
+    else LQCD_FLUSH(double, 32);
+  }
+#undef LQCD_FLUSH
+  LQCD_LAUNCH_CHECK();
+  timing_end(ev, s, "ms_flush" + tag);
+  hipLaunchKernelGGL(k_sc_win_reset, dim3(k.nsys), dim3(kScalarThreads), 0, s, st, wc, k.nshift,
+                     ph.prec == LQCD_F64 ? 1 : 0, 0);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s, bool flush) {
   SysState* st = c.at<SysState>(c.L.st);
   GlobalFlags* gf = c.at<GlobalFlags>(c.L.gf);
   const int64_t vs = vstride(c);
+  const bool win = k.win > 1;
   int rc;
   // K1: t = D_oe p_base
   DslashCall d1 = phase_call(c, k, ph, 1);
   d1.mode = DM_PLAIN;
-  d1.in = vec_at(c, ph.p, ph.prec, k.base);
-  d1.in_stride = int64_t(k.nshift) * vs;
+  d1.in = win ? c.ws + ph.pc : vec_at(c, ph.p, ph.prec, k.base);
+  d1.in_stride = win ? vs : int64_t(k.nshift) * vs;
   d1.out = c.ws + ph.t;
   d1.out_stride = vs;
   d1.live = &st->live;
@@ -779,8 +1022,8 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   d3.mode = DM_CG;
   d3.in = c.ws + ph.t;
   d3.in_stride = vs;
-  d3.diag = vec_at(c, ph.p, ph.prec, k.base);
-  d3.diag_stride = int64_t(k.nshift) * vs;
+  d3.diag = win ? c.ws + ph.pc : vec_at(c, ph.p, ph.prec, k.base);
+  d3.diag_stride = win ? vs : int64_t(k.nshift) * vs;
   d3.r = c.ws + ph.r;
   d3.r_stride = vs;
   d3.m2s = &st->m2s;
@@ -797,12 +1040,27 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   // K4
   hipLaunchKernelGGL(k_sc_beta, dim3(k.nsys), dim3(kScalarThreads), 0, s, st, gf, k.nshift,
                      c.at<double>(c.L.pr), ph.nb_eo, c.p.max_iter, ph.rel_d2, ph.sw2,
-                     ph.prec == LQCD_F64 ? 1 : 0);
+                     ph.prec == LQCD_F64 ? 1 : 0, win ? c.at<WinCoef>(c.L.wc) : nullptr, k.win);
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_sc_flags, dim3(1), dim3(64), 0, s, st, gf, k.nsys);
   LQCD_LAUNCH_CHECK();
   // K5
   const dim3 grid(k.nbv, k.nsys);
+  if (win) {
+    ev = timing_begin(s);
+    if (ph.prec == LQCD_F32)
+      hipLaunchKernelGGL(k_base_update<float>, grid, dim3(kVecBlock), 0, s, st,
+                         c.at<const float2>(ph.r), c.at<float2>(ph.pc), c.at<float2>(c.L.ring),
+                         k.win, k.base, c.g.Vh, c.at<double>(c.L.pp));
+    else
+      hipLaunchKernelGGL(k_base_update<double>, grid, dim3(kVecBlock), 0, s, st,
+                         c.at<const double2>(ph.r), c.at<double2>(ph.pc),
+                         c.at<double2>(c.L.ring), k.win, k.base, c.g.Vh,
+                         c.at<double>(c.L.pp));
+    LQCD_LAUNCH_CHECK();
+    timing_end(ev, s, "base_update" + tag);
+    return flush ? launch_flush(c, k, ph, s) : LQCD_OK;
+  }
   ev = timing_begin(s);
   if (ph.prec == LQCD_F32)
     hipLaunchKernelGGL((k_ms_update<float, float>), grid, dim3(kVecBlock), 0, s, st,
@@ -853,18 +1111,22 @@ int launch_residual(const Ctx& c, const Core& k, const double* m2s, int m2s_stri
 int launch_reliable(const Ctx& c, const Core& k, hipStream_t s) {
   SysState* st = c.at<SysState>(c.L.st);
   GlobalFlags* gf = c.at<GlobalFlags>(c.L.gf);
+  int rc;
+  // open windows are applied first, so that x_lo and every p_s are current
+  if (k.win > 1 && (rc = launch_flush(c, k, k.main, s))) return rc;
   hipLaunchKernelGGL(k_sc_rel_begin, dim3(1), dim3(64), 0, s, st, gf, k.nsys, k.nshift);
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_accum, dim3(k.nbv, k.nsys * k.nshift), dim3(kVecBlock), 0, s, st,
                      c.at<float2>(c.L.xlo), k.x, k.nshift, c.g.Vh);
   LQCD_LAUNCH_CHECK();
-  int rc = launch_residual(c, k, &st->m2s, kStateStrideD, &st->rel, c.at<double>(c.L.pres), s);
+  rc = launch_residual(c, k, &st->m2s, kStateStrideD, &st->rel, c.at<double>(c.L.pres), s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_sc_reliable, dim3(1), dim3(kScalarThreads), 0, s, st, gf, k.nsys,
                      k.nshift, k.base, c.at<double>(c.L.pres), k.nb64_eo, c.p.max_iter);
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_restart_dirs<float>, dim3(k.nbv, k.nsys), dim3(kVecBlock), 0, s, st,
-                     c.at<const float2>(c.L.r), c.at<float2>(c.L.p), k.nshift, k.base, c.g.Vh,
+                     c.at<const float2>(c.L.r), c.at<float2>(c.L.p),
+                     k.win > 1 ? c.at<float2>(c.L.pc) : nullptr, k.nshift, k.base, c.g.Vh,
                      c.at<double>(c.L.pp));
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
@@ -882,12 +1144,14 @@ std::string graph_key(const Ctx& c, const Core& k, const Phase& ph) {
   add(&k.base, sizeof(int));
   add(&k.nbv, sizeof(int));
   add(&k.poll, sizeof(int));
+  add(&k.win, sizeof(int));
   add(&ph.prec, sizeof(int));
   add(&ph.fmt, sizeof(int));
   add(&ph.U, sizeof(void*));
   add(&ph.r, sizeof(size_t));
   add(&ph.t, sizeof(size_t));
   add(&ph.p, sizeof(size_t));
+  add(&ph.pc, sizeof(size_t));
   add(&ph.x, sizeof(void*));
   add(&ph.c_oe, sizeof(DslashCfg));
   add(&ph.c_eo, sizeof(DslashCfg));
@@ -908,7 +1172,8 @@ int iteration_graph(const Ctx& c, const Core& k, const Phase& ph, hipGraphExec_t
   if (!gl.cap) LQCD_HIP_TRY(hipStreamCreateWithFlags(&gl.cap, hipStreamNonBlocking));
   LQCD_HIP_TRY(hipStreamBeginCapture(gl.cap, hipStreamCaptureModeThreadLocal));
   int rc = LQCD_OK;
-  for (int i = 0; i < k.poll && rc == LQCD_OK; ++i) rc = launch_iteration(c, k, ph, gl.cap);
+  for (int i = 0; i < k.poll && rc == LQCD_OK; ++i)
+    rc = launch_iteration(c, k, ph, gl.cap, (i + 1) % k.win == 0);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(gl.cap, &graph);
   if (rc != LQCD_OK) {
@@ -988,6 +1253,8 @@ int setup_core(const Ctx& c, Core& k) {
   m.r = c.L.r;
   m.t = c.L.t;
   m.p = c.L.p;
+  m.pc = c.L.pc;
+  k.win = k.nshift > 1 ? c.L.win : 1;
   m.x = mixed ? static_cast<void*>(c.ws + c.L.xlo) : static_cast<void*>(k.x);
   m.rel_d2 = mixed ? c.p.reliable_delta * c.p.reliable_delta : 0.0;
   m.sw2 = 0.0;
@@ -1000,6 +1267,7 @@ int setup_core(const Ctx& c, Core& k) {
     q.r = c.L.r64;
     q.t = c.L.t64;
     q.p = c.L.p64;
+    q.pc = c.L.pc64;
     q.x = k.x;
     q.rel_d2 = 0.0;
     q.sw2 = c.p.mixed_switch * c.p.mixed_switch;
@@ -1032,7 +1300,7 @@ int run_phase(const Ctx& c, const Core& k, const Phase& ph, bool reliable, bool 
       LQCD_HIP_TRY(hipGraphLaunch(exec, c.s));
     } else {
       for (int i = 0; i < k.poll; ++i)
-        if ((rc = launch_iteration(c, k, ph, c.s))) return rc;
+        if ((rc = launch_iteration(c, k, ph, c.s, (i + 1) % k.win == 0))) return rc;
     }
     *iters_run += k.poll;
     since_rel += k.poll;
@@ -1094,10 +1362,12 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
     }
     hipLaunchKernelGGL((k_init_dirs<float, float>), gv, dim3(kVecBlock), 0, s,
                        c.at<const float2>(first.r), c.at<float2>(first.p), (float2*)first.x,
-                       k.nshift, 1, c.g.Vh, c.at<double>(c.L.pp));
+                       k.win > 1 ? c.at<float2>(first.pc) : nullptr, k.nshift, 1, c.g.Vh,
+                       c.at<double>(c.L.pp));
   } else {
     hipLaunchKernelGGL((k_init_dirs<double, double>), gv, dim3(kVecBlock), 0, s,
-                       c.at<const double2>(first.r), c.at<double2>(first.p), k.x, k.nshift,
+                       c.at<const double2>(first.r), c.at<double2>(first.p), k.x,
+                       k.win > 1 ? c.at<double2>(first.pc) : nullptr, k.nshift,
                        k.guess ? 0 : 1, c.g.Vh, c.at<double>(c.L.pp));
   }
   LQCD_LAUNCH_CHECK();
@@ -1105,6 +1375,11 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
                      dparams, k.tol * k.tol, first.sw2, c.at<double>(c.L.pb), k.nbv,
                      c.at<double>(c.L.pr), nb_r, c.at<double>(c.L.pp), k.nbv);
   LQCD_LAUNCH_CHECK();
+  if (k.win > 1) {
+    hipLaunchKernelGGL(k_sc_win_reset, dim3(k.nsys), dim3(kScalarThreads), 0, s, st,
+                       c.at<WinCoef>(c.L.wc), k.nshift, 0, 1);
+    LQCD_LAUNCH_CHECK();
+  }
 
   int iters_run = 0;
   GlobalFlags f{};
@@ -1113,9 +1388,13 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
   if (k.two_phase) {
     // FP64 opening phase until every system's residual is below mixed_switch |b|
     if ((rc = run_phase(c, k, k.pre, false, true, &iters_run, &f))) return rc;
+    if (k.win > 1 && (rc = launch_flush(c, k, k.pre, s))) return rc;
     if (!f.all_done && !f.error) {
+      const bool w = k.win > 1;
       hipLaunchKernelGGL(k_to_fp32, gv, dim3(kVecBlock), 0, s, c.at<const double2>(c.L.r64),
-                         c.at<const double2>(c.L.p64), c.at<float2>(c.L.r), c.at<float2>(c.L.p),
+                         c.at<const double2>(c.L.p64),
+                         w ? c.at<const double2>(c.L.pc64) : nullptr, c.at<float2>(c.L.r),
+                         c.at<float2>(c.L.p), w ? c.at<float2>(c.L.pc) : nullptr,
                          c.at<float2>(c.L.xlo), k.nshift, k.base, c.g.Vh,
                          c.at<double>(c.L.pp));
       LQCD_LAUNCH_CHECK();
@@ -1128,11 +1407,14 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
   // a mixed solve that stopped on the iteration limit still folds its FP32 sums in
   if (mixed && !f.error) {
     if ((rc = launch_reliable(c, k, s))) return rc;
+  } else if (k.win > 1 && (rc = launch_flush(c, k, k.main, s))) {
+    return rc;
   }
   state_out->resize(k.nsys);
   LQCD_HIP_TRY(hipMemcpyAsync(state_out->data(), st, sizeof(SysState) * k.nsys,
                               hipMemcpyDeviceToHost, s));
   LQCD_HIP_TRY(hipStreamSynchronize(s));
+  timing_resolve();  // launches after the last flag read belong to this solve
   if (f.error) {
     set_error("solver hit a non-finite value or non-positive curvature");
     return LQCD_ERR_NUMERIC;
@@ -1219,15 +1501,15 @@ int check_params(const lqcd_solver_params* p) {
     set_error("rhs_block = %d must be 0, 1, 2, 4 or 8", p->rhs_block);
     return LQCD_ERR_INVALID_ARG;
   }
+  if (p->shift_window < 1 || p->shift_window > kMaxWin) {
+    set_error("shift_window = %d must be in [1, %d]", p->shift_window, kMaxWin);
+    return LQCD_ERR_INVALID_ARG;
+  }
   if (p->poll_interval < 0 || p->max_refine < 0) {
     set_error("poll_interval and max_refine must be >= 0");
     return LQCD_ERR_INVALID_ARG;
   }
   return LQCD_OK;
-}
-
-int poll_for(const lqcd_solver_params& p) {
-  return p.poll_interval > 0 ? p.poll_interval : (p.inner_prec == LQCD_F32 ? 10 : 50);
 }
 
 // Shared driver of lqcd_cg (nshift = 1, x holds a guess) and lqcd_cg_multishift.
@@ -1387,8 +1669,13 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
       lqcd_solve_stats& o = stats[i];
       o.iters = main_state[j].iters;
       o.iters_fp64 = main_state[j].iters64;
+      o.shift_window = nshift > 1 ? c.L.win : 1;
       o.shift_updates_fp64 = main_state[j].upd64;
       o.shift_updates_fp32 = main_state[j].upd32;
+      o.flush_shifts_fp64 = main_state[j].fsh64;
+      o.flush_shifts_fp32 = main_state[j].fsh32;
+      o.flush_slots_fp64 = main_state[j].fsl64;
+      o.flush_slots_fp32 = main_state[j].fsl32;
       o.reliable_updates = main_state[j].nrel;
       o.refine_iters = refine_iters[i];
       o.true_rel_residual = bn > 0 ? std::sqrt(res2[i] / bn) : std::sqrt(res2[i]);
@@ -1449,6 +1736,7 @@ void lqcd_solver_params_default(lqcd_solver_params* p) {
   p->rhs_block = 0;
   p->poll_interval = 0;
   p->max_refine = 3;
+  p->shift_window = 10;
   p->reliable_delta = 1e-3;
   p->mixed_switch = 1e-3;
 }
@@ -1485,6 +1773,11 @@ int lqcd_kernel_timing_enable(int32_t on) {
   if (on) {
     T().acc.clear();
     T().order.clear();
+    for (auto& pe : T().pending) {  // unresolved launches of an earlier solve
+      T().pool.push_back(pe.a);
+      T().pool.push_back(pe.b);
+    }
+    T().pending.clear();
   }
   return LQCD_OK;
 }

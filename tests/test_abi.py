@@ -111,13 +111,22 @@ def test_solver_parameter_validation(lq):
     assert lq.solver_workspace_bytes(g, p, 12, 8) > 0
     for bad in [dict(mass=0.0), dict(mass=-1.0), dict(tol=0.0), dict(tol=1.5), dict(max_iter=0),
                 dict(inner_prec=3), dict(inner_fmt=5), dict(rhs_block=3), dict(use_graph=2),
-                dict(inner_prec=1, reliable_interval=0), dict(max_refine=-1)]:
+                dict(inner_prec=1, reliable_interval=0), dict(max_refine=-1),
+                dict(shift_window=0), dict(shift_window=32)]:
         kw = dict(mass=0.1)
         kw.update(bad)
         q = lq.solver_params(**kw)
         assert lq.solver_workspace_bytes(g, q, 1, 1) == 0, bad
     assert lq.solver_workspace_bytes(g, p, 0, 1) == 0
     assert lq.solver_workspace_bytes(g, p, 33, 1) == 0
+    # deferred shift updates keep the window's residuals: W FP64 vectors per
+    # right-hand side beyond the per-iteration layout (W = 10 divides poll 50)
+    assert p.shift_window == 10
+    p1 = lq.solver_params(mass=0.1, shift_window=1)
+    vec = 3 * g.Vh * 16
+    extra = lq.solver_workspace_bytes(g, p, 12, 8) - lq.solver_workspace_bytes(g, p1, 12, 8)
+    assert extra >= 8 * (10 + 1) * vec
+    assert lq.solver_workspace_bytes(g, p, 1, 8) == lq.solver_workspace_bytes(g, p1, 1, 8)
     assert lq.solver_workspace_bytes(g, p, 1, 65) == 0
     # a too-small workspace is reported before any device work
     stats = (lq.SolveStats * 1)()

@@ -236,13 +236,64 @@ def test_kernel_timing_instrumentation(lq):
     lq.kernel_timing(False)
     kt = lq.kernel_timing()
     assert torch.equal(Xg, Xt)
-    n64 = kt["ms_update_f64_n2"][0]
-    n32 = kt["ms_update_f32_n2"][0]
+    # deferred shift updates: K5 forms the base direction, K6 flushes each window
+    n64 = kt["base_update_f64_n2"][0]
+    n32 = kt["base_update_f32_n2"][0]
     it64 = st[0][0]["iters_fp64"]
     # launches come in blocks of the poll interval, so there can be a few more than iterations
     assert n64 >= it64 and n32 >= st[0][0]["iters"] - it64
     assert kt["dslash_oe_f64_n2"][0] == n64 and kt["dslash_eo_cg_f32_n2"][0] == n32
+    w = st[0][0]["shift_window"]
+    assert w == 10
+    # one scheduled flush per window, plus the forced ones at phase ends and reliable updates
+    assert kt["ms_flush_f64_n2"][0] >= n64 // w and kt["ms_flush_f32_n2"][0] >= n32 // w
     assert all(ms > 0 for _, ms in kt.values())
+    # the per-iteration shift update is back with shift_window = 1
+    p1 = lq.solver_params(mass=0.1, tol=1e-10, inner_prec=1, inner_fmt=1, shift_window=1)
+    lq.kernel_timing(True)
+    X1, _, s1 = lq.cg_multishift(g, p1, U64, sig, b)
+    lq.kernel_timing(False)
+    kt1 = lq.kernel_timing()
+    assert "ms_update_f32_n2" in kt1 and "ms_flush_f32_n2" not in kt1
+    assert s1[0][0]["shift_window"] == 1 and s1[0][0]["flush_slots_fp32"] == 0
+    assert (X1 - Xt).abs().max().item() / Xt.abs().max().item() < 1e-6
     lq.kernel_timing(True)
     assert lq.kernel_timing() == {}
     lq.kernel_timing(False)
+
+
+@pytest.mark.parametrize("mode", MODES[:2])
+@pytest.mark.parametrize("window,poll", [(1, 0), (10, 0), (7, 0), (4, 6), (31, 31)])
+def test_deferred_shift_updates_match(lq, mode, window, poll):
+    """Deferred shift updates (x_s, p_s kept as combinations of the window's
+    base residuals, Sec. 2 recurrences regrouped) reach every shift's true
+    residual bar for any window length, including ones that are not a divisor
+    of the poll interval (reduced to one) and the longest window; every
+    iteration's residual is combined by exactly one flush."""
+    L = (6, 4, 4, 8)
+    m = 0.03
+    U = synth.links_haar(L, 110)
+    g, U64, b_nat, b = setup(lq, L, U, 210, 2)
+    sig = synth.rational_shifts(7, 1e-4, 3.0)
+    p = lq.solver_params(mass=m, tol=1e-10, shift_window=window, poll_interval=poll, **mode)
+    X, st, stats = lq.cg_multishift(g, p, U64, sig, b)
+    assert st == 0
+    Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(2, len(sig), -1, 3)
+    pol = poll if poll else (10 if mode["inner_prec"] == 1 else 50)
+    w_expect = max(d for d in range(1, min(window, 31) + 1) if pol % d == 0)
+    for j in range(2):
+        for s, sg in enumerate(sig):
+            assert oracle.true_residual(L, U, m, sg, b_nat[j], Xn[j, s]) <= 1e-10, (j, s)
+        r = stats[j][0]
+        assert r["shift_window"] == w_expect
+        if w_expect > 1:
+            assert r["flush_slots_fp64"] + r["flush_slots_fp32"] == r["iters"]
+            assert r["flush_shifts_fp64"] + r["flush_shifts_fp32"] <= (
+                r["shift_updates_fp64"] + r["shift_updates_fp32"])
+            assert r["flush_shifts_fp64"] >= r["flush_slots_fp64"] // w_expect
+        else:
+            assert r["flush_slots_fp64"] == r["flush_slots_fp32"] == 0
+    Xo, _, _, _ = oracle.cg_multishift(L, U, m, sig, b_nat[0], tol=1e-12)
+    for s in range(len(sig)):
+        assert H.max_rel(Xn[0, s], Xo[s]) < 1e-7
+
