@@ -47,9 +47,11 @@ int check_geom(const lqcd_geom* g) {
     }
     V *= n;
   }
-  if (V / 2 >= (int64_t(1) << 31) / 2) {
-    // half indices and offsets up to 2*Vh stay in int32
-    set_error("lattice too large: V/2 = %lld must be < 2^30", (long long)(V / 2));
+  if ((V / 2) * 144 >= (int64_t(1) << 32)) {
+    // byte offsets inside one [9][Vh] FP64 link block (the stencil's buffer
+    // loads) stay in uint32
+    set_error("lattice too large: V/2 = %lld must be below 2^32 / 144 = %lld", (long long)(V / 2),
+              (long long)(((int64_t(1) << 32) - 1) / 144));
     return LQCD_ERR_INVALID_ARG;
   }
   if (g->antiperiodic_t != 0 && g->antiperiodic_t != 1) {

@@ -35,10 +35,12 @@ template <typename R>
 __device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
 template <typename R>
 __device__ __forceinline__ cplx<R> cscale(R s, cplx<R> a) { return mk<R>(s * a.x, s * a.y); }
-// a * b
+// a * b, with the fused multiply-adds written out so that every kernel
+// instantiation rounds the same way (right-hand-side batching is bitwise
+// neutral)
 template <typename R>
 __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
-  return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return mk<R>(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 // conj(a) * b
 template <typename R>
@@ -59,7 +61,7 @@ __device__ __forceinline__ void cfmac(cplx<R>& acc, cplx<R> a, cplx<R> b) {
 }
 template <typename R>
 __device__ __forceinline__ double cnorm2(cplx<R> a) {
-  return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+  return fma((double)a.x, (double)a.x, (double)a.y * (double)a.y);
 }
 
 // ----------------------------------------------------------------- geometry

@@ -91,47 +91,108 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
     const int64_t par_stride = int64_t(4) * NE * g.Vh;
     const cplx<R>* Uout = static_cast<const cplx<R>*>(a.U) + a.out_par * par_stride;
     const cplx<R>* Uin = static_cast<const cplx<R>*>(a.U) + (1 - a.out_par) * par_stride;
-    const cplx<R>* in = static_cast<const cplx<R>*>(a.in) + int64_t(rhs0) * a.in_stride;
-
+    constexpr uint32_t cb = sizeof(cplx<R>);
+    const uint32_t link_bytes = uint32_t(NE) * uint32_t(g.Vh) * cb;
+    // Input rows of the block's right-hand sides; rows past nrhs alias the
+    // last one (loaded and computed, never stored), so the loads of every
+    // right-hand side issue together without a branch between them.
+    __amdgpu_buffer_rsrc_t rin[B];
 #pragma unroll
+    for (int b = 0; b < B; ++b)
+      rin[b] = make_res(static_cast<const cplx<R>*>(a.in) +
+                            int64_t(rhs0 + b < a.nrhs ? rhs0 + b : a.nrhs - 1) * a.in_stride,
+                        3u * uint32_t(g.Vh) * cb);
+    const uint32_t csoff = uint32_t(g.Vh) * cb;  // colour stride in bytes
+
+    // One direction per iteration (not unrolled: an unrolled body lets the
+    // compiler hoist every direction's loads at once and run out of
+    // registers).  Each iteration first issues all of its loads -- both links
+    // and both neighbours of every right-hand side -- so one memory round
+    // trip serves the whole iteration, then does the arithmetic.
+#pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
-      R cf = R(0.5 * eta[mu]), cb = cf;
+      R cf = R(0.5 * eta[mu]), cb_ = cf;
       if (mu == 3 && g.anti) {
         if (s.t == g.Lt - 1) cf = -cf;  // link (x, t) crosses the time boundary
-        if (s.t == 0) cb = -cb;         // link (x - t, t) crosses it
+        if (s.t == 0) cb_ = -cb_;       // link (x - t, t) crosses it
       }
-      {
-        Su3<R> u;
-        load_link<R, NE, NT>(Uout + int64_t(mu) * NE * g.Vh, h, g.Vh, u);
+      const int nf = fwd[mu], nb = bwd[mu];
+      Su3<R> uf, ub;
+      cplx<R> vf[B][3], vb[B][3];
+      if (NT) {
+        load_link<R, NE, NT>(Uout + int64_t(mu) * NE * g.Vh, h, g.Vh, uf);
+        load_link<R, NE, NT>(Uin + int64_t(mu) * NE * g.Vh, nb, g.Vh, ub);
+      } else {
+        const __amdgpu_buffer_rsrc_t rf =
+            make_res(Uout + int64_t(mu) * NE * g.Vh, link_bytes);
+        const __amdgpu_buffer_rsrc_t rb = make_res(Uin + int64_t(mu) * NE * g.Vh, link_bytes);
+        const uint32_t of = uint32_t(h) * cb, ob = uint32_t(nb) * cb;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-          if (!lv[b]) continue;
-          cplx<R> v[3], y[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) v[c] = in[b * a.in_stride + int64_t(c) * g.Vh + fwd[mu]];
-          mat_vec<R>(u, v, y);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            acc[b][c].x = fma(cf, y[c].x, acc[b][c].x);
-            acc[b][c].y = fma(cf, y[c].y, acc[b][c].y);
-          }
+        for (int e = 0; e < NE; ++e) {
+          uf.e[e] = ld_buf<R>(rf, of, uint32_t(e) * csoff);
+          ub.e[e] = ld_buf<R>(rb, ob, uint32_t(e) * csoff);
         }
       }
       {
-        Su3<R> u;
-        load_link<R, NE, NT>(Uin + int64_t(mu) * NE * g.Vh, bwd[mu], g.Vh, u);
+        const uint32_t of = uint32_t(nf) * cb, ob = uint32_t(nb) * cb;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-          if (!lv[b]) continue;
-          cplx<R> v[3], y[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) v[c] = in[b * a.in_stride + int64_t(c) * g.Vh + bwd[mu]];
-          adj_mat_vec<R>(u, v, y);
+        for (int b = 0; b < B; ++b)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            acc[b][c].x = fma(-cb, y[c].x, acc[b][c].x);
-            acc[b][c].y = fma(-cb, y[c].y, acc[b][c].y);
+            vf[b][c] = ld_buf<R>(rin[b], of, uint32_t(c) * csoff);
+            vb[b][c] = ld_buf<R>(rin[b], ob, uint32_t(c) * csoff);
           }
+      }
+      if (NE == 6 && !NT) {
+        reconstruct_row2<R>(uf);
+        reconstruct_row2<R>(ub);
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        cplx<R> y[3];
+        mat_vec<R>(uf, vf[b], y);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc[b][c].x = fma(cf, y[c].x, acc[b][c].x);
+          acc[b][c].y = fma(cf, y[c].y, acc[b][c].y);
+        }
+        adj_mat_vec<R>(ub, vb[b], y);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc[b][c].x = fma(-cb_, y[c].x, acc[b][c].x);
+          acc[b][c].y = fma(-cb_, y[c].y, acc[b][c].y);
+        }
+      }
+      // FP32: schedule every load of the iteration first, then the
+      // arithmetic (for FP64 the registers this holds cost more occupancy
+      // than the extra loads in flight gain)
+      if (sizeof(R) == 4) {
+        __builtin_amdgcn_sched_group_barrier(0x020, 2 * NE + 6 * B, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 4096, 0);
+      }
+    }
+
+    // Own-site operands of the fused update for every right-hand side of the
+    // block, loaded before any is used (rows past nrhs alias the last one),
+    // so that their latencies overlap instead of adding up per RHS.
+    cplx<R> dv[B][3], rv[B][3];
+    double2 bv[B][3];
+    if (MODE != DM_PLAIN) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int jl = rhs0 + b < a.nrhs ? rhs0 + b : a.nrhs - 1;
+        const cplx<R>* d = static_cast<const cplx<R>*>(a.diag) + int64_t(jl) * a.diag_stride + h;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dv[b][c] = d[int64_t(c) * g.Vh];
+        if (MODE == DM_CG) {
+          const cplx<R>* r = static_cast<const cplx<R>*>(a.r) + int64_t(jl) * a.r_stride + h;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) rv[b][c] = r[int64_t(c) * g.Vh];
+        }
+        if (MODE == DM_RES) {
+          const double2* bp = static_cast<const double2*>(a.b) + int64_t(jl) * a.b_stride + h;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) bv[b][c] = bp[int64_t(c) * g.Vh];
         }
       }
     }
@@ -149,40 +210,33 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
         }
       } else {
         const double m2s = a.m2s ? a.m2s[j * a.m2s_stride] : a.m2s_c;
-        const cplx<R>* d = static_cast<const cplx<R>*>(a.diag) + int64_t(j) * a.diag_stride + h;
         if (MODE == DM_AXPY) {
           cplx<R>* out = static_cast<cplx<R>*>(a.out) + int64_t(j) * a.out_stride + h;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const cplx<R> dv = d[int64_t(c) * g.Vh];
-            out[int64_t(c) * g.Vh] =
-                mk<R>(fma(R(m2s), dv.x, -acc[b][c].x), fma(R(m2s), dv.y, -acc[b][c].y));
-          }
+          for (int c = 0; c < 3; ++c)
+            out[int64_t(c) * g.Vh] = mk<R>(fma(R(m2s), dv[b][c].x, -acc[b][c].x),
+                                           fma(R(m2s), dv[b][c].y, -acc[b][c].y));
         } else if (MODE == DM_CG) {
           const R al = R(a.alpha[j * a.alpha_stride]);
           cplx<R>* r = static_cast<cplx<R>*>(a.r) + int64_t(j) * a.r_stride + h;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const cplx<R> dv = d[int64_t(c) * g.Vh];
-            const R wx = fma(R(m2s), dv.x, -acc[b][c].x);
-            const R wy = fma(R(m2s), dv.y, -acc[b][c].y);
-            cplx<R> rv = r[int64_t(c) * g.Vh];
-            rv.x = fma(-al, wx, rv.x);
-            rv.y = fma(-al, wy, rv.y);
-            r[int64_t(c) * g.Vh] = rv;
-            nrm[b] += cnorm2<R>(rv);
+            const R wx = fma(R(m2s), dv[b][c].x, -acc[b][c].x);
+            const R wy = fma(R(m2s), dv[b][c].y, -acc[b][c].y);
+            cplx<R> rn = rv[b][c];
+            rn.x = fma(-al, wx, rn.x);
+            rn.y = fma(-al, wy, rn.y);
+            r[int64_t(c) * g.Vh] = rn;
+            nrm[b] += cnorm2<R>(rn);
           }
         } else {  // DM_RES, R = double
-          const double2* bv = static_cast<const double2*>(a.b) + int64_t(j) * a.b_stride + h;
           cplx<RO>* r = a.r ? static_cast<cplx<RO>*>(a.r) + int64_t(j) * a.r_stride + h : nullptr;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const cplx<R> dv = d[int64_t(c) * g.Vh];
-            const double2 bb = bv[int64_t(c) * g.Vh];
-            const double rx = bb.x - fma(m2s, (double)dv.x, -(double)acc[b][c].x);
-            const double ry = bb.y - fma(m2s, (double)dv.y, -(double)acc[b][c].y);
+            const double rx = bv[b][c].x - fma(m2s, (double)dv[b][c].x, -(double)acc[b][c].x);
+            const double ry = bv[b][c].y - fma(m2s, (double)dv[b][c].y, -(double)acc[b][c].y);
             if (r) r[int64_t(c) * g.Vh] = mk<RO>(RO(rx), RO(ry));
-            nrm[b] += rx * rx + ry * ry;
+            nrm[b] += fma(rx, rx, ry * ry);
           }
         }
       }
@@ -321,8 +375,7 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
       return LQCD_OK;
     }
   }
-  const TuneKey key{c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, c.prec, c.fmt, c.nrhs, forced,
-                    c.mode == DM_RES ? 1 : 0};
+  const TuneKey key{c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, c.prec, c.fmt, c.nrhs, forced, c.mode};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -337,8 +390,9 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     return LQCD_OK;
   }
 
-  // Candidates are timed in plain mode on private scratch fields with the
-  // caller's links, so no caller data is touched.
+  // Candidates are timed in the caller's mode (the fused CG update with its
+  // own-site loads, or plain) with FP64 norm partials, on private scratch
+  // fields and the caller's links, so no caller data is touched.
   // Stage 1: workgroup size, RHS block, XCD remap, traversal.  Stage 2: the
   // three fastest of stage 1 with streaming link loads and occupancy caps.
   std::vector<DslashCfg> cand;
@@ -356,24 +410,40 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     }
 
   const size_t vec = size_t(3) * c.g.Vh * 2 * (c.prec == LQCD_F32 ? 4 : 8);
+  const bool cg = c.mode == DM_CG;
+  // [in][out or r][diag][partials][alpha]
+  const size_t fields = (cg ? 3 : 2) * vec * c.nrhs;
+  const size_t npart = dslash_partials_max(c.g, c.nrhs);
+  const size_t sbytes = fields + npart * 8 + size_t(c.nrhs) * 8;
   void* scratch = nullptr;
   LQCD_HIP_TRY(hipStreamSynchronize(st));
-  LQCD_HIP_TRY(hipMalloc(&scratch, 2 * vec * c.nrhs));
-  // non-zero data (0x3f bytes: ~0.75 in FP32, ~5e-4 in FP64) so timings match real fields
-  LQCD_HIP_TRY(hipMemsetAsync(scratch, 0x3f, 2 * vec * c.nrhs, st));
+  LQCD_HIP_TRY(hipMalloc(&scratch, sbytes));
+  // non-zero data (0x3f bytes: ~0.75 in FP32, ~3e-4 in FP64, also the CG step
+  // length) so timings match real fields and the CG update stays finite
+  LQCD_HIP_TRY(hipMemsetAsync(scratch, 0x3f, sbytes, st));
   hipEvent_t e0, e1;
   LQCD_HIP_TRY(hipEventCreate(&e0));
   LQCD_HIP_TRY(hipEventCreate(&e1));
 
   DslashCall t = c;
-  t.mode = DM_PLAIN;
+  t.mode = cg ? DM_CG : DM_PLAIN;
   t.in = scratch;
   t.in_stride = int64_t(3) * c.g.Vh;
   t.out = static_cast<char*>(scratch) + vec * c.nrhs;
   t.out_stride = int64_t(3) * c.g.Vh;
+  if (cg) {
+    t.r = t.out;
+    t.r_stride = t.out_stride;
+    t.diag = static_cast<char*>(scratch) + 2 * vec * c.nrhs;
+    t.diag_stride = int64_t(3) * c.g.Vh;
+    t.m2s = nullptr;
+    t.m2s_c = 0.01;
+    t.alpha = reinterpret_cast<const double*>(static_cast<char*>(scratch) + fields + npart * 8);
+    t.alpha_stride = 1;
+  }
   t.live = nullptr;
   t.halt = nullptr;
-  t.partials = nullptr;
+  t.partials = reinterpret_cast<double*>(static_cast<char*>(scratch) + fields);
   t.prec = c.prec;
   t.fmt = c.fmt;
   if (c.mode == DM_RES) {  // the residual kernels run on FP64 18-real links

@@ -35,6 +35,33 @@ __device__ __forceinline__ cplx<R> load_nt(const cplx<R>* p) {
   return mk<R>(v.x, v.y);
 }
 
+// Buffer resources: a scalar 64-bit base and byte range for a whole array
+// block, so that each load needs one 32-bit per-lane offset (shared by every
+// element and colour) plus a scalar offset.  Reads outside [0, bytes) return
+// zero instead of touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_res(const void* base, uint32_t bytes) {
+  // dword 3 of the descriptor for untyped 32-bit access on CDNA
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+// Link with half index h from a packed [NE][Vh] block held by resource r.
+template <typename R, int NE>
+__device__ __forceinline__ void load_link_buf(__amdgpu_buffer_rsrc_t r, int h, int Vh, Su3<R>& u) {
+  constexpr uint32_t cb = sizeof(cplx<R>);
+  const uint32_t voff = uint32_t(h) * cb;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) u.e[e] = ld_buf<R>(r, voff, uint32_t(e) * uint32_t(Vh) * cb);
+  if (NE == 6) reconstruct_row2<R>(u);
+}
+
 // Load the link with half index h from a packed [NE][Vh] block; NT selects
 // streaming loads (every link is read once per application).
 template <typename R, int NE, int NT = 0>

@@ -86,6 +86,21 @@ def test_bad_geometry_is_rejected_before_device_work(lq, L):
     assert "extent" in lq.last_error()
 
 
+def test_lattice_size_limit(lq):
+    """Byte offsets inside one FP64 18-real link block ([9][Vh] x 16 B) are
+    32-bit: 144 Vh must stay below 2^32."""
+    g = lq.lqcd_geom()
+    for i, n in enumerate((96, 96, 96, 96)):  # Vh = 42467328
+        g.L[i] = n
+    assert lq._fn("lqcd_links_bytes")(ctypes.byref(g), 0, 0) == 0
+    st = lq._fn("lqcd_doe")(ctypes.byref(g), 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(32),
+                           ctypes.c_void_p(48), 1, None)
+    assert st == lq.ERR_INVALID_ARG and "too large" in lq.last_error()
+    for i, n in enumerate((64, 64, 64, 112)):  # Vh = 14680064
+        g.L[i] = n
+    assert lq._fn("lqcd_links_bytes")(ctypes.byref(g), 0, 0) == 2 * 4 * 9 * 16 * 14680064
+
+
 def test_bad_arguments_are_rejected(lq):
     g = lq.Geometry((4, 4, 4, 4))
     fn = lq._fn("lqcd_doe")
@@ -120,12 +135,12 @@ def test_solver_parameter_validation(lq):
     assert lq.solver_workspace_bytes(g, p, 0, 1) == 0
     assert lq.solver_workspace_bytes(g, p, 33, 1) == 0
     # deferred shift updates keep the window's residuals: W FP64 vectors per
-    # right-hand side beyond the per-iteration layout (W = 10 divides poll 50)
-    assert p.shift_window == 10
+    # right-hand side beyond the per-iteration layout (W = 20 divides poll 40)
+    assert p.shift_window == 20
     p1 = lq.solver_params(mass=0.1, shift_window=1)
     vec = 3 * g.Vh * 16
     extra = lq.solver_workspace_bytes(g, p, 12, 8) - lq.solver_workspace_bytes(g, p1, 12, 8)
-    assert extra >= 8 * (10 + 1) * vec
+    assert extra >= 8 * (20 + 1) * vec
     assert lq.solver_workspace_bytes(g, p, 1, 8) == lq.solver_workspace_bytes(g, p1, 1, 8)
     assert lq.solver_workspace_bytes(g, p, 1, 65) == 0
     # a too-small workspace is reported before any device work
