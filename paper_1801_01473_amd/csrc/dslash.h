@@ -55,6 +55,8 @@ struct DslashCfg {
   int ilv = 0;      // 1: the RHS groups of one site block are consecutive workgroups (links
                     // then come from L2 after the first group, and fewer distinct sites are
                     // in flight); 0: RHS groups along the second grid dimension
+  int lf = 0;       // 1: every load of a direction is scheduled before its arithmetic (more
+                    // loads in flight per wave, more registers held); buffer loads only
 };
 
 // Dynamic LDS a workgroup reserves so that at most occ waves per SIMD are resident.
