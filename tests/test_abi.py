@@ -170,3 +170,16 @@ def test_force_and_action_validation(lq):
     a = lq._fn("lqcd_action")
     assert a(g.c(), 1, 2, 0.0, al, v(256), v(512), ctypes.byref(S), v(1024), 8,
              None) == lq.ERR_WORKSPACE
+
+
+def test_bench_traffic_record_is_tied_to_the_profiled_sources():
+    """The bench reports the dominant kernel's counter traffic only for the
+    kernel class that was profiled and only while the stencil sources hash to
+    the profiled ones."""
+    import json
+    import bench
+    rec = json.load(open(os.path.join(ROOT, "profiles", "dominant_kernel_traffic.json")))
+    assert rec["read_bytes_per_launch"] > 0 and rec["write_bytes_per_launch"] > 0
+    assert bench.measured_traffic("not_the_profiled_kernel") is None
+    got = bench.measured_traffic(rec["kernel_class"])
+    assert got is None or got == rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
