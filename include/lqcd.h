@@ -170,6 +170,9 @@ typedef struct {
     double reliable_delta;     /* mixed: also update when |r| fell by this factor    */
     double mixed_switch;       /* mixed multi-shift: iterate in FP64 until |r| <=
                                   mixed_switch |b|, then in FP32 (0: FP32 throughout) */
+    double inner_tol_factor;   /* the main iteration stops, and freezes shifts, at
+                                  inner_tol_factor * tol (0 < f <= 1); every system is
+                                  still verified against tol and refined if above it */
 } lqcd_solver_params;
 
 typedef struct {
@@ -192,7 +195,7 @@ typedef struct {
 
 /* Fills p with defaults: tol 1e-10, max_iter 10000, F64 inner, LINKS18,
  * reliable_interval 100, use_graph 1, rhs_block 0, poll 0, max_refine 3,
- * shift_window 20, reliable_delta 1e-3, mixed_switch 1e-3. */
+ * shift_window 20, reliable_delta 1e-3, mixed_switch 1e-3, inner_tol_factor 0.7. */
 void lqcd_solver_params_default(lqcd_solver_params *p);
 
 /* Device workspace that lqcd_cg / lqcd_cg_multishift need for these sizes. */

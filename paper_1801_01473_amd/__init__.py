@@ -59,7 +59,7 @@ class SolverParams(ctypes.Structure):
         ("rhs_block", ctypes.c_int32), ("poll_interval", ctypes.c_int32),
         ("max_refine", ctypes.c_int32), ("shift_window", ctypes.c_int32),
         ("reliable_delta", ctypes.c_double),
-        ("mixed_switch", ctypes.c_double),
+        ("mixed_switch", ctypes.c_double), ("inner_tol_factor", ctypes.c_double),
     ]
 
 

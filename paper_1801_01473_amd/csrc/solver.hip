@@ -1488,6 +1488,10 @@ int check_params(const lqcd_solver_params* p) {
     set_error("mixed_switch = %g must be in [0, 1)", p->mixed_switch);
     return LQCD_ERR_INVALID_ARG;
   }
+  if (!(p->inner_tol_factor > 0.0 && p->inner_tol_factor <= 1.0)) {
+    set_error("inner_tol_factor = %g must be in (0, 1]", p->inner_tol_factor);
+    return LQCD_ERR_INVALID_ARG;
+  }
   if (p->inner_prec == LQCD_F32 && p->reliable_interval <= 0) {
     set_error("reliable_interval = %d must be > 0 for mixed precision", p->reliable_interval);
     return LQCD_ERR_INVALID_ARG;
@@ -1586,7 +1590,7 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
   k.guess = guess;
   k.b = static_cast<const double2*>(b);
   k.x = static_cast<double2*>(x);
-  k.tol = params->tol;
+  k.tol = params->tol * params->inner_tol_factor;
   k.poll = poll_for(c.p);
   std::vector<double> m2s(nrhs, c.m2 + sigma[base]);
   std::vector<double> delta(size_t(nrhs) * nshift);
@@ -1739,6 +1743,7 @@ void lqcd_solver_params_default(lqcd_solver_params* p) {
   p->shift_window = 20;
   p->reliable_delta = 1e-3;
   p->mixed_switch = 1e-3;
+  p->inner_tol_factor = 0.7;
 }
 
 size_t lqcd_solver_workspace_bytes(const lqcd_geom* g, const lqcd_solver_params* p,

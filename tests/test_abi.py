@@ -127,7 +127,8 @@ def test_solver_parameter_validation(lq):
     for bad in [dict(mass=0.0), dict(mass=-1.0), dict(tol=0.0), dict(tol=1.5), dict(max_iter=0),
                 dict(inner_prec=3), dict(inner_fmt=5), dict(rhs_block=3), dict(use_graph=2),
                 dict(inner_prec=1, reliable_interval=0), dict(max_refine=-1),
-                dict(shift_window=0), dict(shift_window=32)]:
+                dict(shift_window=0), dict(shift_window=32), dict(inner_tol_factor=0.0),
+                dict(inner_tol_factor=1.5)]:
         kw = dict(mass=0.1)
         kw.update(bad)
         q = lq.solver_params(**kw)
