@@ -77,17 +77,38 @@ def make_inputs(w):
 
 
 def event_time_ms(fn, reps):
+    """Median of `reps` individually event-timed launches after 3 warm-ups."""
     import torch
-    fn()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
+    for _ in range(3):
         fn()
-    e1.record()
-    e1.synchronize()
-    return e0.elapsed_time(e1) / reps
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    ts = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return ts[len(ts) // 2]
+
+
+def dslash_entry(lq, torch, g, Ul, prec, fmt, n, copy_gbs, label):
+    """Standalone D_oe: median launch time, algorithmic GB/s, GFLOP/s (570 per
+    output site and RHS; 'executed' adds the 12-real reconstruction, 336 per
+    site and link load)."""
+    cd = torch.complex128 if prec == lq.F64 else torch.complex64
+    x = torch.randn(n, 3, g.Vh, dtype=cd, device="cuda")
+    y = torch.empty_like(x)
+    ms = event_time_ms(lambda: lq.doe(g, Ul, x, out=y), 20)
+    byts = g.Vh * dslash_bytes_per_site(prec, fmt, n)
+    gbs = byts / (ms * 1e-3) / 1e9
+    flops = 570.0 * g.Vh * n
+    exe = flops + (336.0 * g.Vh if fmt == lq.LINKS12 else 0.0)
+    del x, y
+    return dict(what=label, us=1000 * ms, GBps=gbs, frac_hbm_peak=gbs / HBM_PEAK_GBS,
+                frac_stream_copy=gbs / copy_gbs, GFLOPs=flops / (ms * 1e-3) / 1e9,
+                executed_GFLOPs=exe / (ms * 1e-3) / 1e9)
 
 
 def dslash_bytes_per_site(prec, fmt, nrhs):
@@ -177,14 +198,63 @@ def measured_traffic(kernel_class):
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, budget_s=20.0):
+def config3_m2(lq, torch):
+    """Time-to-1e-10 on the 32^4 single-RHS configuration (links exp(0.5iH),
+    m = 0.02, the same 12 shifts): mixed FP32-12 with FP64 reliable updates vs
+    plain FP64 18-real, each after one untimed solve (tuning, graph capture)."""
+    w = WORKLOADS["c3"]
+    U, phi, sig, _ = make_inputs(w)
+    g = lq.Geometry(w["L"])
+    U64 = lq.pack_links(g, torch.from_numpy(U).to("cuda"))
+    b = lq.pack_spinor(g, torch.from_numpy(phi).to("cuda"), 0)
+    del U, phi
+    out = {}
+    for name, kw in (("mixed", dict(inner_prec=lq.F32, inner_fmt=lq.LINKS12)),
+                     ("fp64", dict(inner_prec=lq.F64, inner_fmt=lq.LINKS18))):
+        p = lq.solver_params(mass=w["mass"], tol=1e-10, **kw)
+        lq.cg_multishift(g, p, U64, sig, b)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, _, st = lq.cg_multishift(g, p, U64, sig, b)
+        torch.cuda.synchronize()
+        out[name] = dict(seconds=time.time() - t0, iters=st[0][0]["iters"],
+                         refine_iters=sum(s["refine_iters"] for s in st[0]),
+                         max_true_rel_residual=max(s["true_rel_residual"] for s in st[0]))
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    log(f"config 3 (32^4, 1 RHS): mixed {out['mixed']['seconds']:.3f} s, "
+        f"FP64 {out['fp64']['seconds']:.3f} s")
+    return out
+
+
+def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, X0=None, budget_s=20.0):
     """Oracle multi-shift CG timed on a bounded sample: a few iterations on one
     right-hand side of the same lattice, scaled to the GPU run's iteration
-    count and number of right-hand sides."""
+    count and number of right-hand sides.  Also times the oracle's D_oe on all
+    host threads and on one, and recomputes with the oracle the FP64 true
+    residual of the GPU's solutions for the first right-hand side (X0: natural
+    layout [nshift][V][3])."""
+    import numpy as np
     import oracle
     L = w["L"]
     threads = len(os.sched_getaffinity(0))
     oracle.set_threads(threads)
+    ts = []
+    for _ in range(3):
+        t0 = time.time()
+        oracle.doe(L, U, phi[0])
+        ts.append(time.time() - t0)
+    doe_all = sorted(ts)[1]
+    oracle.set_threads(1)
+    t0 = time.time()
+    oracle.doe(L, U, phi[0])
+    doe_one = time.time() - t0
+    oracle.set_threads(threads)
+    check = None
+    if X0 is not None:
+        tr = [oracle.true_residual(L, U, w["mass"], float(sg), phi[0], X0[s])
+              for s, sg in enumerate(sig)]
+        check = {"rhs": 0, "shifts": len(tr), "max_true_rel_residual": float(np.max(tr)),
+                 "all_below_1e-10": bool(np.max(tr) <= 1e-10)}
     t0 = time.time()
     oracle.cg_multishift(L, U, w["mass"], sig, phi[0], tol=1e-10, max_iter=1, verify=False)
     t1 = time.time() - t0
@@ -204,6 +274,8 @@ def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, budget_s=20.0):
                    f"GPU run's {gpu_iters_per_rhs} iterations per RHS x {w['nrhs']} RHS"),
         "seconds_per_iteration": per_iter,
         "estimated_solve_s": est_solve,
+        "doe_s": {"threads": threads, "all_threads": doe_all, "one_thread": doe_one},
+        "oracle_true_residual_check": check,
     }
 
 
@@ -336,26 +408,44 @@ def main():
         t64 = time.time() - t0
         fp64 = dict(seconds=t64, iters=it64, max_true_residual=max(tr64))
         log(f"FP64 sequential baseline: {t64:.3f} s")
+        # secondary context: each shift of the first RHS by its own plain FP64 CG
+        lq.cg(g, p64, U64, phi_p[0:1].contiguous(), sigma=float(sig[-1]))  # graph capture
+        torch.cuda.synchronize()
+        t0 = time.time()
+        cg_it = []
+        for sg in sig:
+            _, _, sc = lq.cg(g, p64, U64, phi_p[0:1].contiguous(), sigma=float(sg))
+            cg_it.append(sc[0]["iters"])
+        torch.cuda.synchronize()
+        fp64["per_shift_cg_1rhs_s"] = time.time() - t0
+        fp64["per_shift_cg_iters"] = cg_it
+        log(f"per-shift FP64 CG, 1 RHS: {fp64['per_shift_cg_1rhs_s']:.3f} s")
+        fp64["config3_32x4_1rhs"] = config3_m2(lq, torch)
 
     # D_oe bandwidth (standalone, HIP events), STREAM ceiling
     copy_gbs, triad_gbs = lq.stream_bandwidth(1 << 30, 20)
     U64 = state["U64"]
     dsl = {}
-    Uin = lq.convert_links(g, U64, lq.F64, lq.LINKS18, lq.F32, lq.LINKS12)
-    for name, (Ul, prec, fmt, n) in {
-            "fp64_18_1rhs": (U64, lq.F64, lq.LINKS18, 1),
-            "fp32_12_1rhs": (Uin, lq.F32, lq.LINKS12, 1),
-            f"fp32_12_{nrhs}rhs": (Uin, lq.F32, lq.LINKS12, nrhs)}.items():
-        cd = torch.complex128 if prec == lq.F64 else torch.complex64
-        x = torch.randn(n, 3, g.Vh, dtype=cd, device="cuda")
-        y = torch.empty_like(x)
-        ms = event_time_ms(lambda: lq.doe(g, Ul, x, out=y), 20)
-        byts = g.Vh * dslash_bytes_per_site(prec, fmt, n)
-        gbs = byts / (ms * 1e-3) / 1e9
-        flops = 570.0 * g.Vh * n
-        dsl[name] = dict(us=1000 * ms, GBps=gbs, frac_hbm_peak=gbs / HBM_PEAK_GBS,
-                         frac_stream_copy=gbs / copy_gbs, GFLOPs=flops / (ms * 1e-3) / 1e9)
-        del x, y
+    lat = "x".join(map(str, L))
+    for name, (prec, fmt, n) in {
+            "fp64_18_1rhs": (lq.F64, lq.LINKS18, 1),
+            "fp64_12_1rhs": (lq.F64, lq.LINKS12, 1),
+            "fp32_18_1rhs": (lq.F32, lq.LINKS18, 1),
+            "fp32_12_1rhs": (lq.F32, lq.LINKS12, 1),
+            f"fp32_12_{nrhs}rhs": (lq.F32, lq.LINKS12, nrhs),
+            f"fp64_12_{nrhs}rhs": (lq.F64, lq.LINKS12, nrhs)}.items():
+        Ul = U64 if (prec, fmt) == (lq.F64, lq.LINKS18) else lq.convert_links(
+            g, U64, lq.F64, lq.LINKS18, prec, fmt)
+        dsl[name] = dslash_entry(lq, torch, g, Ul, prec, fmt, n, copy_gbs,
+                                 f"{lat}, workload links, {n} RHS")
+        del Ul
+    # the paper-sized FP64 check at 32^4 (links 604 MB, above the 256 MB MALL)
+    g32 = lq.Geometry((32, 32, 32, 32))
+    U32 = lq.pack_links(g32, torch.randn(4, g32.V, 3, 3, dtype=torch.complex128,
+                                         device="cuda"))
+    dsl["fp64_18_1rhs_32x4"] = dslash_entry(lq, torch, g32, U32, lq.F64, lq.LINKS18, 1,
+                                            copy_gbs, "32^4, Gaussian 3x3 links (timing only)")
+    del U32
     kd = kernels[dominant]
     traffic = measured_traffic(dominant)
     roof = {
@@ -374,7 +464,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(w, U, phi, sig, int(round(np.mean(iters))))
+        X0 = lq.unpack_spinor(g, state["X"][0], 0).cpu().numpy()
+        cpu = cpu_baseline(w, U, phi, sig, int(round(np.mean(iters))), X0=X0)
+        del X0
 
     mixed_solve = float(np.median(solve_times))
     out = {
@@ -400,6 +492,9 @@ def main():
             "fp64_sequential_s": fp64["seconds"] if fp64 else None,
             "speedup_mixed_vs_fp64": (fp64["seconds"] / mixed_solve) if fp64 else None,
             "action_plus_force_s": float(np.median(force_times)),
+            "fp64_per_shift_cg_1rhs_s": fp64["per_shift_cg_1rhs_s"] if fp64 else None,
+            "fp64_per_shift_cg_iters": fp64["per_shift_cg_iters"] if fp64 else None,
+            "config3_32x4_1rhs": fp64["config3_32x4_1rhs"] if fp64 else None,
         },
         "solver": {"iters_per_rhs": iters,
                    "fp64_phase_iters_per_rhs": [row[0]["iters_fp64"] for row in stats],
