@@ -42,10 +42,10 @@ template <typename R>
 __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
   return mk<R>(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
-// conj(a) * b
+// conj(a) * b, rounded exactly as cmul(conj(a), b)
 template <typename R>
 __device__ __forceinline__ cplx<R> cmulc(cplx<R> a, cplx<R> b) {
-  return mk<R>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+  return mk<R>(fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -(a.y * b.x)));
 }
 // acc += a * b
 template <typename R>

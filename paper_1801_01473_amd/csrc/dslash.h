@@ -47,9 +47,10 @@ struct DslashCfg {
   int block = 256;  // threads per workgroup (64, 128, 256)
   int rhs_block = 1;  // right-hand sides sharing one link load (1, 2, 4, 8)
   int xcd = 1;      // XCD-contiguous block remap
-  int tz = 0;       // site traversal: 0 lexicographic; n > 0 walks z in tiles of n
-                    // with t inside the tile loop (shorter +-t reuse distance)
-  int nt = 0;       // 1: links loaded non-temporally (they are used once)
+  int tz = 0;       // site traversal: 0 lexicographic; n > 0 walks (y, z) tiles of ty rows
+                    // and tz slices with t inside the tile loop (shorter +-t reuse distance)
+  int ty = 0;       // y rows per tile (0: all of Ly); only with tz > 0
+  int nt = 0;       // 1: link loads marked non-temporal (each link is used once)
   int occ = 0;      // >0: cap resident waves per SIMD (dynamic LDS reservation), which
                     // shrinks the set of sites in flight so neighbours stay in L2
   int ilv = 0;      // 1: the RHS groups of one site block are consecutive workgroups (links
@@ -57,6 +58,8 @@ struct DslashCfg {
                     // in flight); 0: RHS groups along the second grid dimension
   int lf = 0;       // 1: every load of a direction is scheduled before its arithmetic (more
                     // loads in flight per wave, more registers held); buffer loads only
+  int hh = 0;       // 1: one hop (forward or backward) per loop iteration instead of both
+                    // of a direction: half the loads held, more waves; buffer loads only
 };
 
 // Dynamic LDS a workgroup reserves so that at most occ waves per SIMD are resident.

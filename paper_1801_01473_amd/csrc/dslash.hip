@@ -32,30 +32,41 @@ namespace lqcd {
 namespace {
 
 // Half index of the i-th site visited.  tz = 0: lexicographic (i = h).
-// tz > 0: x, y fastest, then z inside a tile of tz slices, then t, then the
-// z tile -- consecutive workgroups sweep t inside a thin z slab, so an input
-// site is reused as a +-t neighbour while still in L2.  Within a (z, t) plane
-// sites stay contiguous, so loads remain coalesced.
-__device__ __forceinline__ int site_of(const KGeom& g, int i, int tz) {
+// tz > 0: the (y, z) cross-section is cut into tiles of ty rows (ty = 0: all
+// Ly) and tz slices; inside a tile x and y run fastest, then z, then t, and
+// the tiles come last -- consecutive workgroups sweep t through one small
+// tile, so an input site is reused as a +-t neighbour (and as a y, z
+// neighbour inside the tile) while still in L2.  A tile row of one (z, t) is
+// a contiguous run of half indices, so loads stay coalesced.  A bijection on
+// [0, Vh) when ty divides Ly and tz divides Lz.
+__device__ __forceinline__ int site_of(const KGeom& g, int i, int tz, int ty) {
   if (tz == 0) return i;
-  const int xy = g.Lxh * g.Ly;
-  const int inplane = i % xy;
-  int r = i / xy;
+  const int tyy = ty ? ty : g.Ly;
+  const int row = g.Lxh * tyy;
+  const int inrow = i % row;  // x and y inside the tile
+  int r = i / row;
   const int zi = r % tz;
   r /= tz;
   const int t = r % g.Lt;
-  const int z = (r / g.Lt) * tz + zi;
-  return inplane + xy * (z + g.Lz * t);
+  const int tile = r / g.Lt;
+  const int nty = g.Ly / tyy;
+  const int y0 = (tile % nty) * tyy, z = (tile / nty) * tz + zi;
+  return inrow + g.Lxh * y0 + g.sz * z + g.st * t;
 }
 
-// V: bit 0 streams the links with non-temporal global loads, bit 1 schedules
+// V: bit 0 marks the link loads non-temporal (each link is read once; the
+// hint keeps L2 for the spinors that neighbours read again), bit 1 schedules
 // every load of a direction before its arithmetic (more loads in flight per
-// wave, more registers held).
+// wave, more registers held), bit 2 walks the eight hops one per iteration
+// (half the loads held per iteration, so more waves fit; the backward link is
+// conjugate-transposed in registers so that one product serves both).
 template <typename R, int NE, int B, int MODE, typename RO, int V>
 __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xcd, const int tz,
-                                                const int ngroups, const int ilv) {
-  constexpr int NT = V & 1;
+                                                const int ty, const int ngroups,
+                                                const int ilv) {
+  constexpr int LAUX = (V & 1) ? 2 : 0;  // buffer cache policy of link loads: 2 = nt
   constexpr bool LF = (V & 2) != 0;
+  constexpr bool HH = (V & 4) != 0;
   __shared__ double lds[B][4];
   if (a.halt && *a.halt) return;
   const KGeom& g = a.g;
@@ -75,7 +86,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
   if (!any) return;  // uniform over the block
 
   const int idx = blk * blockDim.x + threadIdx.x;
-  const int h = idx < a.g.Vh ? site_of(a.g, idx, tz) : idx;
+  const int h = idx < a.g.Vh ? site_of(a.g, idx, tz, ty) : idx;
   double nrm[B];
 #pragma unroll
   for (int b = 0; b < B; ++b) nrm[b] = 0.0;
@@ -109,6 +120,63 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
                         3u * uint32_t(g.Vh) * cb);
     const uint32_t csoff = uint32_t(g.Vh) * cb;  // colour stride in bytes
 
+    if (HH) {
+      // one hop per iteration: k = 2 mu + (0 forward, 1 backward)
+#pragma unroll 1
+      for (int k = 0; k < 8; ++k) {
+        const int mu = k >> 1;
+        const bool fw = (k & 1) == 0;
+        // neighbour and phase from the coordinates (a per-k table would be
+        // indexed dynamically and live in scratch)
+        int nbr;
+        if (mu == 0) {
+          const int xn = fw ? (s.x + 1 == g.Lx ? 0 : s.x + 1) : (s.x == 0 ? g.Lx - 1 : s.x - 1);
+          nbr = h - (s.x >> 1) + (xn >> 1);
+        } else {
+          const int L = mu == 1 ? g.Ly : (mu == 2 ? g.Lz : g.Lt);
+          const int st = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+          const int cm = mu == 1 ? s.y : (mu == 2 ? s.z : s.t);
+          nbr = fw ? h + (cm + 1 == L ? -(L - 1) * st : st) : h + (cm == 0 ? (L - 1) * st : -st);
+        }
+        const int ep = ((mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0)) & 1;
+        R c = ep ? R(-0.5) : R(0.5);
+        if (mu == 3 && g.anti && (fw ? s.t == g.Lt - 1 : s.t == 0)) c = -c;
+        if (!fw) c = -c;
+        Su3<R> u;
+        cplx<R> v[B][3];
+        const __amdgpu_buffer_rsrc_t rl =
+            make_res((fw ? Uout : Uin) + int64_t(mu) * NE * g.Vh, link_bytes);
+        const uint32_t ol = uint32_t(fw ? h : nbr) * cb, on = uint32_t(nbr) * cb;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) u.e[e] = ld_buf<R, LAUX>(rl, ol, uint32_t(e) * csoff);
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) v[b][cc] = ld_buf<R>(rin[b], on, uint32_t(cc) * csoff);
+        if (NE == 6) reconstruct_row2<R>(u);
+        if (!fw) {  // U^dag
+          Su3<R> t = u;
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) u.e[3 * i + j] = conj_of<R>(t.e[3 * j + i]);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          cplx<R> y[3];
+          mat_vec<R>(u, v[b], y);
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            acc[b][cc].x = fma(c, y[cc].x, acc[b][cc].x);
+            acc[b][cc].y = fma(c, y[cc].y, acc[b][cc].y);
+          }
+        }
+        if (LF) {
+          __builtin_amdgcn_sched_group_barrier(0x020, NE + 3 * B, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 4096, 0);
+        }
+      }
+    } else {
     // One direction per iteration (not unrolled: an unrolled body lets the
     // compiler hoist every direction's loads at once and run out of
     // registers).  Each iteration first issues all of its loads -- both links
@@ -124,18 +192,15 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
       const int nf = fwd[mu], nb = bwd[mu];
       Su3<R> uf, ub;
       cplx<R> vf[B][3], vb[B][3];
-      if (NT) {
-        load_link<R, NE, NT>(Uout + int64_t(mu) * NE * g.Vh, h, g.Vh, uf);
-        load_link<R, NE, NT>(Uin + int64_t(mu) * NE * g.Vh, nb, g.Vh, ub);
-      } else {
+      {
         const __amdgpu_buffer_rsrc_t rf =
             make_res(Uout + int64_t(mu) * NE * g.Vh, link_bytes);
         const __amdgpu_buffer_rsrc_t rb = make_res(Uin + int64_t(mu) * NE * g.Vh, link_bytes);
         const uint32_t of = uint32_t(h) * cb, ob = uint32_t(nb) * cb;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-          uf.e[e] = ld_buf<R>(rf, of, uint32_t(e) * csoff);
-          ub.e[e] = ld_buf<R>(rb, ob, uint32_t(e) * csoff);
+          uf.e[e] = ld_buf<R, LAUX>(rf, of, uint32_t(e) * csoff);
+          ub.e[e] = ld_buf<R, LAUX>(rb, ob, uint32_t(e) * csoff);
         }
       }
       {
@@ -148,7 +213,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
             vb[b][c] = ld_buf<R>(rin[b], ob, uint32_t(c) * csoff);
           }
       }
-      if (NE == 6 && !NT) {
+      if (NE == 6) {
         reconstruct_row2<R>(uf);
         reconstruct_row2<R>(ub);
       }
@@ -173,6 +238,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
         __builtin_amdgcn_sched_group_barrier(0x020, 2 * NE + 6 * B, 0);
         __builtin_amdgcn_sched_group_barrier(0x002, 4096, 0);
       }
+    }
     }
 
     // Own-site operands of the fused update for every right-hand side of the
@@ -266,15 +332,20 @@ int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     set_error("occupancy cap %d is below one workgroup of %d threads", cfg.occ, cfg.block);
     return LQCD_ERR_UNSUPPORTED;
   }
-  if (cfg.nt)
-    hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, 1>), grid, dim3(cfg.block), lds, st, c,
-                       cfg.xcd, cfg.tz, ngroups, ilv);
-  else if (cfg.lf)
-    hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, 2>), grid, dim3(cfg.block), lds, st, c,
-                       cfg.xcd, cfg.tz, ngroups, ilv);
-  else
-    hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, 0>), grid, dim3(cfg.block), lds, st, c,
-                       cfg.xcd, cfg.tz, ngroups, ilv);
+#define LQCD_K(V)                                                                         \
+  hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, V>), grid, dim3(cfg.block), lds, st, c, \
+                     cfg.xcd, cfg.tz, cfg.ty, ngroups, ilv)
+  switch ((cfg.nt ? 1 : 0) | (cfg.lf ? 2 : 0) | (cfg.hh ? 4 : 0)) {
+    case 0: LQCD_K(0); break;
+    case 1: LQCD_K(1); break;
+    case 2: LQCD_K(2); break;
+    case 3: LQCD_K(3); break;
+    case 4: LQCD_K(4); break;
+    case 5: LQCD_K(5); break;
+    case 6: LQCD_K(6); break;
+    default: LQCD_K(7); break;
+  }
+#undef LQCD_K
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
@@ -311,8 +382,9 @@ int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     set_error("unsupported dslash block size %d", cfg.block);
     return LQCD_ERR_UNSUPPORTED;
   }
-  if (cfg.tz < 0 || (cfg.tz > 0 && c.g.Lz % cfg.tz != 0)) {
-    set_error("z tile %d must divide Lz = %d", cfg.tz, c.g.Lz);
+  if (cfg.tz < 0 || (cfg.tz > 0 && c.g.Lz % cfg.tz != 0) || cfg.ty < 0 ||
+      (cfg.ty > 0 && c.g.Ly % cfg.ty != 0)) {
+    set_error("tile %d x %d (y, z) must divide Ly = %d, Lz = %d", cfg.ty, cfg.tz, c.g.Ly, c.g.Lz);
     return LQCD_ERR_UNSUPPORTED;
   }
   if (c.mode == DM_RES) {
@@ -371,12 +443,12 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     set_error("rhs_block must be 0 (tuned), 1, 2, 4 or 8, got %d", forced);
     return LQCD_ERR_INVALID_ARG;
   }
-  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf]" pins the configuration
+  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty]" pins the configuration
   // (testing, profiling)
   if (const char* e = std::getenv("LQCD_DSLASH_CFG")) {
     DslashCfg f;
-    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz, &f.nt,
-                    &f.occ, &f.ilv, &f.lf) >= 4) {
+    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz,
+                    &f.nt, &f.occ, &f.ilv, &f.lf, &f.hh, &f.ty) >= 4) {
       if (forced) f.rhs_block = forced;
       *out = f;
       return LQCD_OK;
@@ -400,8 +472,11 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   // Candidates are timed in the caller's mode (the fused CG update with its
   // own-site loads, or plain) with FP64 norm partials, on private scratch
   // fields and the caller's links, so no caller data is touched.
-  // Stage 1: workgroup size, RHS block, XCD remap, traversal.  Stage 2: the
-  // three fastest of stage 1 with streaming link loads and occupancy caps.
+  // Stage 1: workgroup size, RHS block, XCD remap, z-slab traversal, RHS
+  // interleave.  Stage 2: (y, z) tiles for the three fastest, with plain and
+  // non-temporal link loads.  Stage 3: the three fastest so far with the
+  // other schedules (loads first, one hop per iteration, non-temporal links)
+  // and occupancy caps.  Stage 4: the five fastest re-timed, best median.
   std::vector<DslashCfg> cand;
   for (int blk : {64, 128, 256})
     for (int b : {1, 2, 4, 8}) {
@@ -411,7 +486,14 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
           if (tz && (c.g.Lz % tz || tz >= c.g.Lz)) continue;
           for (int ilv : {0, 1}) {
             if (ilv && b >= c.nrhs) continue;  // a single RHS group has nothing to interleave
-            cand.push_back(DslashCfg{blk, b, x, tz, 0, 0, ilv, best.lf});
+            DslashCfg v = best;
+            v.block = blk;
+            v.rhs_block = b;
+            v.xcd = x;
+            v.tz = tz;
+            v.ty = 0;
+            v.ilv = ilv;
+            cand.push_back(v);
           }
         }
     }
@@ -480,52 +562,70 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   int rc = LQCD_OK;
   std::vector<std::pair<float, DslashCfg>> timed;
   const size_t stage1 = cand.size();
-  for (size_t ci = 0; ci < cand.size(); ++ci) {
+  size_t stage2 = size_t(-1);
+  auto top3 = [&]() {
+    std::vector<std::pair<float, DslashCfg>> s1 = timed;
+    std::sort(s1.begin(), s1.end(),
+              [](const std::pair<float, DslashCfg>& a, const std::pair<float, DslashCfg>& b) {
+                return a.first < b.first;
+              });
+    if (s1.size() > 3) s1.resize(3);
+    return s1;
+  };
+  for (size_t ci = 0; ci < cand.size() && rc == LQCD_OK; ++ci) {
     const DslashCfg cfg = cand[ci];
-    if (dslash_launch(t, cfg, st) != LQCD_OK) {  // warm-up; skip what cannot launch
-      clear_error();
-      continue;
-    }
     float ms = 0;
-    if (time_cfg(cfg, 3, &ms) != LQCD_OK) {
+    const bool runs = dslash_launch(t, cfg, st) == LQCD_OK;  // warm-up
+    if (!runs) clear_error();  // skip what cannot launch
+    if (runs && time_cfg(cfg, 3, &ms) != LQCD_OK) {
       set_error("dslash tuning run failed");
       rc = LQCD_ERR_HIP;
       break;
     }
-    timed.push_back({ms, cfg});
-    if (tuning_verbose())
+    if (runs) timed.push_back({ms, cfg});
+    if (runs && tuning_verbose())
       fprintf(stderr,
               "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d mode=%d block=%d B=%d xcd=%d "
-              "tz=%d nt=%d occ=%d ilv=%d lf=%d: %.2f us\n",
+              "ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d: %.2f us\n",
               c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, t.mode, cfg.block,
-              cfg.rhs_block, cfg.xcd, cfg.tz, cfg.nt, cfg.occ, cfg.ilv, cfg.lf, 1000.0 * ms);
-    if (ms < best_ms) {
+              cfg.rhs_block, cfg.xcd, cfg.ty, cfg.tz, cfg.nt, cfg.occ, cfg.ilv, cfg.lf, cfg.hh,
+              1000.0 * ms);
+    if (runs && ms < best_ms) {
       best_ms = ms;
       best = cfg;
     }
-    if (ci + 1 == stage1) {  // stage 2: the best three of stage 1, streamed / capped
-      std::vector<std::pair<float, DslashCfg>> s1 = timed;
-      std::sort(s1.begin(), s1.end(),
-                [](const std::pair<float, DslashCfg>& a, const std::pair<float, DslashCfg>& b) {
-                  return a.first < b.first;
-                });
-      for (size_t k = 0; k < s1.size() && k < 3; ++k)
-        for (int nt : {0, 1})
-          for (int lf : {0, 1})
-            for (int occ : {0, 2, 3, 4}) {
-              DslashCfg v = s1[k].second;
-              if (nt && lf) continue;  // non-temporal links are global loads, not scheduled
-              if (!nt && lf == v.lf && !occ) continue;  // stage 1 timed it
+    if (ci + 1 == stage1) {  // stage 2: (y, z) tiles of the best three
+      for (const auto& tk : top3())
+        for (int ty : {4, 8, 12, 16, 24})
+          for (int tz : {2, 4, 6, 8, 12})
+            for (int nt : {0, 1}) {
+              if (c.g.Ly % ty || ty >= c.g.Ly || c.g.Lz % tz || tz >= c.g.Lz) continue;
+              DslashCfg v = tk.second;
+              v.ty = ty;
+              v.tz = tz;
               v.nt = nt;
-              v.lf = lf;
-              v.occ = occ;
-              const int lds = dslash_lds_bytes(v);
-              if (lds < 0 || lds > 64 * 1024) continue;
               cand.push_back(v);
             }
+      stage2 = cand.size();
+    } else if (ci + 1 == stage2) {  // stage 3: schedules and occupancy caps
+      for (const auto& tk : top3())
+        for (int nt : {0, 1})
+          for (int lf : {0, 1})
+            for (int hh : {0, 1})
+              for (int occ : {0, 2, 3, 4}) {
+                DslashCfg v = tk.second;
+                if (nt == v.nt && lf == v.lf && hh == v.hh && occ == v.occ) continue;
+                v.nt = nt;
+                v.lf = lf;
+                v.hh = hh;
+                v.occ = occ;
+                const int lds = dslash_lds_bytes(v);
+                if (lds < 0 || lds > 64 * 1024) continue;
+                cand.push_back(v);
+              }
     }
   }
-  // Stage 3: single short timings are noisy and the minimum over ~200 of them
+  // Stage 4: single short timings are noisy and the minimum over ~200 of them
   // favours lucky ones; re-time the five fastest in interleaved rounds and
   // keep the best median.
   if (rc == LQCD_OK && timed.size() > 1) {
@@ -569,10 +669,10 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   if (tuning_verbose())
     fprintf(stderr,
             "[lqcd tune] chosen L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d mode=%d: block=%d B=%d "
-            "xcd=%d tz=%d nt=%d occ=%d ilv=%d lf=%d (%.2f us)\n",
+            "xcd=%d ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d (%.2f us)\n",
             c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, t.mode, best.block,
-            best.rhs_block, best.xcd, best.tz, best.nt, best.occ, best.ilv, best.lf,
-            1000.0 * best_ms);
+            best.rhs_block, best.xcd, best.ty, best.tz, best.nt, best.occ, best.ilv, best.lf,
+            best.hh, 1000.0 * best_ms);
   *out = best;
   return LQCD_OK;
 }

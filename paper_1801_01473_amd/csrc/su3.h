@@ -44,12 +44,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_res(const void* base, uin
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
 }
 
-template <typename R>
+// AUX: cache policy bits of the load (2: non-temporal)
+template <typename R, int AUX = 0>
 __device__ __forceinline__ cplx<R> ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(R) == 4)
-    return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
   else
-    return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
 }
 
 // Link with half index h from a packed [NE][Vh] block held by resource r.
