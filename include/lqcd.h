@@ -11,7 +11,9 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Geometry: extents L = {Lx, Ly, Lz, Lt} (direction mu = 0..3 is x, y, z, t),
- *   each even and >= 2; lex = x + Lx*(y + Ly*(z + Lz*t)); parity =
+ *   each even and >= 2, with 144 * V/2 < 2^32 (byte offsets inside one FP64
+ *   18-real link block fit 32 bits; e.g. 86^4 is the largest hypercube);
+ *   lex = x + Lx*(y + Ly*(z + Lz*t)); parity =
  *   (x+y+z+t) mod 2 (0 even, 1 odd); V = Lx*Ly*Lz*Lt; Vh = V/2.  Within one
  *   parity a site's half index is lex >> 1 (unique because Lx is even).
  *   Boundaries are periodic in x, y, z; time is antiperiodic when
@@ -134,6 +136,12 @@ int lqcd_unpack_spinor(const lqcd_geom *g, int parity, int prec, const void *pac
  * ([nrhs][3][Vh] each, precision prec) with links U_packed of (prec, fmt).
  * Each link is loaded once per site and reused across the right-hand sides.
  * 1 <= nrhs <= 64.  in and out must not overlap.
+ * Launch configuration: tuned on the first call for each (geometry,
+ * precision, format, nrhs, mode) and cached for the process; that first call
+ * allocates temporary scratch and synchronises the stream.  Environment:
+ * LQCD_TUNE=0 uses a fixed default instead, LQCD_TUNE_VERBOSE=1 prints the
+ * timings, LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty]"
+ * pins one configuration (testing and profiling).
  */
 int lqcd_doe(const lqcd_geom *g, int prec, int fmt, const void *U_packed,
              const void *in_even, void *out_odd, int32_t nrhs, void *stream);

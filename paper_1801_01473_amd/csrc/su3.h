@@ -23,18 +23,6 @@ __device__ __forceinline__ void reconstruct_row2(Su3<R>& u) {
   u.e[8] = conj_of<R>(csub<R>(cmul<R>(u.e[0], u.e[4]), cmul<R>(u.e[1], u.e[3])));
 }
 
-template <typename R> struct NativeVec2;
-template <> struct NativeVec2<float> { typedef float T __attribute__((ext_vector_type(2))); };
-template <> struct NativeVec2<double> { typedef double T __attribute__((ext_vector_type(2))); };
-
-// Non-temporal (streaming) load of one complex number: data read exactly once
-// should not evict data that neighbouring sites will read again.
-template <typename R>
-__device__ __forceinline__ cplx<R> load_nt(const cplx<R>* p) {
-  const auto v = __builtin_nontemporal_load(reinterpret_cast<const typename NativeVec2<R>::T*>(p));
-  return mk<R>(v.x, v.y);
-}
-
 // Buffer resources: a scalar 64-bit base and byte range for a whole array
 // block, so that each load needs one 32-bit per-lane offset (shared by every
 // element and colour) plus a scalar offset.  Reads outside [0, bytes) return
@@ -53,24 +41,12 @@ __device__ __forceinline__ cplx<R> ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t vof
     return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
 }
 
-// Link with half index h from a packed [NE][Vh] block held by resource r.
+// Load the link with half index h from a packed [NE][Vh] block.
 template <typename R, int NE>
-__device__ __forceinline__ void load_link_buf(__amdgpu_buffer_rsrc_t r, int h, int Vh, Su3<R>& u) {
-  constexpr uint32_t cb = sizeof(cplx<R>);
-  const uint32_t voff = uint32_t(h) * cb;
-#pragma unroll
-  for (int e = 0; e < NE; ++e) u.e[e] = ld_buf<R>(r, voff, uint32_t(e) * uint32_t(Vh) * cb);
-  if (NE == 6) reconstruct_row2<R>(u);
-}
-
-// Load the link with half index h from a packed [NE][Vh] block; NT selects
-// streaming loads (every link is read once per application).
-template <typename R, int NE, int NT = 0>
 __device__ __forceinline__ void load_link(const cplx<R>* __restrict__ base, int h, int Vh,
                                           Su3<R>& u) {
 #pragma unroll
-  for (int e = 0; e < NE; ++e)
-    u.e[e] = NT ? load_nt<R>(base + int64_t(e) * Vh + h) : base[int64_t(e) * Vh + h];
+  for (int e = 0; e < NE; ++e) u.e[e] = base[int64_t(e) * Vh + h];
   if (NE == 6) reconstruct_row2<R>(u);
 }
 

@@ -297,3 +297,24 @@ def test_deferred_shift_updates_match(lq, mode, window, poll):
     for s in range(len(sig)):
         assert H.max_rel(Xn[0, s], Xo[s]) < 1e-7
 
+
+
+def test_inner_tol_factor_margin(lq):
+    """A tighter stopping margin makes the main iteration run longer and every
+    (rhs, shift) still meets tol; factor 1 stops exactly at tol."""
+    L = (8, 8, 8, 8)
+    m = 0.03
+    U = synth.links_haar(L, 111)
+    g, U64, b_nat, b = setup(lq, L, U, 211, 2)
+    sig = synth.rational_shifts(6, 1e-4, 1.0)
+    its = {}
+    for f in (1.0, 0.5):
+        p = lq.solver_params(mass=m, tol=1e-10, inner_prec=1, inner_fmt=1, inner_tol_factor=f)
+        X, st, stats = lq.cg_multishift(g, p, U64, sig, b)
+        assert st == 0
+        Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(2, len(sig), -1, 3)
+        for j in range(2):
+            for s_, sg in enumerate(sig):
+                assert oracle.true_residual(L, U, m, sg, b_nat[j], Xn[j, s_]) <= 1e-10
+        its[f] = stats[0][0]["iters"]
+    assert its[0.5] > its[1.0]
