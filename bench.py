@@ -123,7 +123,7 @@ def shift_update_bytes(Vh, stats):
     """Algorithmic bytes of the shift-update kernels of a solve, per precision
     and kernel, from the device's counters (per even site, spinor = 3 complex):
       per-iteration update (window 1): r in + per updated shift x, p in and out
-      base update (window > 1): r in, p in and out, ring slot out per iteration
+      base update (window > 1): r in (the residual ring slot), p in and out
       window flush: each ring slot in + per materialised shift x, p in and out"""
     spin = {"f64": 48, "f32": 24}
     its = {"f64": sum(r[0]["iters_fp64"] for r in stats),
@@ -132,7 +132,7 @@ def shift_update_bytes(Vh, stats):
     for prec, sfx in (("f64", "fp64"), ("f32", "fp32")):
         sp = spin[prec]
         if stats[0][0]["shift_window"] > 1:
-            out["base_update_" + prec] = Vh * its[prec] * 4 * sp
+            out["base_update_" + prec] = Vh * its[prec] * 3 * sp
             out["ms_flush_" + prec] = Vh * sum(r[0]["flush_slots_" + sfx] * sp
                                                + r[0]["flush_shifts_" + sfx] * 4 * sp
                                                for r in stats)

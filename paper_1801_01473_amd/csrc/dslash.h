@@ -29,7 +29,14 @@ struct DslashCall {
   const void* diag = nullptr;
   int64_t diag_stride = 0;
   void* r = nullptr;
-  int64_t r_stride = 0;
+  int64_t r_stride = 0;     // complex elements between consecutive slots (or RHS)
+  // Residual ring: right-hand side j keeps r_slots slots; the residual of its
+  // iteration it is slot it % r_slots (r_iter: per-RHS iteration counters).
+  // DM_CG reads slot it and writes slot it + 1; DM_RES writes slot it.
+  // r_iter == nullptr: one slot per RHS, updated in place.
+  const int* r_iter = nullptr;
+  int r_iter_stride = 0;    // in ints
+  int r_slots = 1;
   const void* b = nullptr;  // DM_RES: FP64 right-hand side
   int64_t b_stride = 0;
   const double* m2s = nullptr;  // per right-hand side diagonal, or m2s_c when null

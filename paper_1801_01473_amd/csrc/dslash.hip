@@ -54,6 +54,14 @@ __device__ __forceinline__ int site_of(const KGeom& g, int i, int tz, int ty) {
   return inrow + g.Lxh * y0 + g.sz * z + g.st * t;
 }
 
+// Slot index (in units of r_stride) of right-hand side j's residual of its
+// current iteration + ahead (ahead = 1: the slot the update writes).
+__device__ __forceinline__ int64_t r_slot(const DslashCall& a, int j, int ahead) {
+  if (!a.r_iter) return j;
+  const int it = a.r_iter[j * a.r_iter_stride];
+  return int64_t(j) * a.r_slots + (it + ahead) % a.r_slots;
+}
+
 // V: bit 0 marks the link loads non-temporal (each link is read once; the
 // hint keeps L2 for the spinors that neighbours read again), bit 1 schedules
 // every load of a direction before its arithmetic (more loads in flight per
@@ -254,7 +262,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
 #pragma unroll
         for (int c = 0; c < 3; ++c) dv[b][c] = d[int64_t(c) * g.Vh];
         if (MODE == DM_CG) {
-          const cplx<R>* r = static_cast<const cplx<R>*>(a.r) + int64_t(jl) * a.r_stride + h;
+          const cplx<R>* r = static_cast<const cplx<R>*>(a.r) + r_slot(a, jl, 0) * a.r_stride + h;
 #pragma unroll
           for (int c = 0; c < 3; ++c) rv[b][c] = r[int64_t(c) * g.Vh];
         }
@@ -287,7 +295,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
                                            fma(R(m2s), dv[b][c].y, -acc[b][c].y));
         } else if (MODE == DM_CG) {
           const R al = R(a.alpha[j * a.alpha_stride]);
-          cplx<R>* r = static_cast<cplx<R>*>(a.r) + int64_t(j) * a.r_stride + h;
+          cplx<R>* r = static_cast<cplx<R>*>(a.r) + r_slot(a, j, 1) * a.r_stride + h;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const R wx = fma(R(m2s), dv[b][c].x, -acc[b][c].x);
@@ -299,7 +307,8 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
             nrm[b] += cnorm2<R>(rn);
           }
         } else {  // DM_RES, R = double
-          cplx<RO>* r = a.r ? static_cast<cplx<RO>*>(a.r) + int64_t(j) * a.r_stride + h : nullptr;
+          cplx<RO>* r = a.r ? static_cast<cplx<RO>*>(a.r) + r_slot(a, j, 0) * a.r_stride + h
+                            : nullptr;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const double rx = bv[b][c].x - fma(m2s, (double)dv[b][c].x, -(double)acc[b][c].x);

@@ -100,10 +100,11 @@ __global__ void __launch_bounds__(kVecBlock) k_norm2_f64(const double2* __restri
   if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = s;
 }
 
-// r = (RI) b, partials of |r|^2
+// r = (RI) b into slot 0 of each system's residual ring (R slots), partials of |r|^2
 template <typename RI>
 __global__ void __launch_bounds__(kVecBlock) k_copy_to_inner(const double2* __restrict__ b,
-                                                             cplx<RI>* __restrict__ r, int Vh,
+                                                             cplx<RI>* __restrict__ r, int R,
+                                                             int Vh,
                                                              double* __restrict__ part) {
   __shared__ double lds[kVecBlock / 64];
   const int j = blockIdx.y;
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(kVecBlock) k_copy_to_inner(const double2* __re
     for (int c = 0; c < 3; ++c) {
       const int64_t i = (int64_t(j) * 3 + c) * Vh + h;
       const cplx<RI> z = mk<RI>(RI(b[i].x), RI(b[i].y));
-      r[i] = z;
+      r[(int64_t(j) * R * 3 + c) * Vh + h] = z;
       s += cnorm2<RI>(z);
     }
   }
@@ -125,7 +126,7 @@ __global__ void __launch_bounds__(kVecBlock) k_copy_to_inner(const double2* __re
 // p_s = r for every shift, optionally x_s = 0; partials of |r|^2 (= |p|^2)
 // (pc, when given: the base direction of deferred shift updates, also = r)
 template <typename RI, typename RX>
-__global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restrict__ r,
+__global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restrict__ r, int R,
                                                          cplx<RI>* __restrict__ p,
                                                          cplx<RX>* __restrict__ x,
                                                          cplx<RI>* __restrict__ pc, int nshift,
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restr
   if (h < Vh) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cplx<RI> z = r[(int64_t(j) * 3 + c) * Vh + h];
+      const cplx<RI> z = r[(int64_t(j) * R * 3 + c) * Vh + h];  // slot 0
       s += cnorm2<RI>(z);
       if (pc) pc[(int64_t(j) * 3 + c) * Vh + h] = z;
       for (int k = 0; k < nshift; ++k) {
@@ -403,12 +404,13 @@ __global__ void __launch_bounds__(kVecBlock) k_ms_update(const SysState* __restr
 }
 
 // K5 with deferred shift updates: p = zeta_0 r + beta_0 p for the base
-// direction only (zeta_0 = 1), r filed in ring slot wpos - 1; partials of |p|^2.
+// direction only (zeta_0 = 1); r is the new residual, which the fused D_eo
+// update wrote into ring slot iters % R (R = window + 1 slots, so a window's
+// residuals stay in place until it is flushed); partials of |p|^2.
 template <typename RI>
 __global__ void __launch_bounds__(kVecBlock) k_base_update(const SysState* __restrict__ st,
                                                            const cplx<RI>* __restrict__ r,
-                                                           cplx<RI>* __restrict__ pc,
-                                                           cplx<RI>* __restrict__ ring, int win,
+                                                           int R, cplx<RI>* __restrict__ pc,
                                                            int base, int Vh,
                                                            double* __restrict__ part) {
   __shared__ double lds[kVecBlock / 64];
@@ -416,19 +418,18 @@ __global__ void __launch_bounds__(kVecBlock) k_base_update(const SysState* __res
   const SysState& S = st[j];
   if (!S.upd_any) return;
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
-  const int slot = S.wpos - 1;  // in [0, win): k_sc_beta stops a system before overflow
+  const int64_t rs = int64_t(j) * R + S.iters % R;
   double pn = 0.0;
   if (h < Vh) {
     const RI zs = RI(S.zeta[base]), bs = RI(S.b_s[base]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t i = (int64_t(j) * 3 + c) * Vh + h;
-      const cplx<RI> rv = r[i];
+      const cplx<RI> rv = r[(rs * 3 + c) * Vh + h];
       cplx<RI> pv = pc[i];
       pv.x = fma(zs, rv.x, bs * pv.x);
       pv.y = fma(zs, rv.y, bs * pv.y);
       pc[i] = pv;
-      ring[((int64_t(j) * win + slot) * 3 + c) * Vh + h] = rv;
       pn += cnorm2<RI>(pv);
     }
   }
@@ -438,10 +439,12 @@ __global__ void __launch_bounds__(kVecBlock) k_base_update(const SysState* __res
 
 // K6: applies the window of every system that has one open (wpos > 0) to the
 // shifts updated in it; WM >= window length bounds the unrolled ring.
+// The window's residuals r(k0 + 1 .. k0 + n) are ring slots (k0 + q) % R,
+// k0 = iters - wpos.
 template <typename RI, typename RX, int WM>
 __global__ void __launch_bounds__(kVecBlock) k_ms_flush(const SysState* __restrict__ st,
                                                         const WinCoef* __restrict__ wc,
-                                                        const cplx<RI>* __restrict__ ring,
+                                                        const cplx<RI>* __restrict__ ring, int R,
                                                         cplx<RI>* __restrict__ p,
                                                         cplx<RX>* __restrict__ x, int nshift,
                                                         int win, int Vh) {
@@ -449,6 +452,7 @@ __global__ void __launch_bounds__(kVecBlock) k_ms_flush(const SysState* __restri
   const SysState& S = st[j];
   const int n = S.wpos < win ? S.wpos : win;
   if (n <= 0) return;
+  const int k0 = S.iters - S.wpos;
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= Vh) return;
   const WinCoef& C = wc[j];
@@ -457,7 +461,7 @@ __global__ void __launch_bounds__(kVecBlock) k_ms_flush(const SysState* __restri
     cplx<RI> v[WM];
 #pragma unroll
     for (int q = 0; q < WM; ++q)
-      if (q < n) v[q] = ring[((int64_t(j) * win + q) * 3 + c) * Vh + h];
+      if (q < n) v[q] = ring[((int64_t(j) * R + (k0 + 1 + q) % R) * 3 + c) * Vh + h];
     for (int s = 0; s < nshift; ++s) {
       if (!S.wdirty[s]) continue;
       const int64_t o = ((int64_t(j) * nshift + s) * 3 + c) * Vh + h;
@@ -607,7 +611,7 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_reliable(SysState* __rest
 // (and the base direction pc of deferred shift updates, when given)
 template <typename RI>
 __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __restrict__ st,
-                                                            const cplx<RI>* __restrict__ r,
+                                                            const cplx<RI>* __restrict__ r, int R,
                                                             cplx<RI>* __restrict__ p,
                                                             cplx<RI>* __restrict__ pc, int nshift,
                                                             int base, int Vh,
@@ -621,7 +625,7 @@ __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __re
   if (h < Vh) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cplx<RI> rv = r[(int64_t(j) * 3 + c) * Vh + h];
+      const cplx<RI> rv = r[((int64_t(j) * R + S.iters % R) * 3 + c) * Vh + h];
       for (int s = 0; s < nshift; ++s) {
         if (!S.active[s] && s != base) continue;
         const RI z = RI(S.zeta[s]);
@@ -640,7 +644,9 @@ __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __re
 
 // FP64 Krylov state -> FP32: r, every shift's p; x_lo = 0; partials of |p_base|^2
 // (with deferred shift updates the base direction is pc64 -> pc32)
-__global__ void __launch_bounds__(kVecBlock) k_to_fp32(const double2* __restrict__ r64,
+// (r: the current slot, iters % R, of each system's residual ring in both)
+__global__ void __launch_bounds__(kVecBlock) k_to_fp32(const SysState* __restrict__ st, int R,
+                                                       const double2* __restrict__ r64,
                                                        const double2* __restrict__ p64,
                                                        const double2* __restrict__ pc64,
                                                        float2* __restrict__ r32,
@@ -657,7 +663,8 @@ __global__ void __launch_bounds__(kVecBlock) k_to_fp32(const double2* __restrict
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t ir = (int64_t(j) * 3 + c) * Vh + h;
-      r32[ir] = make_float2(float(r64[ir].x), float(r64[ir].y));
+      const int64_t irr = ((int64_t(j) * R + st[j].iters % R) * 3 + c) * Vh + h;
+      r32[irr] = make_float2(float(r64[irr].x), float(r64[irr].y));
       if (pc64) {
         const float2 pv = make_float2(float(pc64[ir].x), float(pc64[ir].y));
         pc32[ir] = pv;
@@ -703,7 +710,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t r, t, p, xlo, r64, t64, p64, thi, bb, xb, st, gf, params, pt, pr, pp, pb, pres, resn,
-      links, links_pre, pc, pc64, ring, wc, total;
+      links, links_pre, pc, pc64, wc, total;
   bool has_xlo, has_pre, has_links;
   int win;  // window of deferred shift updates of the main solve (1: none)
 };
@@ -739,13 +746,18 @@ Layout make_layout(const KGeom& g, const lqcd_solver_params& p, int nshift, int 
     off = align_up(off + n);
     return o;
   };
-  L.r = take(nrhs * vin);
+  // residuals: a ring of W + 1 slots per system with deferred shift updates
+  // (the window's residuals stay in place until the window is flushed), else
+  // one slot updated in place
+  L.win = window_for(p, nshift);
+  const size_t R = L.win > 1 ? size_t(L.win) + 1 : 1;
+  L.r = take(nrhs * R * vin);
   L.t = take(nrhs * vin);
   L.p = take(size_t(nrhs) * nshift * vin);
   L.has_xlo = iprec == LQCD_F32;
   L.xlo = L.has_xlo ? take(size_t(nrhs) * nshift * vin) : 0;
   L.has_pre = iprec == LQCD_F32 && p.mixed_switch > 0.0 && nshift > 1;
-  L.r64 = L.has_pre ? take(nrhs * v64) : 0;
+  L.r64 = L.has_pre ? take(nrhs * R * v64) : 0;
   L.t64 = L.has_pre ? take(nrhs * v64) : 0;
   L.p64 = L.has_pre ? take(size_t(nrhs) * nshift * v64) : 0;
   L.thi = take(nrhs * v64);
@@ -765,13 +777,10 @@ Layout make_layout(const KGeom& g, const lqcd_solver_params& p, int nshift, int 
   // the FP64 opening phase streams FP64 links in the inner format (12-real:
   // a third fewer link bytes than the 18-real copy used for residuals)
   L.links_pre = (L.has_pre && ifmt == LQCD_LINKS12) ? take(size_t(8) * 6 * g.Vh * 16) : 0;
-  // deferred shift updates: base directions and the residual ring, shared by
-  // the FP64 opening phase and the main phase (the ring is empty at the switch)
-  L.win = window_for(p, nshift);
+  // deferred shift updates: base directions and window coefficients
   if (L.win > 1) {
     L.pc = take(nrhs * vin);
     L.pc64 = L.has_pre ? take(nrhs * v64) : 0;
-    L.ring = take(size_t(nrhs) * L.win * (L.has_pre ? v64 : vin));
     L.wc = take(size_t(nrhs) * sizeof(WinCoef));
   }
   L.total = off;
@@ -931,6 +940,9 @@ struct Core {
 
 bool is_mixed(const Ctx& c) { return c.iprec == LQCD_F32; }
 
+// residual ring slots per system (1: r updated in place)
+int rslots(const Core& k) { return k.win > 1 ? k.win + 1 : 1; }
+
 int64_t vstride(const Ctx& c) { return int64_t(3) * c.g.Vh; }
 
 size_t cbytes(int prec) { return prec == LQCD_F32 ? 8 : 16; }  // bytes per complex
@@ -971,7 +983,7 @@ int launch_flush(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s) {
   hipEvent_t ev = timing_begin(s);
 #define LQCD_FLUSH(RI, WM)                                                                     \
   hipLaunchKernelGGL((k_ms_flush<RI, RI, WM>), grid, dim3(kVecBlock), 0, s, st, wc,            \
-                     c.at<const cplx<RI>>(c.L.ring), c.at<cplx<RI>>(ph.p),                     \
+                     c.at<const cplx<RI>>(ph.r), rslots(k), c.at<cplx<RI>>(ph.p),              \
                      static_cast<cplx<RI>*>(ph.x), k.nshift, k.win, c.g.Vh)
   if (ph.prec == LQCD_F32) {
     if (k.win <= 8) LQCD_FLUSH(float, 8);
@@ -1026,6 +1038,11 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   d3.diag_stride = win ? vs : int64_t(k.nshift) * vs;
   d3.r = c.ws + ph.r;
   d3.r_stride = vs;
+  if (win) {
+    d3.r_iter = &st->iters;
+    d3.r_iter_stride = kStateStrideI;
+    d3.r_slots = rslots(k);
+  }
   d3.m2s = &st->m2s;
   d3.m2s_stride = kStateStrideD;
   d3.alpha = &st->a;
@@ -1050,13 +1067,12 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
     ev = timing_begin(s);
     if (ph.prec == LQCD_F32)
       hipLaunchKernelGGL(k_base_update<float>, grid, dim3(kVecBlock), 0, s, st,
-                         c.at<const float2>(ph.r), c.at<float2>(ph.pc), c.at<float2>(c.L.ring),
-                         k.win, k.base, c.g.Vh, c.at<double>(c.L.pp));
+                         c.at<const float2>(ph.r), rslots(k), c.at<float2>(ph.pc), k.base,
+                         c.g.Vh, c.at<double>(c.L.pp));
     else
       hipLaunchKernelGGL(k_base_update<double>, grid, dim3(kVecBlock), 0, s, st,
-                         c.at<const double2>(ph.r), c.at<double2>(ph.pc),
-                         c.at<double2>(c.L.ring), k.win, k.base, c.g.Vh,
-                         c.at<double>(c.L.pp));
+                         c.at<const double2>(ph.r), rslots(k), c.at<double2>(ph.pc), k.base,
+                         c.g.Vh, c.at<double>(c.L.pp));
     LQCD_LAUNCH_CHECK();
     timing_end(ev, s, "base_update" + tag);
     return flush ? launch_flush(c, k, ph, s) : LQCD_OK;
@@ -1100,6 +1116,11 @@ int launch_residual(const Ctx& c, const Core& k, const double* m2s, int m2s_stri
   e2.b_stride = vs;
   e2.r = c.ws + k.main.r;
   e2.r_stride = vs;
+  if (rslots(k) > 1) {  // the residual of the current iteration's ring slot
+    e2.r_iter = &c.at<SysState>(c.L.st)->iters;
+    e2.r_iter_stride = kStateStrideI;
+    e2.r_slots = rslots(k);
+  }
   e2.m2s = m2s;
   e2.m2s_stride = m2s_stride;
   e2.live = live;
@@ -1125,7 +1146,7 @@ int launch_reliable(const Ctx& c, const Core& k, hipStream_t s) {
                      k.nshift, k.base, c.at<double>(c.L.pres), k.nb64_eo, c.p.max_iter);
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_restart_dirs<float>, dim3(k.nbv, k.nsys), dim3(kVecBlock), 0, s, st,
-                     c.at<const float2>(c.L.r), c.at<float2>(c.L.p),
+                     c.at<const float2>(c.L.r), rslots(k), c.at<float2>(c.L.p),
                      k.win > 1 ? c.at<float2>(c.L.pc) : nullptr, k.nshift, k.base, c.g.Vh,
                      c.at<double>(c.L.pp));
   LQCD_LAUNCH_CHECK();
@@ -1348,10 +1369,10 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
     nb_r = k.nb64_eo;
   } else if (first.prec == LQCD_F32) {
     hipLaunchKernelGGL(k_copy_to_inner<float>, gv, dim3(kVecBlock), 0, s, k.b,
-                       c.at<float2>(first.r), c.g.Vh, c.at<double>(c.L.pr));
+                       c.at<float2>(first.r), rslots(k), c.g.Vh, c.at<double>(c.L.pr));
   } else {
     hipLaunchKernelGGL(k_copy_to_inner<double>, gv, dim3(kVecBlock), 0, s, k.b,
-                       c.at<double2>(first.r), c.g.Vh, c.at<double>(c.L.pr));
+                       c.at<double2>(first.r), rslots(k), c.g.Vh, c.at<double>(c.L.pr));
   }
   LQCD_LAUNCH_CHECK();
   if (first.prec == LQCD_F32) {
@@ -1361,12 +1382,13 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
       LQCD_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL((k_init_dirs<float, float>), gv, dim3(kVecBlock), 0, s,
-                       c.at<const float2>(first.r), c.at<float2>(first.p), (float2*)first.x,
+                       c.at<const float2>(first.r), rslots(k), c.at<float2>(first.p),
+                       (float2*)first.x,
                        k.win > 1 ? c.at<float2>(first.pc) : nullptr, k.nshift, 1, c.g.Vh,
                        c.at<double>(c.L.pp));
   } else {
     hipLaunchKernelGGL((k_init_dirs<double, double>), gv, dim3(kVecBlock), 0, s,
-                       c.at<const double2>(first.r), c.at<double2>(first.p), k.x,
+                       c.at<const double2>(first.r), rslots(k), c.at<double2>(first.p), k.x,
                        k.win > 1 ? c.at<double2>(first.pc) : nullptr, k.nshift,
                        k.guess ? 0 : 1, c.g.Vh, c.at<double>(c.L.pp));
   }
@@ -1391,7 +1413,8 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
     if (k.win > 1 && (rc = launch_flush(c, k, k.pre, s))) return rc;
     if (!f.all_done && !f.error) {
       const bool w = k.win > 1;
-      hipLaunchKernelGGL(k_to_fp32, gv, dim3(kVecBlock), 0, s, c.at<const double2>(c.L.r64),
+      hipLaunchKernelGGL(k_to_fp32, gv, dim3(kVecBlock), 0, s, st, rslots(k),
+                         c.at<const double2>(c.L.r64),
                          c.at<const double2>(c.L.p64),
                          w ? c.at<const double2>(c.L.pc64) : nullptr, c.at<float2>(c.L.r),
                          c.at<float2>(c.L.p), w ? c.at<float2>(c.L.pc) : nullptr,
