@@ -226,6 +226,36 @@ def config3_m2(lq, torch):
     return out
 
 
+def config2_overhead(lq, torch):
+    """Plain FP64 CG at 24^4 (Haar links, m = 0.05, 1 RHS): time per iteration
+    with graph replay and with direct launches, against the standalone FP64
+    18-real D_oe; shows how much of an iteration is launch latency at a size
+    where each kernel runs only tens of microseconds."""
+    import synth
+    L = (24, 24, 24, 24)
+    g = lq.Geometry(L)
+    U64 = lq.pack_links(g, torch.from_numpy(synth.links_haar(L, 102)).to("cuda"))
+    b = lq.pack_spinor(g, torch.from_numpy(synth.gaussian_even_source(L, 1, 202)).to("cuda"), 0)
+    out = {}
+    for name, graph in (("graph", 1), ("direct", 0)):
+        p = lq.solver_params(mass=0.05, tol=1e-10, use_graph=graph)
+        lq.cg(g, p, U64, b)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, _, st = lq.cg(g, p, U64, b)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        out[name] = dict(seconds=dt, iters=st[0]["iters"],
+                         us_per_iter=1e6 * dt / max(st[0]["iters"], 1),
+                         true_rel_residual=st[0]["true_rel_residual"])
+    x = torch.randn(1, 3, g.Vh, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    out["doe_fp64_18_us"] = 1000 * event_time_ms(lambda: lq.doe(g, U64, x, out=y), 20)
+    log(f"config 2 (24^4 FP64 CG): {out['graph']['us_per_iter']:.1f} us/iter with graphs, "
+        f"{out['direct']['us_per_iter']:.1f} direct")
+    return out
+
+
 def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, X0=None, budget_s=20.0):
     """Oracle multi-shift CG timed on a bounded sample: a few iterations on one
     right-hand side of the same lattice, scaled to the GPU run's iteration
@@ -421,6 +451,7 @@ def main():
         fp64["per_shift_cg_iters"] = cg_it
         log(f"per-shift FP64 CG, 1 RHS: {fp64['per_shift_cg_1rhs_s']:.3f} s")
         fp64["config3_32x4_1rhs"] = config3_m2(lq, torch)
+        fp64["config2_24x4_cg"] = config2_overhead(lq, torch)
 
     # D_oe bandwidth (standalone, HIP events), STREAM ceiling
     copy_gbs, triad_gbs = lq.stream_bandwidth(1 << 30, 20)
@@ -495,6 +526,7 @@ def main():
             "fp64_per_shift_cg_1rhs_s": fp64["per_shift_cg_1rhs_s"] if fp64 else None,
             "fp64_per_shift_cg_iters": fp64["per_shift_cg_iters"] if fp64 else None,
             "config3_32x4_1rhs": fp64["config3_32x4_1rhs"] if fp64 else None,
+            "config2_24x4_fp64_cg": fp64["config2_24x4_cg"] if fp64 else None,
         },
         "solver": {"iters_per_rhs": iters,
                    "fp64_phase_iters_per_rhs": [row[0]["iters_fp64"] for row in stats],

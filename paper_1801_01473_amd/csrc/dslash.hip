@@ -19,8 +19,10 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -440,6 +442,79 @@ bool tuning_verbose() {
   return e && e[0] == '1';
 }
 
+// ---- optional on-disk tuning cache (LQCD_TUNE_CACHE=file) ----------------
+// One line per tuned shape: "<key>;<block>,<B>,<xcd>,<tz>,<nt>,<occ>,<ilv>,<lf>,<hh>,<ty>"
+// where the key names the cache format, the GPU architecture and CU count,
+// the geometry, precision, link format, RHS count, forced RHS block and
+// mode.  Lines that do not parse, or whose configuration is not valid for
+// the shape, are ignored (that shape is tuned again).
+constexpr int kTuneCacheFormat = 1;
+
+const char* tune_cache_path() {
+  const char* e = std::getenv("LQCD_TUNE_CACHE");
+  return (e && e[0]) ? e : nullptr;
+}
+
+std::string tune_cache_key(const DslashCall& c, int forced) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char& ch : arch)
+    if (ch == ';' || ch == ' ') ch = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "v%d/%s/%dcu/%dx%dx%dx%d/p%d/f%d/n%d/b%d/m%d", kTuneCacheFormat,
+                arch.c_str(), cus, c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, c.prec, c.fmt, c.nrhs, forced,
+                c.mode);
+  return buf;
+}
+
+bool cfg_valid(const DslashCall& c, const DslashCfg& f, int forced) {
+  const bool b_ok = f.rhs_block == 1 || f.rhs_block == 2 || f.rhs_block == 4 || f.rhs_block == 8;
+  return (f.block == 64 || f.block == 128 || f.block == 256) && b_ok &&
+         (!forced || f.rhs_block == forced) && (f.xcd == 0 || f.xcd == 1) && f.tz >= 0 &&
+         (f.tz == 0 || c.g.Lz % f.tz == 0) && f.ty >= 0 && (f.ty == 0 || c.g.Ly % f.ty == 0) &&
+         (f.nt == 0 || f.nt == 1) && (f.lf == 0 || f.lf == 1) && (f.hh == 0 || f.hh == 1) &&
+         (f.ilv == 0 || f.ilv == 1) && f.occ >= 0 && dslash_lds_bytes(f) >= 0 &&
+         dslash_lds_bytes(f) <= 64 * 1024;
+}
+
+// The last valid entry for the key, if any.
+bool tune_cache_lookup(const char* path, const std::string& key, const DslashCall& c, int forced,
+                       DslashCfg* out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char* semi = std::strchr(line, ';');
+    if (!semi) continue;
+    *semi = '\0';
+    if (key != line) continue;
+    DslashCfg v;
+    if (std::sscanf(semi + 1, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &v.block, &v.rhs_block, &v.xcd,
+                    &v.tz, &v.nt, &v.occ, &v.ilv, &v.lf, &v.hh, &v.ty) != 10)
+      continue;
+    if (!cfg_valid(c, v, forced)) continue;
+    *out = v;
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_store(const char* path, const std::string& key, const DslashCfg& v) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;  // the cache is an optimisation; an unwritable file only costs tuning
+  std::fprintf(f, "%s;%d,%d,%d,%d,%d,%d,%d,%d,%d,%d\n", key.c_str(), v.block, v.rhs_block, v.xcd,
+               v.tz, v.nt, v.occ, v.ilv, v.lf, v.hh, v.ty);
+  std::fclose(f);
+}
+
 }  // namespace
 
 void dslash_clear_tuning() {
@@ -474,6 +549,14 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   }
   DslashCfg best = default_cfg(c.nrhs, forced, c.mode == DM_RES ? LQCD_F64 : c.prec);
   if (!tuning_enabled()) {
+    *out = best;
+    return LQCD_OK;
+  }
+  const char* cache_path = tune_cache_path();
+  const std::string cache_key = cache_path ? tune_cache_key(c, forced) : std::string();
+  if (cache_path && tune_cache_lookup(cache_path, cache_key, c, forced, &best)) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
     *out = best;
     return LQCD_OK;
   }
@@ -675,6 +758,7 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = best;
   }
+  if (cache_path) tune_cache_store(cache_path, cache_key, best);
   if (tuning_verbose())
     fprintf(stderr,
             "[lqcd tune] chosen L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d mode=%d: block=%d B=%d "

@@ -197,3 +197,34 @@ def test_every_launch_configuration(lq, cfg, prec, fmt, tol, monkeypatch):
     got = host(lq.unpack_spinor(g, lq.deo(g, Up, lq.pack_spinor(g, cu(f), 1, prec)), 0))
     ref = np.stack([oracle.deo(L, U, f[j]) for j in range(5)])
     assert H.max_rel(got, ref) <= tol
+
+
+def test_tuning_cache_file(lq, tmp_path, monkeypatch):
+    """LQCD_TUNE_CACHE: a tuned shape is appended to the file; a valid entry
+    for the key is used without tuning again (and, every launch variant
+    rounding alike, gives the same bits); an invalid entry is ignored and the
+    shape is tuned again."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("LQCD_TUNE_CACHE", str(path))
+    monkeypatch.delenv("LQCD_DSLASH_CFG", raising=False)
+    L = (6, 4, 8, 6)
+    g = lq.Geometry(L)
+    Up = lq.pack_links(g, cu(_links(L, "haar", 31)))
+    x = lq.pack_spinor(g, cu(synth.gaussian_field(L, 1, 32)), 0)
+    lq.finalize()
+    y1 = lq.doe(g, Up, x)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].count(";") == 1
+    key = lines[0].split(";")[0]
+    assert key.startswith("v1/") and "/6x4x8x6/" in key
+    path.write_text(f"{key};64,1,0,2,0,0,0,0,1,2\n")
+    lq.finalize()
+    y2 = lq.doe(g, Up, x)
+    assert path.read_text().splitlines() == [f"{key};64,1,0,2,0,0,0,0,1,2"]
+    assert torch.equal(y1, y2)
+    path.write_text(f"{key};96,3,0,5,0,0,0,0,1,2\n")
+    lq.finalize()
+    y3 = lq.doe(g, Up, x)
+    assert len(path.read_text().splitlines()) == 2
+    assert torch.equal(y1, y3)
+    lq.finalize()
