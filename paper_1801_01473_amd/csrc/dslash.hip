@@ -565,10 +565,11 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   // own-site loads, or plain) with FP64 norm partials, on private scratch
   // fields and the caller's links, so no caller data is touched.
   // Stage 1: workgroup size, RHS block, XCD remap, z-slab traversal, RHS
-  // interleave.  Stage 2: (y, z) tiles for the three fastest, with plain and
-  // non-temporal link loads.  Stage 3: the three fastest so far with the
-  // other schedules (loads first, one hop per iteration, non-temporal links)
-  // and occupancy caps.  Stage 4: the five fastest re-timed, best median.
+  // interleave.  Stage 2: (y, z) tiles for the three fastest, each with and
+  // without one hop per iteration, non-temporal link loads.  Stage 3: the
+  // three fastest so far with the other schedules (loads first, one hop per
+  // iteration, non-temporal links) and occupancy caps.  Stage 4: the five
+  // fastest re-timed, best median.
   std::vector<DslashCfg> cand;
   for (int blk : {64, 128, 256})
     for (int b : {1, 2, 4, 8}) {
@@ -606,7 +607,14 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   hipEvent_t ev[2 * kMaxReps];
   for (auto& e : ev) LQCD_HIP_TRY(hipEventCreate(&e));
 
-  DslashCall t = c;
+  // Built from scratch: only the shape, parity, precision and links are the
+  // caller's; every field pointer (residual ring, right-hand side, flags) is
+  // either a scratch field below or left null.
+  DslashCall t;
+  t.g = c.g;
+  t.out_par = c.out_par;
+  t.nrhs = c.nrhs;
+  t.U = c.U;
   t.mode = cg ? DM_CG : DM_PLAIN;
   t.in = scratch;
   t.in_stride = int64_t(3) * c.g.Vh;
@@ -622,8 +630,6 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     t.alpha = reinterpret_cast<const double*>(static_cast<char*>(scratch) + fields + npart * 8);
     t.alpha_stride = 1;
   }
-  t.live = nullptr;
-  t.halt = nullptr;
   t.partials = reinterpret_cast<double*>(static_cast<char*>(scratch) + fields);
   t.prec = c.prec;
   t.fmt = c.fmt;
@@ -687,15 +693,28 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
       best = cfg;
     }
     if (ci + 1 == stage1) {  // stage 2: (y, z) tiles of the best three
-      for (const auto& tk : top3())
-        for (int ty : {4, 8, 12, 16, 24})
+      // The tile and the one-hop schedule interact (a tile pays off most with
+      // one hop per iteration), so both are crossed here.  The seeds cover
+      // both block-to-XCD maps: the remap that wins untiled can lose tiled.
+      auto seeds = top3();
+      if (seeds.size() == 3 && seeds[0].second.xcd == seeds[1].second.xcd &&
+          seeds[1].second.xcd == seeds[2].second.xcd) {
+        const std::pair<float, DslashCfg>* other = nullptr;
+        for (const auto& tk : timed)
+          if (tk.second.xcd != seeds[0].second.xcd && (!other || tk.first < other->first))
+            other = &tk;
+        if (other) seeds[2] = *other;
+      }
+      for (const auto& tk : seeds)
+        for (int ty : {0, 4, 8, 12, 16, 24})
           for (int tz : {2, 4, 6, 8, 12})
-            for (int nt : {0, 1}) {
-              if (c.g.Ly % ty || ty >= c.g.Ly || c.g.Lz % tz || tz >= c.g.Lz) continue;
+            for (int hh : {0, 1}) {
+              if ((ty && (c.g.Ly % ty || ty >= c.g.Ly)) || c.g.Lz % tz || tz >= c.g.Lz) continue;
               DslashCfg v = tk.second;
               v.ty = ty;
               v.tz = tz;
-              v.nt = nt;
+              v.nt = 1;
+              v.hh = hh;
               cand.push_back(v);
             }
       stage2 = cand.size();
