@@ -140,7 +140,7 @@ int lqcd_unpack_spinor(const lqcd_geom *g, int parity, int prec, const void *pac
  * precision, format, nrhs, mode) and cached for the process; that first call
  * allocates temporary scratch and synchronises the stream.  Environment:
  * LQCD_TUNE=0 uses a fixed default instead, LQCD_TUNE_VERBOSE=1 prints the
- * timings, LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty]"
+ * timings, LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty,ns]"
  * pins one configuration (testing and profiling), LQCD_TUNE_CACHE=<file>
  * keeps tuned configurations across processes (one text line per shape,
  * keyed by GPU architecture and CU count; entries that are not valid for the

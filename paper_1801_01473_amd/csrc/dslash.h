@@ -67,6 +67,9 @@ struct DslashCfg {
                     // loads in flight per wave, more registers held); buffer loads only
   int hh = 0;       // 1: one hop (forward or backward) per loop iteration instead of both
                     // of a direction: half the loads held, more waves; buffer loads only
+  int ns = 0;       // 1: the own-site operands and the outputs (each touched once) are loaded
+                    // and stored non-temporal as well, leaving L2 to the neighbour spinors;
+                    // only with nt = 1
 };
 
 // Dynamic LDS a workgroup reserves so that at most occ waves per SIMD are resident.

@@ -77,6 +77,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
   constexpr int LAUX = (V & 1) ? 2 : 0;  // buffer cache policy of link loads: 2 = nt
   constexpr bool LF = (V & 2) != 0;
   constexpr bool HH = (V & 4) != 0;
+  constexpr bool NS = (V & 8) != 0;  // own-site operands and outputs non-temporal
   __shared__ double lds[B][4];
   if (a.halt && *a.halt) return;
   const KGeom& g = a.g;
@@ -262,16 +263,17 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
         const int jl = rhs0 + b < a.nrhs ? rhs0 + b : a.nrhs - 1;
         const cplx<R>* d = static_cast<const cplx<R>*>(a.diag) + int64_t(jl) * a.diag_stride + h;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dv[b][c] = d[int64_t(c) * g.Vh];
+        for (int c = 0; c < 3; ++c) dv[b][c] = ld_once<R, NS>(d + int64_t(c) * g.Vh);
         if (MODE == DM_CG) {
           const cplx<R>* r = static_cast<const cplx<R>*>(a.r) + r_slot(a, jl, 0) * a.r_stride + h;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) rv[b][c] = r[int64_t(c) * g.Vh];
+          for (int c = 0; c < 3; ++c) rv[b][c] = ld_once<R, NS>(r + int64_t(c) * g.Vh);
         }
         if (MODE == DM_RES) {
-          const double2* bp = static_cast<const double2*>(a.b) + int64_t(jl) * a.b_stride + h;
+          const cplx<double>* bp =
+              static_cast<const cplx<double>*>(a.b) + int64_t(jl) * a.b_stride + h;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) bv[b][c] = bp[int64_t(c) * g.Vh];
+          for (int c = 0; c < 3; ++c) bv[b][c] = ld_once<double, NS>(bp + int64_t(c) * g.Vh);
         }
       }
     }
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
         cplx<R>* out = static_cast<cplx<R>*>(a.out) + int64_t(j) * a.out_stride + h;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          out[int64_t(c) * g.Vh] = acc[b][c];
+          st_once<R, NS>(out + int64_t(c) * g.Vh, acc[b][c]);
           nrm[b] += cnorm2<R>(acc[b][c]);
         }
       } else {
@@ -293,8 +295,9 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
           cplx<R>* out = static_cast<cplx<R>*>(a.out) + int64_t(j) * a.out_stride + h;
 #pragma unroll
           for (int c = 0; c < 3; ++c)
-            out[int64_t(c) * g.Vh] = mk<R>(fma(R(m2s), dv[b][c].x, -acc[b][c].x),
-                                           fma(R(m2s), dv[b][c].y, -acc[b][c].y));
+            st_once<R, NS>(out + int64_t(c) * g.Vh,
+                           mk<R>(fma(R(m2s), dv[b][c].x, -acc[b][c].x),
+                                 fma(R(m2s), dv[b][c].y, -acc[b][c].y)));
         } else if (MODE == DM_CG) {
           const R al = R(a.alpha[j * a.alpha_stride]);
           cplx<R>* r = static_cast<cplx<R>*>(a.r) + r_slot(a, j, 1) * a.r_stride + h;
@@ -305,7 +308,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
             cplx<R> rn = rv[b][c];
             rn.x = fma(-al, wx, rn.x);
             rn.y = fma(-al, wy, rn.y);
-            r[int64_t(c) * g.Vh] = rn;
+            st_once<R, NS>(r + int64_t(c) * g.Vh, rn);
             nrm[b] += cnorm2<R>(rn);
           }
         } else {  // DM_RES, R = double
@@ -315,7 +318,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
           for (int c = 0; c < 3; ++c) {
             const double rx = bv[b][c].x - fma(m2s, (double)dv[b][c].x, -(double)acc[b][c].x);
             const double ry = bv[b][c].y - fma(m2s, (double)dv[b][c].y, -(double)acc[b][c].y);
-            if (r) r[int64_t(c) * g.Vh] = mk<RO>(RO(rx), RO(ry));
+            if (r) st_once<RO, NS>(r + int64_t(c) * g.Vh, mk<RO>(RO(rx), RO(ry)));
             nrm[b] += fma(rx, rx, ry * ry);
           }
         }
@@ -346,7 +349,11 @@ int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
 #define LQCD_K(V)                                                                         \
   hipLaunchKernelGGL((k_dslash<R, NE, B, MODE, RO, V>), grid, dim3(cfg.block), lds, st, c, \
                      cfg.xcd, cfg.tz, cfg.ty, ngroups, ilv)
-  switch ((cfg.nt ? 1 : 0) | (cfg.lf ? 2 : 0) | (cfg.hh ? 4 : 0)) {
+  if (cfg.ns && !cfg.nt) {
+    set_error("non-temporal own-site streams (ns) need non-temporal link loads (nt)");
+    return LQCD_ERR_UNSUPPORTED;
+  }
+  switch ((cfg.nt ? 1 : 0) | (cfg.lf ? 2 : 0) | (cfg.hh ? 4 : 0) | (cfg.ns ? 8 : 0)) {
     case 0: LQCD_K(0); break;
     case 1: LQCD_K(1); break;
     case 2: LQCD_K(2); break;
@@ -354,7 +361,11 @@ int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     case 4: LQCD_K(4); break;
     case 5: LQCD_K(5); break;
     case 6: LQCD_K(6); break;
-    default: LQCD_K(7); break;
+    case 7: LQCD_K(7); break;
+    case 9: LQCD_K(9); break;
+    case 11: LQCD_K(11); break;
+    case 13: LQCD_K(13); break;
+    default: LQCD_K(15); break;
   }
 #undef LQCD_K
   LQCD_LAUNCH_CHECK();
@@ -443,7 +454,7 @@ bool tuning_verbose() {
 }
 
 // ---- optional on-disk tuning cache (LQCD_TUNE_CACHE=file) ----------------
-// One line per tuned shape: "<key>;<block>,<B>,<xcd>,<tz>,<nt>,<occ>,<ilv>,<lf>,<hh>,<ty>"
+// One line per tuned shape: "<key>;<block>,<B>,<xcd>,<tz>,<nt>,<occ>,<ilv>,<lf>,<hh>,<ty>[,<ns>]"
 // where the key names the cache format, the GPU architecture and CU count,
 // the geometry, precision, link format, RHS count, forced RHS block and
 // mode.  Lines that do not parse, or whose configuration is not valid for
@@ -479,6 +490,7 @@ bool cfg_valid(const DslashCall& c, const DslashCfg& f, int forced) {
          (!forced || f.rhs_block == forced) && (f.xcd == 0 || f.xcd == 1) && f.tz >= 0 &&
          (f.tz == 0 || c.g.Lz % f.tz == 0) && f.ty >= 0 && (f.ty == 0 || c.g.Ly % f.ty == 0) &&
          (f.nt == 0 || f.nt == 1) && (f.lf == 0 || f.lf == 1) && (f.hh == 0 || f.hh == 1) &&
+         (f.ns == 0 || (f.ns == 1 && f.nt == 1)) &&
          (f.ilv == 0 || f.ilv == 1) && f.occ >= 0 && dslash_lds_bytes(f) >= 0 &&
          dslash_lds_bytes(f) <= 64 * 1024;
 }
@@ -496,9 +508,10 @@ bool tune_cache_lookup(const char* path, const std::string& key, const DslashCal
     *semi = '\0';
     if (key != line) continue;
     DslashCfg v;
-    if (std::sscanf(semi + 1, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &v.block, &v.rhs_block, &v.xcd,
-                    &v.tz, &v.nt, &v.occ, &v.ilv, &v.lf, &v.hh, &v.ty) != 10)
-      continue;
+    const int n = std::sscanf(semi + 1, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &v.block,
+                              &v.rhs_block, &v.xcd, &v.tz, &v.nt, &v.occ, &v.ilv, &v.lf, &v.hh,
+                              &v.ty, &v.ns);
+    if (n != 10 && n != 11) continue;
     if (!cfg_valid(c, v, forced)) continue;
     *out = v;
     found = true;
@@ -510,8 +523,8 @@ bool tune_cache_lookup(const char* path, const std::string& key, const DslashCal
 void tune_cache_store(const char* path, const std::string& key, const DslashCfg& v) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;  // the cache is an optimisation; an unwritable file only costs tuning
-  std::fprintf(f, "%s;%d,%d,%d,%d,%d,%d,%d,%d,%d,%d\n", key.c_str(), v.block, v.rhs_block, v.xcd,
-               v.tz, v.nt, v.occ, v.ilv, v.lf, v.hh, v.ty);
+  std::fprintf(f, "%s;%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d\n", key.c_str(), v.block, v.rhs_block,
+               v.xcd, v.tz, v.nt, v.occ, v.ilv, v.lf, v.hh, v.ty, v.ns);
   std::fclose(f);
 }
 
@@ -527,12 +540,12 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     set_error("rhs_block must be 0 (tuned), 1, 2, 4 or 8, got %d", forced);
     return LQCD_ERR_INVALID_ARG;
   }
-  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty]" pins the configuration
+  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty,ns]" pins the configuration
   // (testing, profiling)
   if (const char* e = std::getenv("LQCD_DSLASH_CFG")) {
     DslashCfg f;
-    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz,
-                    &f.nt, &f.occ, &f.ilv, &f.lf, &f.hh, &f.ty) >= 4) {
+    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz,
+                    &f.nt, &f.occ, &f.ilv, &f.lf, &f.hh, &f.ty, &f.ns) >= 4) {
       if (forced) f.rhs_block = forced;
       *out = f;
       return LQCD_OK;
@@ -566,10 +579,10 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   // fields and the caller's links, so no caller data is touched.
   // Stage 1: workgroup size, RHS block, XCD remap, z-slab traversal, RHS
   // interleave.  Stage 2: (y, z) tiles for the three fastest, each with and
-  // without one hop per iteration, non-temporal link loads.  Stage 3: the
-  // three fastest so far with the other schedules (loads first, one hop per
-  // iteration, non-temporal links) and occupancy caps.  Stage 4: the five
-  // fastest re-timed, best median.
+  // without one hop per iteration, non-temporal link loads and own-site
+  // streams.  Stage 3: the three fastest so far with the other schedules
+  // (loads first, one hop per iteration, non-temporal links and streams) and
+  // occupancy caps.  Stage 4: the five fastest re-timed, best median.
   std::vector<DslashCfg> cand;
   for (int blk : {64, 128, 256})
     for (int b : {1, 2, 4, 8}) {
@@ -684,10 +697,10 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     if (runs && tuning_verbose())
       fprintf(stderr,
               "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d mode=%d block=%d B=%d xcd=%d "
-              "ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d: %.2f us\n",
+              "ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d ns=%d: %.2f us\n",
               c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, t.mode, cfg.block,
               cfg.rhs_block, cfg.xcd, cfg.ty, cfg.tz, cfg.nt, cfg.occ, cfg.ilv, cfg.lf, cfg.hh,
-              1000.0 * ms);
+              cfg.ns, 1000.0 * ms);
     if (runs && ms < best_ms) {
       best_ms = ms;
       best = cfg;
@@ -714,19 +727,23 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
               v.ty = ty;
               v.tz = tz;
               v.nt = 1;
+              v.ns = 1;
               v.hh = hh;
               cand.push_back(v);
             }
       stage2 = cand.size();
     } else if (ci + 1 == stage2) {  // stage 3: schedules and occupancy caps
       for (const auto& tk : top3())
-        for (int nt : {0, 1})
+        for (int ntns : {0, 1, 3})  // bit 0: non-temporal links, bit 1: own-site streams too
           for (int lf : {0, 1})
             for (int hh : {0, 1})
               for (int occ : {0, 2, 3, 4}) {
                 DslashCfg v = tk.second;
-                if (nt == v.nt && lf == v.lf && hh == v.hh && occ == v.occ) continue;
+                const int nt = ntns & 1, ns = ntns >> 1;
+                if (nt == v.nt && ns == v.ns && lf == v.lf && hh == v.hh && occ == v.occ)
+                  continue;
                 v.nt = nt;
+                v.ns = ns;
                 v.lf = lf;
                 v.hh = hh;
                 v.occ = occ;
@@ -781,10 +798,10 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   if (tuning_verbose())
     fprintf(stderr,
             "[lqcd tune] chosen L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d mode=%d: block=%d B=%d "
-            "xcd=%d ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d (%.2f us)\n",
+            "xcd=%d ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d ns=%d (%.2f us)\n",
             c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, t.mode, best.block,
             best.rhs_block, best.xcd, best.ty, best.tz, best.nt, best.occ, best.ilv, best.lf,
-            best.hh, 1000.0 * best_ms);
+            best.hh, best.ns, 1000.0 * best_ms);
   *out = best;
   return LQCD_OK;
 }

@@ -41,6 +41,42 @@ __device__ __forceinline__ cplx<R> ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t vof
     return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
 }
 
+// Streaming access to a complex value that is read or written once: the
+// non-temporal hint lets the caches evict it first.  NT = false is a plain access.
+template <typename R, bool NT>
+__device__ __forceinline__ cplx<R> ld_once(const cplx<R>* p) {
+  if constexpr (!NT) {
+    return *p;
+  } else if constexpr (sizeof(R) == 4) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(p));
+    return mk<R>(v.x, v.y);
+  } else {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+    return mk<R>(v.x, v.y);
+  }
+}
+
+template <typename R, bool NT>
+__device__ __forceinline__ void st_once(cplx<R>* p, cplx<R> z) {
+  if constexpr (!NT) {
+    *p = z;
+  } else if constexpr (sizeof(R) == 4) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2 v;
+    v.x = z.x;
+    v.y = z.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<f2*>(p));
+  } else {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 v;
+    v.x = z.x;
+    v.y = z.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<d2*>(p));
+  }
+}
+
 // Load the link with half index h from a packed [NE][Vh] block.
 template <typename R, int NE>
 __device__ __forceinline__ void load_link(const cplx<R>* __restrict__ base, int h, int Vh,

@@ -177,12 +177,15 @@ def test_hop_24_vs_oracle(lq, prec, fmt, tol):
                                  "128,8,1,2,0,3,0,1", "256,1,0,0,0,0,0,1",
                                  "256,8,1,0,0,0,0,1,1", "128,4,0,2,0,0,1,0,1",
                                  "64,1,1,8,0,2,0,0,1", "128,2,1,4,1,0,0,1,0,2",
-                                 "64,8,0,2,1,0,1,0,1,2", "256,4,1,4,0,3,1,1,1,2"])
+                                 "64,8,0,2,1,0,1,0,1,2", "256,4,1,4,0,3,1,1,1,2",
+                                 "128,4,1,2,1,0,0,0,1,2,1", "64,8,0,0,1,3,1,1,0,0,1",
+                                 "256,2,1,4,1,0,0,0,0,0,1"])
 @pytest.mark.parametrize("prec,fmt,tol", [(0, 0, 1e-13), (1, 1, 1e-6)])
 def test_every_launch_configuration(lq, cfg, prec, fmt, tol, monkeypatch):
     """Each (workgroup, RHS block, XCD remap, z-slab or (y, z)-tile traversal,
     non-temporal links, occupancy cap, RHS interleave, loads-first schedule, one
-    hop per iteration) variant the tuner may pick gives the oracle's result;
+    hop per iteration, non-temporal own-site streams) variant the tuner may pick
+    gives the oracle's result;
     ragged RHS count and a lattice whose site count is not a multiple of the
     workgroup."""
     monkeypatch.setenv("LQCD_DSLASH_CFG", cfg)

@@ -110,6 +110,31 @@ def test_batched_rhs_match_single_rhs(lq):
 
 
 @pytest.mark.parametrize("mode", MODES[:2])
+@pytest.mark.parametrize("cfg", ["128,4,1,2,1,0,0,0,1,2", "64,2,0,0,1,3,1,1,0,0"])
+def test_nontemporal_streams_same_bits(lq, mode, cfg, monkeypatch):
+    """Marking the stencils' own-site operands and outputs non-temporal is a
+    cache hint only: every stencil mode of the solver (D_oe, the fused CG
+    update, the FP64 residual) pinned with and without it gives the same bits,
+    and every shift meets the tolerance."""
+    L = (8, 4, 6, 4)
+    U = synth.links_haar(L, 107)
+    g, U64, b_nat, b = setup(lq, L, U, 207, 3)
+    sig = synth.rational_shifts(5, 1e-3, 1.0)
+    p = lq.solver_params(mass=0.05, tol=1e-10, **mode)
+    out = []
+    for ns in (0, 1):
+        monkeypatch.setenv("LQCD_DSLASH_CFG", f"{cfg},{ns}")
+        lq.finalize()
+        X, _, stats = lq.cg_multishift(g, p, U64, sig, b)
+        assert all(s["converged"] == 1 and s["true_rel_residual"] <= 1e-10
+                   for row in stats for s in row)
+        out.append(X)
+    monkeypatch.delenv("LQCD_DSLASH_CFG")
+    lq.finalize()
+    assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("mode", MODES[:2])
 def test_determinism_and_graph_equivalence(lq, mode):
     """Two runs are bitwise equal, with and without hipGraph replay."""
     L = (8, 4, 6, 4)
