@@ -131,6 +131,28 @@ __device__ __forceinline__ int xcd_block(int b, int nb, int enable) {
 // Deterministic block sum of one double: butterfly inside each 64-lane wave,
 // then wave partials summed in order by thread 0.  The result is valid in
 // thread 0 only.  All threads of the block must call it.
+// This thread's share of sum_i p[i] over i = threadIdx.x + k blockDim.x < n,
+// added in increasing i.  The loads of a batch of kBatch terms are issued
+// before any is added, so a small workgroup reading partials that other
+// XCDs just wrote waits for a few memory round trips rather than one per
+// term; the order of the additions, and so the result, is the plain loop's.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int n) {
+  constexpr int kBatch = 16;
+  double s = 0.0;
+  for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * blockDim.x) {
+    double v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = i0 + u * int(blockDim.x);
+      v[u] = i < n ? p[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (i0 + u * int(blockDim.x) < n) s += v[u];
+  }
+  return s;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* lds) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

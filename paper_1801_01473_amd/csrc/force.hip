@@ -192,8 +192,7 @@ __global__ void __launch_bounds__(kActionBlock) k_action(int Vh, const double2* 
 __global__ void __launch_bounds__(kActionBlock) k_sum(const double* __restrict__ part, int n,
                                                       double* __restrict__ out) {
   __shared__ double lds[kActionBlock / 64];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  double s = strided_sum(part, n);
   s = block_sum(s, lds);
   if (threadIdx.x == 0) *out = s;
 }

@@ -62,8 +62,7 @@ constexpr int kVecBlock = 256;
 // Deterministic sum of p[0..n) by the whole workgroup, broadcast to all threads.
 __device__ double wg_sum(const double* __restrict__ p, int n, double* lds) {
   __shared__ double bc;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += p[i];
+  double s = strided_sum(p, n);
   s = block_sum(s, lds);
   if (threadIdx.x == 0) bc = s;
   __syncthreads();
@@ -698,8 +697,7 @@ __global__ void __launch_bounds__(kVecBlock) k_reduce_vec(const double* __restri
                                                           double* __restrict__ out) {
   __shared__ double lds[kVecBlock / 64];
   const int v = blockIdx.x;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[int64_t(v) * nb + i];
+  double s = strided_sum(part + int64_t(v) * nb, nb);
   s = block_sum(s, lds);
   if (threadIdx.x == 0) out[v] = s;
 }
