@@ -256,6 +256,54 @@ def config2_overhead(lq, torch):
     return out
 
 
+def rhmc_heatbath(lq, torch, g, U64, mass, nrhs, degree=14, seed=205):
+    """RHMC pseudofermion heatbath and accept/reject action on the workload
+    lattice: minimax x^(1/8) and x^(-1/4) of the given degree on the spectral
+    interval [m^2, m^2 + 16] (Remez, host); phi = r_{1/8}(A) xi for nrhs
+    Gaussian xi (mixed-precision multi-shift solve + combination kernel), then
+    S = phi^dag r_{-1/4}(A) phi.  Reports the times, the identity
+    S / |xi|^2 - 1 (bounded by 2 eps(1/8) + eps(-1/4) + solver error) and the
+    combination kernel's algorithmic bandwidth."""
+    import synth
+    L = tuple(g.L)
+    lo, hi = lq.spectral_bounds(mass)
+    t0 = time.time()
+    e = lq.minimax(0.125, lo, hi, degree)
+    q = lq.minimax(-0.25, lo, hi, degree)
+    t_remez = time.time() - t0
+    xi = lq.pack_spinor(g, torch.from_numpy(synth.gaussian_even_source(L, nrhs, seed)).to("cuda"),
+                        0)
+    p = lq.solver_params(mass=mass, tol=1e-10, inner_prec=lq.F32, inner_fmt=lq.LINKS12,
+                         reliable_interval=100, use_graph=1)
+    lq.pseudofermion_heatbath(g, p, U64, e, xi)  # tuning and graph capture for this shape
+    torch.cuda.synchronize()
+    t0 = time.time()
+    phi, st1 = lq.pseudofermion_heatbath(g, p, U64, e, xi)
+    torch.cuda.synchronize()
+    t_hb = time.time() - t0
+    t0 = time.time()
+    S, X, st2 = lq.rational_action(g, p, U64, q, phi)
+    torch.cuda.synchronize()
+    t_act = time.time() - t0
+    xi2 = float((xi.abs() ** 2).sum().item())
+    y = torch.empty_like(phi)
+    ms = event_time_ms(lambda: lq.rational_combine(g, q.alpha0, q.alpha, phi, X, out=y), 20)
+    nbytes = g.Vh * 48 * nrhs * (q.degree + 2)  # b and every X_i read once, y written
+    del X, y
+    out = dict(degree=degree, interval=[lo, hi], remez_s=t_remez,
+               eps_eighth=e.max_rel_error, eps_quarter=q.max_rel_error,
+               heatbath_s=t_hb, action_s=t_act,
+               identity_dev=abs(S / xi2 - 1.0),
+               identity_bound=2 * e.max_rel_error + q.max_rel_error,
+               max_true_rel_residual=max(s["true_rel_residual"] for st in (st1, st2)
+                                         for row in st for s in row),
+               combine_us=1000 * ms, combine_GBps=nbytes / (ms * 1e-3) / 1e9,
+               combine_frac_hbm_peak=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    log(f"RHMC heatbath ({nrhs} RHS, degree {degree}): {t_hb:.3f} s, action {t_act:.3f} s, "
+        f"|S/|xi|^2 - 1| = {out['identity_dev']:.2e}, combine {out['combine_GBps']:.0f} GB/s")
+    return out
+
+
 def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, X0=None, budget_s=20.0):
     """Oracle multi-shift CG timed on a bounded sample: a few iterations on one
     right-hand side of the same lattice, scaled to the GPU run's iteration
@@ -317,6 +365,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c4")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rhmc", action="store_true",
+                    help="skip the RHMC heatbath / action measurement")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="one solve + standalone D_oe + copy kernel, for counter runs")
     args = ap.parse_args()
@@ -477,6 +527,9 @@ def main():
     dsl["fp64_18_1rhs_32x4"] = dslash_entry(lq, torch, g32, U32, lq.F64, lq.LINKS18, 1,
                                             copy_gbs, "32^4, Gaussian 3x3 links (timing only)")
     del U32
+    rhmc = None
+    if not args.no_rhmc:
+        rhmc = rhmc_heatbath(lq, torch, g, U64, w["mass"], nrhs)
     kd = kernels[dominant]
     traffic = measured_traffic(dominant)
     roof = {
@@ -542,6 +595,7 @@ def main():
                    "fp64_max_true_rel_residual": fp64["max_true_residual"] if fp64 else None},
         "kernels": kernels,
         "dslash": dsl,
+        "rhmc_heatbath": rhmc,
         "stream": {"copy_GBps": copy_gbs, "triad_GBps": triad_gbs},
     }
     print(json.dumps(out), flush=True)

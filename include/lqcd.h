@@ -298,6 +298,26 @@ int lqcd_action(const lqcd_geom *g, int32_t npf, int32_t nshift, double alpha0,
                 void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Rational function of A applied to vectors, from the multi-shift solutions
+ * (Sec. 2: the shifts of Eq. (2) are the poles of the rational approximation
+ * used by RHMC):
+ *   y_j = alpha0 b_j + sum_i alpha_i X_ji,   X_ji = (A + sigma_i)^-1 b_j,
+ * so that y_j = r(A) b_j for r(x) = alpha0 + sum_i alpha_i / (x + sigma_i).
+ * With the coefficients of r ~ x^(1/8) and b = Gaussian noise this is the
+ * pseudofermion heatbath.
+ *   b      packed even FP64 [nrhs][3][Vh]
+ *   X      packed even FP64 [nrhs][nshift][3][Vh] (the x of lqcd_cg_multishift)
+ *   alpha  host [nshift]
+ *   y      packed even FP64 [nrhs][3][Vh]; may be b, must not overlap X.
+ * The terms are added in a fixed order (FP64 fused multiply-adds), so the
+ * result is reproducible.  1 <= nrhs <= 64, 1 <= nshift <= 32.  Stream-ordered,
+ * asynchronous, allocates nothing.
+ */
+int lqcd_rational_combine(const lqcd_geom *g, int32_t nrhs, int32_t nshift, double alpha0,
+                          const double *alpha, const void *b, const void *X, void *y,
+                          void *stream);
+
+/*
  * Achievable HBM bandwidth of the current device: STREAM-style copy
  * (read + write) and triad (2 reads + write) over `bytes` per array, median
  * of `reps` timed launches, in GB/s (1e9 B/s).  The roofline of the

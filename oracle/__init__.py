@@ -6,7 +6,8 @@ arrays are numpy complex128 in natural lexicographic layout (see the C file).
 
 Parity status: every function here is pinned in ``tests/test_oracle.py``
 (closed-form free-field spectrum, anti-Hermiticity, gauge covariance, dense
-LAPACK solves, exact derivatives and finite differences).  The one convention
+LAPACK solves, exact derivatives and finite differences); ``rational_apply``
+in ``tests/test_rational.py`` (dense eigendecomposition of A).  The one convention
 those pins cannot fix is the order of the staggered phases over the axes,
 eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}) with (x, y, z, t) = (0, 1, 2, 3):
 any ordering gives the same spectrum and symmetries, so that ordering is a
@@ -173,6 +174,26 @@ def cg_multishift(L, U, mass, sigmas, b, tol=1e-10, max_iter=10000, antiperiodic
                                    _ptr(sig), _ptr(b), _ptr(x), float(tol), int(max_iter),
                                    iters, _ptr(tr), 1 if verify else 0)
     return x, int(st), (int(iters[0]), int(iters[1])), tr
+
+
+def rational_apply(L, U, mass, alpha0, alpha, sigma, b, tol=1e-12, antiperiodic=True):
+    """r(A) b_j = alpha0 b_j + sum_i alpha_i (A + sigma_i)^-1 b_j for every row of
+    b (natural even-site [n][V][3]): a rational function of the even/odd
+    operator in partial fractions, whose poles are the shifts of Eq. (2)
+    (Sec. 2).  The oracle's multi-shift CG (with per-shift verification) to
+    tol, then the sum, term by term in FP64."""
+    V = _V(L)
+    b = np.ascontiguousarray(b, dtype=np.complex128).reshape(-1, V, 3)
+    out = np.empty_like(b)
+    for j in range(b.shape[0]):
+        X, st, _, _ = cg_multishift(L, U, mass, sigma, b[j], tol=tol, antiperiodic=antiperiodic)
+        if st != 0:
+            raise RuntimeError(f"oracle multi-shift CG failed with status {st}")
+        y = float(alpha0) * b[j]
+        for a, x in zip(alpha, X):
+            y = y + float(a) * x
+        out[j] = y
+    return out
 
 
 def action(L, alpha0, alpha, phi, X) -> float:

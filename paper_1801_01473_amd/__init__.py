@@ -1,6 +1,8 @@
 """Python binding of liblqcd, the MI355X staggered even/odd solver library.
 
 Argument marshalling only: every operation runs in the library's HIP kernels.
+(The one host-side computation is setup: the Remez exchange of ``rational``,
+which produces the rational approximations' poles and residues.)
 Tensors are torch tensors on the GPU (torch provides device memory and the
 current stream).  The binding fails loudly when the library has not been
 built; there is no CPU fallback.
@@ -13,10 +15,13 @@ Layouts follow ``include/lqcd.h``:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
 import torch
+
+from .rational import RationalApprox, minimax, minimax_for_tol, spectral_bounds  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblqcd.so")
@@ -113,6 +118,7 @@ _SIGS = {
     "lqcd_action_workspace_bytes": (ctypes.c_size_t, [_gp]),
     "lqcd_action": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp,
                                    ctypes.c_size_t, _vp]),
+    "lqcd_rational_combine": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _vp, _vp]),
     "lqcd_stream_bandwidth": (ctypes.c_int, [ctypes.c_size_t, _i32, _dp, _dp]),
     "lqcd_kernel_timing_enable": (ctypes.c_int, [_i32]),
     "lqcd_kernel_timing_get": (ctypes.c_int, [_i32, ctypes.c_char_p, ctypes.c_size_t,
@@ -385,6 +391,63 @@ def action(geom: Geometry, alpha0, alpha, phi, X) -> float:
     _check(_fn("lqcd_action")(geom.c(), npf, nshift, float(alpha0), al, _ptr(phi), _ptr(X),
                               ctypes.byref(S), _ptr(ws), ws.numel(), _stream()))
     return float(S.value)
+
+
+def rational_combine(geom: Geometry, alpha0, alpha, b, X, out=None):
+    """y_j = alpha0 b_j + sum_i alpha_i X_ji on the GPU (packed FP64 even
+    vectors; b [n][3][Vh], X [n][nshift][3][Vh]); out may be b."""
+    nshift = len(alpha)
+    n = b.numel() // (3 * geom.Vh)
+    if X.numel() != n * nshift * 3 * geom.Vh:
+        raise ValueError(f"X must hold {n} x {nshift} even vectors")
+    out = torch.empty_like(b) if out is None else out
+    al = (ctypes.c_double * nshift)(*[float(a) for a in alpha])
+    _check(_fn("lqcd_rational_combine")(geom.c(), n, nshift, float(alpha0), al, _ptr(b),
+                                        _ptr(X), _ptr(out), _stream()))
+    return out
+
+
+def rational_apply(geom: Geometry, params: SolverParams, U64, approx, b, Uinner=None):
+    """r(A) b for a rational function in partial fractions (a RationalApprox or
+    anything with alpha0, alpha, sigma): one multi-shift solve at the poles,
+    then the combination.  Returns (y, per-(rhs, shift) solve stats)."""
+    X, _, stats = cg_multishift(geom, params, U64, approx.sigma, b, Uinner=Uinner)
+    y = rational_combine(geom, approx.alpha0, approx.alpha, b, X)
+    return y, stats
+
+
+def pseudofermion_heatbath(geom: Geometry, params: SolverParams, U64, approx_eighth, xi,
+                           Uinner=None):
+    """RHMC pseudofermion heatbath (Sec. 2): phi = r(A) xi with r ~ x^(1/8) and
+    xi complex Gaussian noise of density exp(-|xi|^2) (drawn by the caller).
+    Then phi^dag A^(-1/4) phi = |xi|^2 up to the approximation errors, so phi
+    has the density exp(-phi^dag A^(-1/4) phi) of the pseudofermion action.
+    Returns (phi, stats)."""
+    if not (0.12 < approx_eighth.power < 0.13):
+        raise ValueError("the heatbath needs the x^(1/8) approximation")
+    return rational_apply(geom, params, U64, approx_eighth, xi, Uinner)
+
+
+def rational_action(geom: Geometry, params: SolverParams, U64, approx_quarter, phi,
+                    Uinner=None):
+    """S = sum_j phi_j^dag r(A) phi_j with r ~ x^(-1/4) (Eq. (1) fermion term in
+    rational form), FP64, for the accept/reject step.  Returns (S, X, stats);
+    X [n][nshift][3][Vh] serves the force as well."""
+    X, _, stats = cg_multishift(geom, params, U64, approx_quarter.sigma, phi, Uinner=Uinner)
+    S = action(geom, approx_quarter.alpha0, approx_quarter.alpha, phi, X)
+    return S, X, stats
+
+
+def metropolis_accept(h_old: float, h_new: float, u: float) -> bool:
+    """Accept/reject step of (R)HMC: accept with probability
+    min(1, exp(-(h_new - h_old))), for u uniform in [0, 1) drawn by the caller;
+    the energies are FP64 (the paper runs this test in double precision)."""
+    if not (0.0 <= u < 1.0):
+        raise ValueError("u must be in [0, 1)")
+    dh = float(h_new) - float(h_old)
+    if not math.isfinite(dh):
+        return False
+    return dh <= 0.0 or u < math.exp(-dh)
 
 
 def stream_bandwidth(nbytes: int = 1 << 30, reps: int = 20):

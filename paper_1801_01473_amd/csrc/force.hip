@@ -32,6 +32,7 @@ namespace {
 
 constexpr int kForceBlock = 256;  // 64 odd sites x 4 directions
 constexpr int kActionBlock = 256;
+constexpr int kCombineBlock = 256;
 
 struct Alphas {
   double a[kMaxShift];
@@ -197,6 +198,35 @@ __global__ void __launch_bounds__(kActionBlock) k_sum(const double* __restrict__
   if (threadIdx.x == 0) *out = s;
 }
 
+// y_j = alpha0 b_j + sum_i alpha_i X_ji for every complex element e of the
+// [3][Vh] even-site vectors (blockIdx.y = j).  The terms are added in a fixed
+// order (alpha0 b first, then i = 0, 1, ...), so the result is reproducible.
+// y may be b (each element is read before it is written), never X.
+__global__ void __launch_bounds__(kCombineBlock) k_rational_combine(
+    int64_t n, const double2* __restrict__ b, const double2* X, int nshift, double alpha0,
+    Alphas al, double2* y) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t j = blockIdx.y;
+  const double2 bv = b[j * n + e];
+  double re = alpha0 * bv.x, im = alpha0 * bv.y;
+  const double2* xj = X + j * nshift * n + e;
+  constexpr int kChunk = 8;  // loads issued together before their products
+  for (int i0 = 0; i0 < nshift; i0 += kChunk) {
+    double2 v[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u)
+      if (i0 + u < nshift) v[u] = xj[int64_t(i0 + u) * n];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u)
+      if (i0 + u < nshift) {
+        re = fma(al.a[i0 + u], v[u].x, re);
+        im = fma(al.a[i0 + u], v[u].y, im);
+      }
+  }
+  y[j * n + e] = make_double2(re, im);
+}
+
 int check_alpha(int32_t nshift, const double* alpha) {
   if (nshift < 1 || nshift > kMaxShift) {
     set_error("nshift = %d must be in [1, %d]", nshift, kMaxShift);
@@ -303,6 +333,41 @@ int lqcd_action(const lqcd_geom* g, int32_t npf, int32_t nshift, double alpha0,
   LQCD_LAUNCH_CHECK();
   LQCD_HIP_TRY(hipMemcpyAsync(S, out, sizeof(double), hipMemcpyDeviceToHost, s));
   LQCD_HIP_TRY(hipStreamSynchronize(s));
+  return LQCD_OK;
+}
+
+int lqcd_rational_combine(const lqcd_geom* g, int32_t nrhs, int32_t nshift, double alpha0,
+                          const double* alpha, const void* b, const void* X, void* y,
+                          void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(b, "b")) || (rc = check_ptr(X, "X")) ||
+      (rc = check_ptr(y, "y")) || (rc = check_alpha(nshift, alpha)))
+    return rc;
+  if (nrhs < 1 || nrhs > 64) {
+    set_error("nrhs = %d must be in [1, 64]", nrhs);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (!std::isfinite(alpha0)) {
+    set_error("alpha0 is not finite");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const int64_t n = int64_t(3) * k.Vh;
+  const char* xb = static_cast<const char*>(X);
+  const char* yb = static_cast<const char*>(y);
+  const int64_t xbytes = int64_t(nrhs) * nshift * n * int64_t(sizeof(double2));
+  const int64_t ybytes = int64_t(nrhs) * n * int64_t(sizeof(double2));
+  if (yb < xb + xbytes && xb < yb + ybytes) {
+    set_error("y must not overlap X");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  Alphas al{};
+  for (int i = 0; i < nshift; ++i) al.a[i] = alpha[i];
+  const dim3 grid(unsigned((n + kCombineBlock - 1) / kCombineBlock), unsigned(nrhs));
+  hipLaunchKernelGGL(k_rational_combine, grid, dim3(kCombineBlock), 0, (hipStream_t)stream, n,
+                     (const double2*)b, (const double2*)X, nshift, alpha0, al, (double2*)y);
+  LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
 
