@@ -66,6 +66,9 @@ def _load():
     lib.orc_action.restype = ctypes.c_double
     lib.orc_force.argtypes = [_ip, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp,
                               ctypes.c_int, _dp]
+    lib.orc_gauge_action.argtypes = [_ip, _dp, ctypes.c_double, ctypes.c_double]
+    lib.orc_gauge_action.restype = ctypes.c_double
+    lib.orc_gauge_force.argtypes = [_ip, _dp, ctypes.c_double, ctypes.c_double, _dp]
     lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_get_threads.restype = ctypes.c_int
     _lib = lib
@@ -174,6 +177,52 @@ def cg_multishift(L, U, mass, sigmas, b, tol=1e-10, max_iter=10000, antiperiodic
                                    _ptr(sig), _ptr(b), _ptr(x), float(tol), int(max_iter),
                                    iters, _ptr(tr), 1 if verify else 0)
     return x, int(st), (int(iters[0]), int(iters[1])), tr
+
+
+def gauge_action(L, U, beta: float, c1: float = -1.0 / 12.0) -> float:
+    """Tree-level Symanzik gauge action (Sec. 2): beta sum over every 1x1
+    plaquette (weight c0 = 1 - 8 c1) and every 1x2 rectangle in both
+    orientations (weight c1) of (1 - Re Tr W / 3).  c1 = 0: Wilson."""
+    V = _V(L)
+    U = _c128(U, (4, V, 3, 3))
+    return float(_load().orc_gauge_action(_geom(L), _ptr(U), float(beta), float(c1)))
+
+
+def gauge_force(L, U, beta: float, c1: float = -1.0 / 12.0) -> np.ndarray:
+    """F = TA(U M), dS_g = sum Re Tr[dU M] (the convention of ``force`` mode 0),
+    natural [4][V][3][3]."""
+    V = _V(L)
+    U = _c128(U, (4, V, 3, 3))
+    F = np.zeros((4, V, 3, 3), np.complex128)
+    _load().orc_gauge_force(_geom(L), _ptr(U), float(beta), float(c1), _ptr(F))
+    return F
+
+
+def md_momenta(H, F, eps: float) -> np.ndarray:
+    """Momentum step of the MD (Sec. 5, "new momenta"): with U' = i H U and the
+    force F = TA(U M) of ``force`` / ``gauge_force`` (dS/deps = sum Tr[T F]
+    for U -> exp(eps T) U), energy conservation of H^2/2 + S gives
+    H' = -i F, so H <- H - i eps F.  Natural [4][V][3][3]."""
+    return np.asarray(H, dtype=np.complex128) - 1j * float(eps) * np.asarray(F)
+
+
+def md_links(U, H, eps: float) -> np.ndarray:
+    """Link step of the MD ("new configuration"): U <- exp(i eps H) U, the
+    matrix exponential of each link's momentum (scipy.linalg.expm)."""
+    from scipy.linalg import expm
+    U = np.asarray(U, dtype=np.complex128)
+    H = np.asarray(H, dtype=np.complex128)
+    out = np.empty_like(U)
+    for mu in range(U.shape[0]):
+        for x in range(U.shape[1]):
+            out[mu, x] = expm(1j * float(eps) * H[mu, x]) @ U[mu, x]
+    return out
+
+
+def kinetic_energy(H) -> float:
+    """H^2 / 2 of Eq. (1): half the sum over links of Tr H^2 (H Hermitian)."""
+    H = np.asarray(H, dtype=np.complex128)
+    return 0.5 * float(np.real(np.einsum("...ab,...ba->...", H, H).sum()))
 
 
 def rational_apply(L, U, mass, alpha0, alpha, sigma, b, tol=1e-12, antiperiodic=True):

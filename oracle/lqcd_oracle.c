@@ -32,6 +32,15 @@
  *   force              the derivative of that action with respect to the
  *                      links (the fermion force driving the MD, Sec. 2 and
  *                      Sec. 4), as the exact derivative of the quadratic form.
+ *   gauge_action       the tree-level Symanzik gauge action S_g of Eq. (1):
+ *                      every 1x1 plaquette and every 1x2 rectangle (both
+ *                      orientations) enumerated once, weights c0 = 1 - 8 c1
+ *                      and c1 (Sec. 2).
+ *   gauge_force        its derivative with respect to the links: for every
+ *                      loop and every link on it, the product of the other
+ *                      links around the loop (the exact derivative of the
+ *                      loop's real trace), then the su(3) projection used by
+ *                      force (Sec. 4, the MD gauge term).
  */
 #include <complex.h>
 #include <math.h>
@@ -477,6 +486,169 @@ void orc_force(const int *L, int anti, const double *Ud, int npf, int nshift,
     }
     free(M);
     free(chi);
+}
+
+/* ------------------------------------------------------------------ */
+/* gauge action and force (tree-level Symanzik)                          */
+/* ------------------------------------------------------------------ */
+
+static void mat_mul(const cplx *A, const cplx *B, cplx *C)
+{
+    cplx T[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            cplx s = 0;
+            for (int k = 0; k < 3; ++k) s += A[a * 3 + k] * B[k * 3 + b];
+            T[a * 3 + b] = s;
+        }
+    memcpy(C, T, sizeof(T));
+}
+
+static void mat_dag(const cplx *A, cplx *B)
+{
+    cplx T[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) T[a * 3 + b] = conj(A[b * 3 + a]);
+    memcpy(B, T, sizeof(T));
+}
+
+/* One closed path of n links: link k is U_{mu[k]}(site[k]), used as U (dag 0)
+ * or as U^dag (dag 1). */
+typedef struct {
+    int n;
+    long site[6];
+    int mu[6];
+    int dag[6];
+} loop_t;
+
+static void path_add(const int L[4], loop_t *lp, int c[4], int mu, int dir)
+{
+    int nb[4];
+    if (dir > 0) {
+        lp->site[lp->n] = lex_of(L, c);
+        lp->mu[lp->n] = mu;
+        lp->dag[lp->n] = 0;
+        step(L, c, mu, +1, nb);
+    } else {
+        step(L, c, mu, -1, nb);
+        lp->site[lp->n] = lex_of(L, nb);
+        lp->mu[lp->n] = mu;
+        lp->dag[lp->n] = 1;
+    }
+    lp->n++;
+    for (int k = 0; k < 4; ++k) c[k] = nb[k];
+}
+
+/* matrix of link k of the loop as it enters the product */
+static void loop_link(const cplx *U, long V, const loop_t *lp, int k, cplx *out)
+{
+    const cplx *u = link_at(U, V, lp->mu[k], lp->site[k]);
+    if (lp->dag[k])
+        mat_dag(u, out);
+    else
+        memcpy(out, u, 9 * sizeof(cplx));
+}
+
+/* the loops whose first corner is x: plaquettes mu < nu (weight c0) and the
+ * 2 (along mu) x 1 (along nu) rectangles for every mu != nu (weight c1) */
+static int loops_at(const int L[4], long x, loop_t lps[18], double w[18], double c0, double c1)
+{
+    int n = 0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu) {
+            if (nu == mu) continue;
+            int c[4];
+            if (mu < nu) {
+                coords_of(L, x, c);
+                loop_t *lp = &lps[n];
+                lp->n = 0;
+                path_add(L, lp, c, mu, +1);
+                path_add(L, lp, c, nu, +1);
+                path_add(L, lp, c, mu, -1);
+                path_add(L, lp, c, nu, -1);
+                w[n++] = c0;
+            }
+            coords_of(L, x, c);
+            loop_t *lp = &lps[n];
+            lp->n = 0;
+            path_add(L, lp, c, mu, +1);
+            path_add(L, lp, c, mu, +1);
+            path_add(L, lp, c, nu, +1);
+            path_add(L, lp, c, mu, -1);
+            path_add(L, lp, c, mu, -1);
+            path_add(L, lp, c, nu, -1);
+            w[n++] = c1;
+        }
+    return n;
+}
+
+/* S_g = beta sum_loops w (1 - Re Tr W / 3) */
+double orc_gauge_action(const int *L, const double *Ud, double beta, double c1)
+{
+    const long V = volume_of(L);
+    const cplx *U = (const cplx *)Ud;
+    const double c0 = 1.0 - 8.0 * c1;
+    double S = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : S)
+    for (long x = 0; x < V; ++x) {
+        loop_t lps[18];
+        double w[18];
+        const int nl = loops_at(L, x, lps, w, c0, c1);
+        for (int l = 0; l < nl; ++l) {
+            cplx W[9], Lk[9];
+            loop_link(U, V, &lps[l], 0, W);
+            for (int k = 1; k < lps[l].n; ++k) {
+                loop_link(U, V, &lps[l], k, Lk);
+                mat_mul(W, Lk, W);
+            }
+            S += beta * w[l] * (1.0 - creal(W[0] + W[4] + W[8]) / 3.0);
+        }
+    }
+    return S;
+}
+
+/* F = TA(U M) with dS_g = sum Re Tr[dU M]: for a loop W = L_1 ... L_n and
+ * its link k, d Re Tr W = Re Tr[dL_k R_k] with R_k = L_{k+1} ... L_n L_1
+ * ... L_{k-1}; for L_k = U that is Re Tr[dU R_k], for L_k = U^dag it is
+ * Re Tr[dU R_k^dag].  F natural [4][V][3][3]. */
+void orc_gauge_force(const int *L, const double *Ud, double beta, double c1, double *Fd)
+{
+    const long V = volume_of(L);
+    const cplx *U = (const cplx *)Ud;
+    cplx *F = (cplx *)Fd;
+    const double c0 = 1.0 - 8.0 * c1;
+    cplx *M = calloc((size_t)4 * V * 9, sizeof(cplx));
+    for (long x = 0; x < V; ++x) {
+        loop_t lps[18];
+        double w[18];
+        const int nl = loops_at(L, x, lps, w, c0, c1);
+        for (int l = 0; l < nl; ++l) {
+            const loop_t *lp = &lps[l];
+            for (int k = 0; k < lp->n; ++k) {
+                cplx R[9], Lk[9];
+                memset(R, 0, sizeof(R));
+                R[0] = R[4] = R[8] = 1.0;
+                for (int q = 1; q < lp->n; ++q) {
+                    loop_link(U, V, lp, (k + q) % lp->n, Lk);
+                    mat_mul(R, Lk, R);
+                }
+                if (lp->dag[k]) mat_dag(R, R);
+                cplx *Ml = M + ((long)lp->mu[k] * V + lp->site[k]) * 9;
+                for (int e = 0; e < 9; ++e) Ml[e] += -beta * w[l] / 3.0 * R[e];
+            }
+        }
+    }
+    for (long l = 0; l < 4 * V; ++l) {
+        cplx W[9];
+        mat_mul(U + l * 9, M + l * 9, W);
+        cplx tr = 0;
+        for (int a = 0; a < 3; ++a) tr += W[a * 3 + a] - conj(W[a * 3 + a]);
+        cplx *Fl = F + l * 9;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                Fl[a * 3 + b] = 0.5 * (W[a * 3 + b] - conj(W[b * 3 + a])) - (a == b ? tr / 6.0 : 0);
+    }
+    free(M);
 }
 
 /* ------------------------------------------------------------------ */

@@ -205,6 +205,14 @@ def su3_algebra_directions(L, n: int, seed: int) -> np.ndarray:
     return su3_from_coeffs(su3_algebra_coeffs(L, n, seed))
 
 
+def momenta(L, seed: int) -> np.ndarray:
+    """Gaussian MD momenta, one traceless Hermitian matrix per link ``[4][V][3][3]``
+    with density exp(-Tr H^2 / 2): H = sum_a c_a lambda_a / sqrt(2), c_a ~ N(0, 1)
+    (Tr lambda_a lambda_b = 2 delta_ab)."""
+    c = rng(seed).standard_normal((4, volume(L), 8))
+    return np.einsum("...a,aij->...ij", c, _gell_mann() / np.sqrt(2.0))
+
+
 def random_gauge_transform(L, seed: int) -> np.ndarray:
     """A Haar SU(3) matrix per site, ``[V][3][3]``."""
     return haar_su3(rng(seed), volume(L))
