@@ -318,6 +318,55 @@ int lqcd_rational_combine(const lqcd_geom *g, int32_t nrhs, int32_t nshift, doub
                           void *stream);
 
 /*
+ * Gauge part of the molecular dynamics (Sec. 2, Sec. 5).  Links U64 and
+ * momenta H use the packed FP64 18-real link layout [2][4][9][Vh] (complex);
+ * gauge links carry no boundary sign or staggered phase.
+ *
+ * Tree-level Symanzik action (Sec. 2: only 1x1 and 1x2 loops enter):
+ *   S_g = beta sum_x [ c0 sum_{mu<nu} (1 - Re Tr P_mu,nu(x)/3)
+ *                    + c1 sum_{mu!=nu} (1 - Re Tr R_mu,nu(x)/3) ],
+ * P the plaquette, R the rectangle two links along mu and one along nu,
+ * c0 = 1 - 8 c1; c1 = -1/12 is tree-level Symanzik, c1 = 0 Wilson.  The
+ * result (FP64, fixed-order reduction) is written to *S on the host; ws must
+ * hold lqcd_gauge_workspace_bytes(g) bytes; synchronises the stream.
+ */
+size_t lqcd_gauge_workspace_bytes(const lqcd_geom *g);
+int lqcd_gauge_action(const lqcd_geom *g, const void *U64, double beta, double c1, double *S,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Gauge force: F = TA(U M) with dS_g = sum Re Tr[dU M] (the convention of
+ * lqcd_fermion_force mode 0), i.e. F_mu(x) = -(beta/3) TA(U_mu(x) A_mu(x)),
+ * A the c0/c1-weighted sum of the 6 plaquette and 18 rectangle staples of the
+ * link.  accumulate != 0 adds into F (e.g. onto the fermion force).  One
+ * thread per link; F must not alias U64.  Stream-ordered, asynchronous.
+ */
+int lqcd_gauge_force(const lqcd_geom *g, const void *U64, double beta, double c1,
+                     int32_t accumulate, void *F, void *stream);
+
+/*
+ * MD steps (Sec. 5: "new momenta", "new configuration").  With U' = i H U,
+ * H Hermitian traceless, and F the force above, H^2/2 + S is conserved by
+ * H' = -i F:
+ *   lqcd_md_update_momenta: H <- H - i eps F           (F must not alias H)
+ *   lqcd_md_update_links:   U <- exp(i eps H) U, the exponential by scaling
+ *     and squaring of a degree-12 Taylor polynomial, then the rows
+ *     re-orthonormalised (row 2 = conj(row0 x row1)), so U stays in SU(3).
+ * Stream-ordered, asynchronous, allocate nothing.
+ */
+int lqcd_md_update_momenta(const lqcd_geom *g, const void *F, double eps, void *H,
+                           void *stream);
+int lqcd_md_update_links(const lqcd_geom *g, const void *H, double eps, void *U64,
+                         void *stream);
+
+/*
+ * Kinetic term H^2/2 of Eq. (1): half the sum over links of Tr H^2 (FP64,
+ * fixed-order reduction) to *K on the host; ws as for lqcd_gauge_action.
+ */
+int lqcd_kinetic_energy(const lqcd_geom *g, const void *H, double *K, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/*
  * Achievable HBM bandwidth of the current device: STREAM-style copy
  * (read + write) and triad (2 reads + write) over `bytes` per array, median
  * of `reps` timed launches, in GB/s (1e9 B/s).  The roofline of the

@@ -119,6 +119,12 @@ _SIGS = {
     "lqcd_action": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp,
                                    ctypes.c_size_t, _vp]),
     "lqcd_rational_combine": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _vp, _vp]),
+    "lqcd_gauge_workspace_bytes": (ctypes.c_size_t, [_gp]),
+    "lqcd_gauge_action": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _dp, _vp, ctypes.c_size_t, _vp]),
+    "lqcd_gauge_force": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
+    "lqcd_md_update_momenta": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _vp]),
+    "lqcd_md_update_links": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _vp]),
+    "lqcd_kinetic_energy": (ctypes.c_int, [_gp, _vp, _dp, _vp, ctypes.c_size_t, _vp]),
     "lqcd_stream_bandwidth": (ctypes.c_int, [ctypes.c_size_t, _i32, _dp, _dp]),
     "lqcd_kernel_timing_enable": (ctypes.c_int, [_i32]),
     "lqcd_kernel_timing_get": (ctypes.c_int, [_i32, ctypes.c_char_p, ctypes.c_size_t,
@@ -448,6 +454,131 @@ def metropolis_accept(h_old: float, h_new: float, u: float) -> bool:
     if not math.isfinite(dh):
         return False
     return dh <= 0.0 or u < math.exp(-dh)
+
+
+SYMANZIK_C1 = -1.0 / 12.0
+
+
+def gauge_action(geom: Geometry, U64, beta: float, c1: float = SYMANZIK_C1) -> float:
+    """Tree-level Symanzik gauge action S_g (c1 = 0: Wilson) of packed FP64
+    18-real links."""
+    ws = _workspace(int(_fn("lqcd_gauge_workspace_bytes")(geom.c())), U64.device)
+    S = ctypes.c_double(0.0)
+    _check(_fn("lqcd_gauge_action")(geom.c(), _ptr(U64), float(beta), float(c1), ctypes.byref(S),
+                                    _ptr(ws), ws.numel(), _stream()))
+    return float(S.value)
+
+
+def gauge_force(geom: Geometry, U64, beta: float, c1: float = SYMANZIK_C1, out=None,
+                accumulate=False):
+    """F = TA(U M) of S_g, packed like the links; accumulate adds into out."""
+    out = empty_links(geom, F64, LINKS18, U64.device) if out is None else out
+    _check(_fn("lqcd_gauge_force")(geom.c(), _ptr(U64), float(beta), float(c1),
+                                   1 if accumulate else 0, _ptr(out), _stream()))
+    return out
+
+
+def md_update_momenta(geom: Geometry, H, F, eps: float):
+    """H <- H - i eps F in place."""
+    _check(_fn("lqcd_md_update_momenta")(geom.c(), _ptr(F), float(eps), _ptr(H), _stream()))
+    return H
+
+
+def md_update_links(geom: Geometry, U64, H, eps: float):
+    """U <- exp(i eps H) U in place (re-orthonormalised to SU(3))."""
+    _check(_fn("lqcd_md_update_links")(geom.c(), _ptr(H), float(eps), _ptr(U64), _stream()))
+    return U64
+
+
+def kinetic_energy(geom: Geometry, H) -> float:
+    """H^2 / 2 = half the sum over links of Tr H^2."""
+    ws = _workspace(int(_fn("lqcd_gauge_workspace_bytes")(geom.c())), H.device)
+    K = ctypes.c_double(0.0)
+    _check(_fn("lqcd_kinetic_energy")(geom.c(), _ptr(H), ctypes.byref(K), _ptr(ws), ws.numel(),
+                                      _stream()))
+    return float(K.value)
+
+
+OMELYAN_LAMBDA = 0.1931833275037836
+
+
+def md_integrate(geom: Geometry, U64, H, tau: float, nsteps: int, force,
+                 integrator: str = "omelyan", lam: float = OMELYAN_LAMBDA):
+    """Integrate U' = i H U, H' = -i F(U) from 0 to tau in nsteps steps, in
+    place (Sec. 5: force, new momenta, new configuration).  force(U64, F)
+    writes the total force into F.  "leapfrog": kick eps/2, (drift eps,
+    kick eps) ..., last kick eps/2; "omelyan": the second-order minimum-norm
+    scheme kick lam eps, drift eps/2, kick (1 - 2 lam) eps, drift eps/2,
+    kick lam eps, adjacent kicks of consecutive steps merged.  Returns the
+    number of force evaluations."""
+    if nsteps < 1 or not math.isfinite(tau):
+        raise ValueError("need nsteps >= 1 and a finite tau")
+    eps = float(tau) / nsteps
+    F = empty_links(geom, F64, LINKS18, U64.device)
+    nforce = 0
+
+    def kick(c):
+        nonlocal nforce
+        force(U64, F)
+        nforce += 1
+        md_update_momenta(geom, H, F, c * eps)
+
+    def drift(c):
+        md_update_links(geom, U64, H, c * eps)
+
+    if integrator == "leapfrog":
+        kick(0.5)
+        for n in range(nsteps):
+            drift(1.0)
+            kick(1.0 if n < nsteps - 1 else 0.5)
+    elif integrator == "omelyan":
+        kick(lam)
+        for n in range(nsteps):
+            drift(0.5)
+            kick(1.0 - 2.0 * lam)
+            drift(0.5)
+            kick(2.0 * lam if n < nsteps - 1 else lam)
+    else:
+        raise ValueError(f"unknown integrator {integrator!r}")
+    return nforce
+
+
+def rhmc_trajectory(geom: Geometry, params: SolverParams, U64, beta: float, approx_eighth,
+                    approx_quarter, xi, H, u: float, tau: float = 1.0, nsteps: int = 10,
+                    c1: float = SYMANZIK_C1, integrator: str = "omelyan"):
+    """One RHMC trajectory (Sec. 2, Sec. 5) for one staggered field with the
+    pseudofermion action phi^dag A^(-1/4) phi (Eq. (1)):
+      heatbath phi = r_{1/8}(A) xi; H_0 = H^2/2 + S_g + S_f;
+      MD over tau with the gauge + fermion force (the fermion force from a
+      multi-shift solve at the poles of r_{-1/4} at the current links);
+      H_1; accept with probability min(1, exp(-(H_1 - H_0))) for the caller's
+      uniform u, else restore the links.
+    U64 (packed FP64 18-real) and H (packed momenta, Hermitian traceless) are
+    updated in place; xi [n][3][Vh] packed even FP64 noise of density
+    exp(-|xi|^2).  Returns a dict with the energies, dH, accepted and counts."""
+    U0 = U64.clone()
+    phi, _ = pseudofermion_heatbath(geom, params, U64, approx_eighth, xi)
+    q = approx_quarter
+
+    def energy():
+        S_f, _, st = rational_action(geom, params, U64, q, phi)
+        return kinetic_energy(geom, H), gauge_action(geom, U64, beta, c1), S_f
+
+    def force(U, F):
+        X, _, _ = cg_multishift(geom, params, U, q.sigma, phi)
+        fermion_force(geom, U, q.alpha, X, mode=0, out=F)
+        del X
+        gauge_force(geom, U, beta, c1, out=F, accumulate=True)
+
+    e0 = energy()
+    nforce = md_integrate(geom, U64, H, tau, nsteps, force, integrator)
+    e1 = energy()
+    h0, h1 = sum(e0), sum(e1)
+    acc = metropolis_accept(h0, h1, u)
+    if not acc:
+        U64.copy_(U0)
+    return dict(H0=h0, H1=h1, dH=h1 - h0, accepted=acc, force_evaluations=nforce,
+                kinetic=(e0[0], e1[0]), gauge=(e0[1], e1[1]), fermion=(e0[2], e1[2]))
 
 
 def stream_bandwidth(nbytes: int = 1 << 30, reps: int = 20):

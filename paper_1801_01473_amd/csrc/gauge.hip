@@ -1,0 +1,585 @@
+// Gauge part of the molecular dynamics (Sec. 2 and Sec. 5): the tree-level
+// Symanzik action (1x1 plaquettes and 1x2 rectangles of the links), its
+// force, the momentum and link steps of the integrator and the kinetic
+// energy.  FP64 throughout (the accept/reject test compares energies in
+// double precision, Sec. 6).
+//
+// Links and momenta use the packed 18-real FP64 link layout
+// [parity][mu][9][Vh] (complex), the layout of LQCD_LINKS18 links, so the
+// fermion force can be added into the same array.  Gauge links carry no
+// boundary sign or staggered phase (those belong to the fermion operator).
+//
+// Force convention (shared with the fermion force): with dS = sum Re Tr[dU M],
+// F = TA(U M), TA(W) = (W - W^dag)/2 - Tr(W - W^dag)/6, so that dS/deps =
+// sum Tr[T F] for U -> exp(eps T) U.  For S_g = beta sum_loops w (1 - Re Tr
+// W / 3), M_mu(x) = -(beta / 3) A_mu(x) with A the weighted sum of the staples
+// of the link (the product of the other links of each loop through it).  The
+// MD equations U' = i H U, H' = -i F conserve H^2/2 + S.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.h"
+
+namespace lqcd {
+
+namespace {
+
+constexpr int kGaugeBlock = 128;
+constexpr int kMdBlock = 256;
+
+struct M3 {
+  double2 e[9];
+};
+
+__device__ __forceinline__ M3 m_zero() {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) r.e[i] = make_double2(0.0, 0.0);
+  return r;
+}
+
+__device__ __forceinline__ M3 m_unit() {
+  M3 r = m_zero();
+  r.e[0].x = r.e[4].x = r.e[8].x = 1.0;
+  return r;
+}
+
+// a b, a b^dag, a^dag b
+__device__ __forceinline__ M3 m_mul(const M3& a, const M3& b) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s = cmul<double>(a.e[3 * i], b.e[j]);
+      cfma<double>(s, a.e[3 * i + 1], b.e[3 + j]);
+      cfma<double>(s, a.e[3 * i + 2], b.e[6 + j]);
+      r.e[3 * i + j] = s;
+    }
+  return r;
+}
+
+__device__ __forceinline__ M3 m_mul_dag(const M3& a, const M3& b) {
+  M3 r;  // r_ij = sum_k a_ik conj(b_jk)
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s = cmulc<double>(b.e[3 * j], a.e[3 * i]);
+      cfmac<double>(s, b.e[3 * j + 1], a.e[3 * i + 1]);
+      cfmac<double>(s, b.e[3 * j + 2], a.e[3 * i + 2]);
+      r.e[3 * i + j] = s;
+    }
+  return r;
+}
+
+__device__ __forceinline__ M3 m_dag_mul(const M3& a, const M3& b) {
+  M3 r;  // r_ij = sum_k conj(a_ki) b_kj
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s = cmulc<double>(a.e[i], b.e[j]);
+      cfmac<double>(s, a.e[3 + i], b.e[3 + j]);
+      cfmac<double>(s, a.e[6 + i], b.e[6 + j]);
+      r.e[3 * i + j] = s;
+    }
+  return r;
+}
+
+__device__ __forceinline__ void m_axpy(double w, const M3& a, M3& acc) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    acc.e[i].x = fma(w, a.e[i].x, acc.e[i].x);
+    acc.e[i].y = fma(w, a.e[i].y, acc.e[i].y);
+  }
+}
+
+__device__ __forceinline__ double re_tr(const M3& a) { return a.e[0].x + a.e[4].x + a.e[8].x; }
+
+// Coordinates with periodic wrap (named fields: a direction index chosen at
+// run time selects among them, so nothing is indexed dynamically), and the
+// link U_mu at a site.
+struct C4 {
+  int x, y, z, t;
+};
+
+__device__ __forceinline__ int wrap(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+__device__ __forceinline__ C4 shift(const KGeom& g, C4 s, int mu, int d) {
+  if (mu == 0)
+    s.x = wrap(s.x + d, g.Lx);
+  else if (mu == 1)
+    s.y = wrap(s.y + d, g.Ly);
+  else if (mu == 2)
+    s.z = wrap(s.z + d, g.Lz);
+  else
+    s.t = wrap(s.t + d, g.Lt);
+  return s;
+}
+
+__device__ __forceinline__ M3 link(const KGeom& g, const double2* __restrict__ U, const C4& s,
+                                   int mu) {
+  const int par = (s.x + s.y + s.z + s.t) & 1;
+  const int h = (s.x >> 1) + g.Lxh * (s.y + g.Ly * (s.z + g.Lz * s.t));
+  const double2* p = U + (int64_t(par) * 4 + mu) * 9 * int64_t(g.Vh) + h;
+  M3 r;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) r.e[e] = p[int64_t(e) * g.Vh];
+  return r;
+}
+
+__device__ __forceinline__ C4 site_c4(const KGeom& g, int h, int par) {
+  const Site s = decode_site(g, h, par);
+  return C4{s.x, s.y, s.z, s.t};
+}
+
+// Weighted staple sum of the link U_mu(x): Tr[U_mu(x) A] runs over every
+// plaquette (weight c0) and every 1x2 rectangle (weight c1) through the link,
+// each as the loop that starts along the link.
+__device__ M3 staples(const KGeom& g, const double2* __restrict__ U, const C4& x, int mu,
+                      double c0, double c1) {
+  M3 A = m_zero();
+#pragma unroll 1
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) continue;
+    const C4 xp = shift(g, x, mu, 1), xn = shift(g, x, nu, 1), xm = shift(g, x, nu, -1);
+    const C4 xpm = shift(g, xp, nu, -1);
+    // plaquettes: up U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag,
+    //             down U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+    {
+      M3 t = m_mul_dag(link(g, U, xp, nu), link(g, U, xn, mu));
+      t = m_mul_dag(t, link(g, U, x, nu));
+      m_axpy(c0, t, A);
+      t = m_dag_mul(link(g, U, xpm, nu), m_dag_mul(link(g, U, xm, mu), link(g, U, xm, nu)));
+      m_axpy(c0, t, A);
+    }
+    if (c1 == 0.0) continue;
+    const C4 xmu = shift(g, x, mu, -1);
+    const C4 x2p = shift(g, xp, mu, 1);
+    // 2 x 1, link first, up:
+    //   U_mu(x+mu) U_nu(x+2mu) U_mu(x+mu+nu)^dag U_mu(x+nu)^dag U_nu(x)^dag
+    {
+      M3 t = m_mul(link(g, U, xp, mu), link(g, U, x2p, nu));
+      t = m_mul_dag(t, link(g, U, shift(g, xp, nu, 1), mu));
+      t = m_mul_dag(t, link(g, U, xn, mu));
+      t = m_mul_dag(t, link(g, U, x, nu));
+      m_axpy(c1, t, A);
+    }
+    // 2 x 1, link second, up:
+    //   U_nu(x+mu) U_mu(x+nu)^dag U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu)
+    {
+      M3 t = m_mul_dag(link(g, U, xp, nu), link(g, U, xn, mu));
+      t = m_mul_dag(t, link(g, U, shift(g, xmu, nu, 1), mu));
+      t = m_mul_dag(t, link(g, U, xmu, nu));
+      t = m_mul(t, link(g, U, xmu, mu));
+      m_axpy(c1, t, A);
+    }
+    // 2 x 1, link first, down:
+    //   U_mu(x+mu) U_nu(x+2mu-nu)^dag U_mu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+    {
+      M3 t = m_mul_dag(link(g, U, xp, mu), link(g, U, shift(g, x2p, nu, -1), nu));
+      t = m_mul_dag(t, link(g, U, xpm, mu));
+      t = m_mul_dag(t, link(g, U, xm, mu));
+      t = m_mul(t, link(g, U, xm, nu));
+      m_axpy(c1, t, A);
+    }
+    // 2 x 1, link second, down:
+    //   U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_mu(x-mu-nu)^dag U_nu(x-mu-nu) U_mu(x-mu)
+    {
+      const C4 xmm = shift(g, xmu, nu, -1);
+      M3 t = m_dag_mul(link(g, U, xpm, nu), m_dag_mul(link(g, U, xm, mu), m_unit()));
+      t = m_mul_dag(t, link(g, U, xmm, mu));
+      t = m_mul(t, link(g, U, xmm, nu));
+      t = m_mul(t, link(g, U, xmu, mu));
+      m_axpy(c1, t, A);
+    }
+    // 1 x 2, up: U_nu(x+mu) U_nu(x+mu+nu) U_mu(x+2nu)^dag U_nu(x+nu)^dag U_nu(x)^dag
+    {
+      M3 t = m_mul(link(g, U, xp, nu), link(g, U, shift(g, xp, nu, 1), nu));
+      t = m_mul_dag(t, link(g, U, shift(g, xn, nu, 1), mu));
+      t = m_mul_dag(t, link(g, U, xn, nu));
+      t = m_mul_dag(t, link(g, U, x, nu));
+      m_axpy(c1, t, A);
+    }
+    // 1 x 2, down:
+    //   U_nu(x+mu-nu)^dag U_nu(x+mu-2nu)^dag U_mu(x-2nu)^dag U_nu(x-2nu) U_nu(x-nu)
+    {
+      const C4 xm2 = shift(g, xm, nu, -1);
+      M3 t = m_dag_mul(link(g, U, xpm, nu), m_dag_mul(link(g, U, shift(g, xpm, nu, -1), nu),
+                                                      m_unit()));
+      t = m_mul_dag(t, link(g, U, xm2, mu));
+      t = m_mul(t, link(g, U, xm2, nu));
+      t = m_mul(t, link(g, U, xm, nu));
+      m_axpy(c1, t, A);
+    }
+  }
+  return A;
+}
+
+// TA(W) = (W - W^dag)/2 - Tr(W - W^dag)/6
+__device__ __forceinline__ M3 traceless_antiherm(const M3& w) {
+  M3 r;
+  const double tr_im = (w.e[0].y + w.e[4].y + w.e[8].y) / 3.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double2 a = w.e[3 * i + j], b = w.e[3 * j + i];
+      r.e[3 * i + j] = make_double2(0.5 * (a.x - b.x), 0.5 * (a.y + b.y) - (i == j ? tr_im : 0.0));
+    }
+  return r;
+}
+
+// One thread per link: idx = (parity * 4 + mu) * Vh + h, so each (parity,
+// mu, element) plane is written coalesced.
+__global__ void __launch_bounds__(kGaugeBlock) k_gauge_force(KGeom g, const double2* __restrict__ U,
+                                                             double beta, double c0, double c1,
+                                                             int accumulate, double2* F) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(8) * g.Vh) return;
+  const int h = int(idx % g.Vh);
+  const int pm = int(idx / g.Vh);
+  const int par = pm >> 2, mu = pm & 3;
+  const C4 x = site_c4(g, h, par);
+  const M3 A = staples(g, U, x, mu, c0, c1);
+  M3 W = m_mul(link(g, U, x, mu), A);
+  const double s = -beta / 3.0;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) W.e[e] = make_double2(s * W.e[e].x, s * W.e[e].y);
+  const M3 f = traceless_antiherm(W);
+  double2* out = F + int64_t(pm) * 9 * g.Vh + h;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double2 v = f.e[e];
+    if (accumulate) {
+      const double2 o = out[int64_t(e) * g.Vh];
+      v.x += o.x;
+      v.y += o.y;
+    }
+    out[int64_t(e) * g.Vh] = v;
+  }
+}
+
+// Sum over the loops whose first corner is the thread's site of
+// w (1 - Re Tr W / 3): plaquettes mu < nu, 2 x 1 rectangles for every mu != nu.
+__global__ void __launch_bounds__(kGaugeBlock) k_gauge_action(KGeom g, const double2* __restrict__ U,
+                                                              double c0, double c1,
+                                                              double* __restrict__ part) {
+  __shared__ double lds[kGaugeBlock / 64];
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (idx < int64_t(2) * g.Vh) {
+    const int par = int(idx / g.Vh), h = int(idx % g.Vh);
+    const C4 x = site_c4(g, h, par);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      const C4 xp = shift(g, x, mu, 1);
+#pragma unroll 1
+      for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        const C4 xn = shift(g, x, nu, 1);
+        if (mu < nu) {  // U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+          M3 t = m_mul(link(g, U, x, mu), link(g, U, xp, nu));
+          t = m_mul_dag(t, link(g, U, xn, mu));
+          t = m_mul_dag(t, link(g, U, x, nu));
+          s += c0 * (1.0 - re_tr(t) / 3.0);
+        }
+        if (c1 != 0.0) {
+          // U_mu(x) U_mu(x+mu) U_nu(x+2mu) U_mu(x+mu+nu)^dag U_mu(x+nu)^dag U_nu(x)^dag
+          M3 t = m_mul(link(g, U, x, mu), link(g, U, xp, mu));
+          t = m_mul(t, link(g, U, shift(g, xp, mu, 1), nu));
+          t = m_mul_dag(t, link(g, U, shift(g, xp, nu, 1), mu));
+          t = m_mul_dag(t, link(g, U, xn, mu));
+          t = m_mul_dag(t, link(g, U, x, nu));
+          s += c1 * (1.0 - re_tr(t) / 3.0);
+        }
+      }
+    }
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kMdBlock) k_reduce_one(const double* __restrict__ part, int n,
+                                                          double scale, double* __restrict__ out) {
+  __shared__ double lds[kMdBlock / 64];
+  double s = strided_sum(part, n);
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) *out = scale * s;
+}
+
+// H <- H - i eps F, element-wise over the packed arrays
+__global__ void __launch_bounds__(kMdBlock) k_md_momenta(int64_t n, const double2* __restrict__ F,
+                                                         double eps, double2* __restrict__ H) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 f = F[i];
+  double2 h = H[i];
+  h.x = fma(eps, f.y, h.x);
+  h.y = fma(-eps, f.x, h.y);
+  H[i] = h;
+}
+
+// exp(X) for the anti-Hermitian X = i eps H: scaling and squaring, with a
+// Taylor polynomial of degree 12 on ||Y|| <= 1/4 (remainder < 3e-18).
+__device__ M3 expm_su3(const M3& X) {
+  double nrm2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) nrm2 += X.e[e].x * X.e[e].x + X.e[e].y * X.e[e].y;
+  double nrm = sqrt(nrm2);
+  int sq = 0;
+  while (nrm > 0.25 && sq < 40) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double sc = ldexp(1.0, -sq);
+  M3 Y;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) Y.e[e] = make_double2(sc * X.e[e].x, sc * X.e[e].y);
+  // Horner: E = I + Y/1 (I + Y/2 (I + ... (I + Y/12)))
+  M3 E = m_unit();
+#pragma unroll 1
+  for (int k = 12; k >= 1; --k) {
+    M3 t = m_mul(Y, E);
+    const double inv = 1.0 / k;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) t.e[e] = make_double2(inv * t.e[e].x, inv * t.e[e].y);
+    t.e[0].x += 1.0;
+    t.e[4].x += 1.0;
+    t.e[8].x += 1.0;
+    E = t;
+  }
+#pragma unroll 1
+  for (int k = 0; k < sq; ++k) E = m_mul(E, E);
+  return E;
+}
+
+// Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1): the nearest
+// special-unitary matrix up to rounding, applied after each link update so
+// that the links stay in SU(3) over many steps.
+__device__ M3 reunitarize(M3 u) {
+  double n0 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) n0 += u.e[j].x * u.e[j].x + u.e[j].y * u.e[j].y;
+  n0 = 1.0 / sqrt(n0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) u.e[j] = make_double2(n0 * u.e[j].x, n0 * u.e[j].y);
+  double2 d = make_double2(0.0, 0.0);  // <row0, row1> = sum_j conj(row0_j) row1_j
+#pragma unroll
+  for (int j = 0; j < 3; ++j) cfmac<double>(d, u.e[j], u.e[3 + j]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double2 p = cmul<double>(d, u.e[j]);
+    u.e[3 + j].x -= p.x;
+    u.e[3 + j].y -= p.y;
+  }
+  double n1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) n1 += u.e[3 + j].x * u.e[3 + j].x + u.e[3 + j].y * u.e[3 + j].y;
+  n1 = 1.0 / sqrt(n1);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) u.e[3 + j] = make_double2(n1 * u.e[3 + j].x, n1 * u.e[3 + j].y);
+  // row2 = conj(row0 x row1)
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int a = (j + 1) % 3, b = (j + 2) % 3;
+    const double2 p = cmul<double>(u.e[a], u.e[3 + b]);
+    const double2 q = cmul<double>(u.e[b], u.e[3 + a]);
+    u.e[6 + j] = make_double2(p.x - q.x, -(p.y - q.y));
+  }
+  return u;
+}
+
+// U <- exp(i eps H) U, one thread per link
+__global__ void __launch_bounds__(kGaugeBlock) k_md_links(KGeom g, const double2* __restrict__ H,
+                                                          double eps, double2* __restrict__ U) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(8) * g.Vh) return;
+  const int h = int(idx % g.Vh);
+  const int64_t base = (idx / g.Vh) * 9 * int64_t(g.Vh) + h;
+  M3 X, u;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    const double2 v = H[base + int64_t(e) * g.Vh];
+    X.e[e] = make_double2(-eps * v.y, eps * v.x);  // i eps H
+    u.e[e] = U[base + int64_t(e) * g.Vh];
+  }
+  const M3 r = reunitarize(m_mul(expm_su3(X), u));
+#pragma unroll
+  for (int e = 0; e < 9; ++e) U[base + int64_t(e) * g.Vh] = r.e[e];
+}
+
+// per link Tr H^2 = sum_ab Re(H_ab H_ba)
+__global__ void __launch_bounds__(kGaugeBlock) k_kinetic(KGeom g, const double2* __restrict__ H,
+                                                         double* __restrict__ part) {
+  __shared__ double lds[kGaugeBlock / 64];
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (idx < int64_t(8) * g.Vh) {
+    const int h = int(idx % g.Vh);
+    const int64_t base = (idx / g.Vh) * 9 * int64_t(g.Vh) + h;
+    M3 m;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m.e[e] = H[base + int64_t(e) * g.Vh];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double2 p = cmul<double>(m.e[3 * a + b], m.e[3 * b + a]);
+        s += p.x;
+      }
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+int check_c1(double beta, double c1) {
+  if (!std::isfinite(beta) || !std::isfinite(c1)) {
+    set_error("beta and c1 must be finite");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  return LQCD_OK;
+}
+
+int reduce_to_host(const double* part, int nb, double scale, double* out_dev, double* host,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_one, dim3(1), dim3(kMdBlock), 0, s, part, nb, scale, out_dev);
+  LQCD_LAUNCH_CHECK();
+  LQCD_HIP_TRY(hipMemcpyAsync(host, out_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  LQCD_HIP_TRY(hipStreamSynchronize(s));
+  return LQCD_OK;
+}
+
+}  // namespace
+
+}  // namespace lqcd
+
+using namespace lqcd;
+
+extern "C" {
+
+size_t lqcd_gauge_workspace_bytes(const lqcd_geom* g) {
+  if (check_geom(g)) return 0;
+  const KGeom k = make_kgeom(g);
+  return (size_t((int64_t(8) * k.Vh + kGaugeBlock - 1) / kGaugeBlock) + 32) * sizeof(double);
+}
+
+int lqcd_gauge_action(const lqcd_geom* g, const void* U64, double beta, double c1, double* S,
+                      void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(U64, "U64")) || (rc = check_ptr(ws, "ws")) ||
+      (rc = check_c1(beta, c1)))
+    return rc;
+  if (!S) {
+    set_error("S must be a host pointer");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (ws_bytes < lqcd_gauge_workspace_bytes(g)) {
+    set_error("gauge workspace of %zu bytes is too small: %zu needed", ws_bytes,
+              lqcd_gauge_workspace_bytes(g));
+    return LQCD_ERR_WORKSPACE;
+  }
+  const KGeom k = make_kgeom(g);
+  const int nb = int((int64_t(2) * k.Vh + kGaugeBlock - 1) / kGaugeBlock);
+  double* part = static_cast<double*>(ws);
+  const hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_gauge_action, dim3(nb), dim3(kGaugeBlock), 0, s, k, (const double2*)U64,
+                     1.0 - 8.0 * c1, c1, part);
+  LQCD_LAUNCH_CHECK();
+  return reduce_to_host(part, nb, beta, part + nb + 16, S, s);
+}
+
+int lqcd_gauge_force(const lqcd_geom* g, const void* U64, double beta, double c1,
+                     int32_t accumulate, void* F, void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(U64, "U64")) || (rc = check_ptr(F, "F")) ||
+      (rc = check_c1(beta, c1)))
+    return rc;
+  if (accumulate != 0 && accumulate != 1) {
+    set_error("accumulate must be 0 or 1");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (F == U64) {
+    set_error("F must not alias U64");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const int64_t n = int64_t(8) * k.Vh;
+  hipLaunchKernelGGL(k_gauge_force, dim3(unsigned((n + kGaugeBlock - 1) / kGaugeBlock)),
+                     dim3(kGaugeBlock), 0, (hipStream_t)stream, k, (const double2*)U64, beta,
+                     1.0 - 8.0 * c1, c1, accumulate, (double2*)F);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int lqcd_md_update_momenta(const lqcd_geom* g, const void* F, double eps, void* H,
+                           void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(F, "F")) || (rc = check_ptr(H, "H"))) return rc;
+  if (!std::isfinite(eps)) {
+    set_error("eps must be finite");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (F == H) {
+    set_error("F must not alias H");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const int64_t n = int64_t(8) * 9 * k.Vh;
+  hipLaunchKernelGGL(k_md_momenta, dim3(unsigned((n + kMdBlock - 1) / kMdBlock)), dim3(kMdBlock),
+                     0, (hipStream_t)stream, n, (const double2*)F, eps, (double2*)H);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int lqcd_md_update_links(const lqcd_geom* g, const void* H, double eps, void* U64,
+                         void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(H, "H")) || (rc = check_ptr(U64, "U64"))) return rc;
+  if (!std::isfinite(eps)) {
+    set_error("eps must be finite");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (H == U64) {
+    set_error("H must not alias U64");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const int64_t n = int64_t(8) * k.Vh;
+  hipLaunchKernelGGL(k_md_links, dim3(unsigned((n + kGaugeBlock - 1) / kGaugeBlock)),
+                     dim3(kGaugeBlock), 0, (hipStream_t)stream, k, (const double2*)H, eps,
+                     (double2*)U64);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int lqcd_kinetic_energy(const lqcd_geom* g, const void* H, double* K, void* ws, size_t ws_bytes,
+                        void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(H, "H")) || (rc = check_ptr(ws, "ws"))) return rc;
+  if (!K) {
+    set_error("K must be a host pointer");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (ws_bytes < lqcd_gauge_workspace_bytes(g)) {
+    set_error("gauge workspace of %zu bytes is too small: %zu needed", ws_bytes,
+              lqcd_gauge_workspace_bytes(g));
+    return LQCD_ERR_WORKSPACE;
+  }
+  const KGeom k = make_kgeom(g);
+  const int nb = int((int64_t(8) * k.Vh + kGaugeBlock - 1) / kGaugeBlock);
+  double* part = static_cast<double*>(ws);
+  const hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(kGaugeBlock), 0, s, k, (const double2*)H, part);
+  LQCD_LAUNCH_CHECK();
+  return reduce_to_host(part, nb, 0.5, part + nb + 16, K, s);
+}
+
+}  // extern "C"
