@@ -305,42 +305,50 @@ def rhmc_heatbath(lq, torch, g, U64, mass, nrhs, degree=14, seed=205):
 
 
 def rhmc_trajectory_bench(lq, torch, g48, U48):
-    """One RHMC trajectory (heatbath, tau = 1 with 10 Omelyan steps of gauge +
-    fermion force, accept/reject) on a 24^4 lattice (Haar-near links
-    exp(0.5 i H), beta = 5.0, m = 0.1, one pseudofermion, degree-12 rational
-    approximations, mixed-precision solves), and the tree-level Symanzik gauge
-    force kernel alone on the workload lattice: 85 SU(3) products (198 flops
-    each) per link, against the FP64 vector peak."""
+    """RHMC trajectories (heatbath, tau = 1 of Omelyan steps with gauge +
+    fermion force, accept/reject) on a 16^4 lattice (links exp(0.3 i H),
+    beta = 2.0, m = 0.1, one pseudofermion, degree-12 rational approximations,
+    mixed-precision solves) at 20 and 40 steps: the time of one trajectory and
+    dH(20) / dH(40), which is ~4 for the second-order scheme.  Then the
+    tree-level Symanzik gauge force kernel alone on the workload lattice: 85
+    SU(3) products (198 flops each) per link, against the FP64 vector peak."""
     import synth
-    L = (24, 24, 24, 24)
+    L = (16, 16, 16, 16)
     g = lq.Geometry(L)
-    beta, m = 5.0, 0.1
+    beta, m = 2.0, 0.1
     lo, hi = lq.spectral_bounds(m)
     e8 = lq.minimax(0.125, lo, hi, 12)
     q4 = lq.minimax(-0.25, lo, hi, 12)
     p = lq.solver_params(mass=m, tol=1e-10, inner_prec=lq.F32, inner_fmt=lq.LINKS12,
                          use_graph=1)
-    U = lq.pack_links(g, torch.from_numpy(synth.links_exp(L, 0.5, 601)).to("cuda"))
-    Hm = lq.pack_links(g, torch.from_numpy(synth.momenta(L, 602)).to("cuda"))
+    U0 = lq.pack_links(g, torch.from_numpy(synth.links_exp(L, 0.3, 601)).to("cuda"))
+    H0 = lq.pack_links(g, torch.from_numpy(synth.momenta(L, 602)).to("cuda"))
     xi = lq.pack_spinor(g, torch.from_numpy(synth.gaussian_even_source(L, 1, 603)).to("cuda"), 0)
-    lq.rhmc_trajectory(g, p, U.clone(), beta, e8, q4, xi, Hm.clone(), u=0.5, tau=0.1,
+    lq.rhmc_trajectory(g, p, U0.clone(), beta, e8, q4, xi, H0.clone(), u=0.5, tau=0.05,
                        nsteps=1)  # tuning and graph capture at this shape
-    torch.cuda.synchronize()
-    t0 = time.time()
-    r = lq.rhmc_trajectory(g, p, U, beta, e8, q4, xi, Hm, u=0.5, tau=1.0, nsteps=10)
-    torch.cuda.synchronize()
-    dt = time.time() - t0
+    res = {}
+    for n in (20, 40):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = lq.rhmc_trajectory(g, p, U0.clone(), beta, e8, q4, xi, H0.clone(), u=0.5, tau=1.0,
+                               nsteps=n)
+        torch.cuda.synchronize()
+        res[n] = (time.time() - t0, r)
     F = lq.empty_links(g48, lq.F64, lq.LINKS18, "cuda")
     ms = event_time_ms(lambda: lq.gauge_force(g48, U48, 5.0, out=F), 10)
     flops = 8 * g48.Vh * 85 * 198
     del F
-    out = dict(lattice=list(L), tau=1.0, nsteps=10, integrator="omelyan",
-               seconds=dt, dH=r["dH"], accepted=r["accepted"],
-               force_evaluations=r["force_evaluations"],
+    out = dict(lattice=list(L), beta=beta, mass=m, tau=1.0, integrator="omelyan",
+               seconds_20_steps=res[20][0], seconds_40_steps=res[40][0],
+               dH_20=res[20][1]["dH"], dH_40=res[40][1]["dH"],
+               dH_ratio=res[20][1]["dH"] / res[40][1]["dH"],
+               accepted_20=res[20][1]["accepted"],
+               force_evaluations_20=res[20][1]["force_evaluations"],
                gauge_force_48x4_ms=ms, gauge_force_TFLOPs=flops / (ms * 1e-3) / 1e12,
                gauge_force_frac_fp64_peak=flops / (ms * 1e-3) / 1e12 / 78.6)
-    log(f"RHMC trajectory 24^4 (10 Omelyan steps): {dt:.2f} s, dH = {r['dH']:.3e}, "
-        f"gauge force 48^4 {ms:.2f} ms ({out['gauge_force_TFLOPs']:.1f} TFLOP/s)")
+    log(f"RHMC trajectory 16^4: {res[20][0]:.2f} s (20 Omelyan steps), dH {out['dH_20']:.3e} / "
+        f"{out['dH_40']:.3e} at 20 / 40 steps; gauge force 48^4 {ms:.2f} ms "
+        f"({out['gauge_force_TFLOPs']:.1f} TFLOP/s)")
     return out
 
 
