@@ -318,6 +318,23 @@ int lqcd_rational_combine(const lqcd_geom *g, int32_t nrhs, int32_t nshift, doub
                           void *stream);
 
 /*
+ * U(1) phases on the links (Sec. 4.1): every flavour couples to a U(1) field
+ * u_mu(x) = exp(i theta_mu(x)) -- imaginary chemical potential, background
+ * (electro)magnetic fields -- and the Dirac operator then hops with
+ * u_mu(x) U_mu(x) instead of U_mu(x).  This writes those phased links:
+ *   U64    packed FP64 18-real links (in)
+ *   theta  device FP64 [4][V], natural lexicographic order
+ *   out    packed FP64 18-real (may be U64).
+ * Every entry point then takes `out` as its FP64 links: D_oe/D_eo, the
+ * solvers and the fermion force (whose TA(U M) is unchanged by the factor).
+ * Phased links are not in SU(3) (det = exp(3 i theta)), so the 12-real
+ * formats -- which rebuild row 2 from det = 1 -- must not be used with them:
+ * convert to LQCD_LINKS18 for any inner solver precision.  Stream-ordered.
+ */
+int lqcd_apply_u1_phases(const lqcd_geom *g, const void *U64, const double *theta, void *out,
+                         void *stream);
+
+/*
  * Gauge part of the molecular dynamics (Sec. 2, Sec. 5).  Links U64 and
  * momenta H use the packed FP64 18-real link layout [2][4][9][Vh] (complex);
  * gauge links carry no boundary sign or staggered phase.

@@ -198,6 +198,15 @@ def gauge_force(L, U, beta: float, c1: float = -1.0 / 12.0) -> np.ndarray:
     return F
 
 
+def phase_links(U, theta) -> np.ndarray:
+    """u_mu(x) U_mu(x) with u = exp(i theta_mu(x)) (Sec. 4.1: the U(1) field of
+    each flavour -- imaginary chemical potential, background fields -- enters
+    the Dirac operator as a factor on the links).  U natural [4][V][3][3],
+    theta [4][V]; every oracle function then takes the phased links as U."""
+    U = np.asarray(U, dtype=np.complex128)
+    return U * np.exp(1j * np.asarray(theta, dtype=np.float64))[..., None, None]
+
+
 def md_momenta(H, F, eps: float) -> np.ndarray:
     """Momentum step of the MD (Sec. 5, "new momenta"): with U' = i H U and the
     force F = TA(U M) of ``force`` / ``gauge_force`` (dS/deps = sum Tr[T F]

@@ -119,6 +119,7 @@ _SIGS = {
     "lqcd_action": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp,
                                    ctypes.c_size_t, _vp]),
     "lqcd_rational_combine": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _vp, _vp]),
+    "lqcd_apply_u1_phases": (ctypes.c_int, [_gp, _vp, _vp, _vp, _vp]),
     "lqcd_gauge_workspace_bytes": (ctypes.c_size_t, [_gp]),
     "lqcd_gauge_action": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _dp, _vp, ctypes.c_size_t, _vp]),
     "lqcd_gauge_force": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
@@ -454,6 +455,18 @@ def metropolis_accept(h_old: float, h_new: float, u: float) -> bool:
     if not math.isfinite(dh):
         return False
     return dh <= 0.0 or u < math.exp(-dh)
+
+
+def apply_u1_phases(geom: Geometry, U64, theta, out=None):
+    """Links u_mu(x) U_mu(x), u = exp(i theta_mu(x)), theta real [4][V] (natural
+    order, FP64, on the device); packed FP64 18-real in and out.  Use 18-real
+    formats for every precision with phased links (they are not SU(3))."""
+    if theta.dtype != torch.float64 or tuple(theta.shape) != (4, geom.V):
+        raise ValueError("theta must be float64 [4][V]")
+    theta = theta.contiguous()
+    out = torch.empty_like(U64) if out is None else out
+    _check(_fn("lqcd_apply_u1_phases")(geom.c(), _ptr(U64), _ptr(theta), _ptr(out), _stream()))
+    return out
 
 
 SYMANZIK_C1 = -1.0 / 12.0

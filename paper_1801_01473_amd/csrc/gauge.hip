@@ -435,6 +435,26 @@ __global__ void __launch_bounds__(kGaugeBlock) k_kinetic(KGeom g, const double2*
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// U_out = exp(i theta) U_in per link, theta natural [4][V] (lex = 2 h + bit)
+__global__ void __launch_bounds__(kMdBlock) k_u1_phases(KGeom g, const double2* __restrict__ U,
+                                                        const double* __restrict__ theta,
+                                                        double2* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(8) * g.Vh) return;
+  const int h = int(idx % g.Vh);
+  const int pm = int(idx / g.Vh);
+  const int par = pm >> 2, mu = pm & 3;
+  const Site s = decode_site(g, h, par);
+  const int64_t lex = int64_t(s.x) + int64_t(g.Lx) * (s.y + int64_t(g.Ly) * (s.z + int64_t(g.Lz) * s.t));
+  const int64_t V = int64_t(2) * g.Vh;
+  double sn, cs;
+  sincos(theta[mu * V + lex], &sn, &cs);
+  const double2 u = make_double2(cs, sn);
+  const int64_t base = int64_t(pm) * 9 * g.Vh + h;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) out[base + int64_t(e) * g.Vh] = cmul<double>(u, U[base + int64_t(e) * g.Vh]);
+}
+
 int check_c1(double beta, double c1) {
   if (!std::isfinite(beta) || !std::isfinite(c1)) {
     set_error("beta and c1 must be finite");
@@ -459,6 +479,24 @@ int reduce_to_host(const double* part, int nb, double scale, double* out_dev, do
 using namespace lqcd;
 
 extern "C" {
+
+int lqcd_apply_u1_phases(const lqcd_geom* g, const void* U64, const double* theta, void* out,
+                         void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(U64, "U64")) || (rc = check_ptr(out, "out")))
+    return rc;
+  if (!theta || (reinterpret_cast<uintptr_t>(theta) & 7)) {
+    set_error("theta must be an 8-byte aligned device array of 4 V doubles");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const int64_t n = int64_t(8) * k.Vh;
+  hipLaunchKernelGGL(k_u1_phases, dim3(unsigned((n + kMdBlock - 1) / kMdBlock)), dim3(kMdBlock),
+                     0, (hipStream_t)stream, k, (const double2*)U64, theta, (double2*)out);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
 
 size_t lqcd_gauge_workspace_bytes(const lqcd_geom* g) {
   if (check_geom(g)) return 0;

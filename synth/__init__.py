@@ -213,6 +213,40 @@ def momenta(L, seed: int) -> np.ndarray:
     return np.einsum("...a,aij->...ij", c, _gell_mann() / np.sqrt(2.0))
 
 
+def u1_phases_chemical(L, mu_i: float) -> np.ndarray:
+    """theta_mu(x) ``[4][V]`` of a constant imaginary chemical potential: mu_i
+    on every time link, zero elsewhere (u_t(x) = exp(i mu_i))."""
+    th = np.zeros((4, volume(L)))
+    th[3] = float(mu_i)
+    return th
+
+
+def u1_phases_magnetic(L, b: int) -> np.ndarray:
+    """theta_mu(x) ``[4][V]`` of a uniform field along z with b flux quanta
+    through the x-y plane (Landau gauge, periodic): theta_y = 2 pi b x /
+    (Lx Ly) on y links; theta_x = -2 pi b y / Ly on the x links leaving
+    x = Lx - 1.  Every x-y plaquette carries the phase 2 pi b / (Lx Ly)."""
+    c = site_coords(L)
+    th = np.zeros((4, volume(L)))
+    th[1] = 2 * np.pi * b * c[:, 0] / (L[0] * L[1])
+    th[0] = np.where(c[:, 0] == L[0] - 1, -2 * np.pi * b * c[:, 1] / L[1], 0.0)
+    return th
+
+
+def u1_phases_pure_gauge(L, seed: int):
+    """(theta, alpha): theta_mu(x) = alpha(x + mu) - alpha(x) for a random
+    alpha(x) in [0, 2 pi) -- a U(1) gauge transformation in phase form."""
+    alpha = rng(seed).uniform(0, 2 * np.pi, volume(L))
+    c = site_coords(L)
+    th = np.zeros((4, volume(L)))
+    for mu in range(4):
+        cf = c.copy()
+        cf[:, mu] = (cf[:, mu] + 1) % L[mu]
+        lex = cf[:, 0] + L[0] * (cf[:, 1] + L[1] * (cf[:, 2] + L[2] * cf[:, 3]))
+        th[mu] = alpha[lex] - alpha
+    return th, alpha
+
+
 def random_gauge_transform(L, seed: int) -> np.ndarray:
     """A Haar SU(3) matrix per site, ``[V][3][3]``."""
     return haar_su3(rng(seed), volume(L))

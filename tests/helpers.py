@@ -40,8 +40,10 @@ def dense_even_operator(L, apply):
     return A
 
 
-def free_spectrum(L, mass, antiperiodic=True):
-    """Closed-form eigenvalues of m^2 - D_eo D_oe for unit links (with multiplicity).
+def free_spectrum(L, mass, antiperiodic=True, theta_t=0.0):
+    """Closed-form eigenvalues of m^2 - D_eo D_oe for unit links (with multiplicity);
+    theta_t: a constant U(1) phase on the time links (imaginary chemical
+    potential), which shifts every time momentum by theta_t.
 
     Over the Brillouin zone the values m^2 + sum_mu sin^2 p_mu come in pairs
     (p, p + pi(1,1,1,1)) that share one even-site eigenvector, so each momentum
@@ -50,7 +52,9 @@ def free_spectrum(L, mass, antiperiodic=True):
     moms = []
     for mu, n in enumerate(L):
         if mu == 3 and antiperiodic:
-            moms.append([(2 * k + 1) * np.pi / n for k in range(n)])
+            moms.append([(2 * k + 1) * np.pi / n + theta_t for k in range(n)])
+        elif mu == 3:
+            moms.append([2 * k * np.pi / n + theta_t for k in range(n)])
         else:
             moms.append([2 * k * np.pi / n for k in range(n)])
     vals = [mass ** 2 + sum(np.sin(p) ** 2 for p in ps) for ps in itertools.product(*moms)]

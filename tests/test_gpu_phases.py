@@ -1,0 +1,95 @@
+"""GPU parity with U(1) phases on the links (Sec. 4.1): the phase kernel, the
+Dirac operator, the multi-shift solver (FP64 and mixed precision with 18-real
+inner links) and the fermion force on phased links, against the oracle on the
+same phased links."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lq():
+    import paper_1801_01473_amd as lq
+    return lq
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _theta(L, kind):
+    if kind == "chemical":
+        return synth.u1_phases_chemical(L, 0.37)
+    if kind == "magnetic":
+        return synth.u1_phases_magnetic(L, 2) + synth.u1_phases_chemical(L, -0.2)
+    return synth.u1_phases_pure_gauge(L, 801)[0]
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 2, 8), (8, 8, 8, 8)])
+@pytest.mark.parametrize("kind", ["chemical", "magnetic", "gauge"])
+def test_phased_links_and_dslash(lq, L, kind):
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 802)
+    th = _theta(L, kind)
+    Up_ref = oracle.phase_links(U, th)
+    U64 = lq.pack_links(g, cu(U))
+    Up = lq.apply_u1_phases(g, U64, cu(th))
+    assert H.max_rel(host(lq.unpack_links(g, Up)), Up_ref) <= 1e-15
+    # in place gives the same
+    U64b = U64.clone()
+    lq.apply_u1_phases(g, U64b, cu(th), out=U64b)
+    assert torch.equal(U64b, Up)
+    f = synth.gaussian_even_source(L, 2, 803)
+    ref = np.stack([oracle.doe(L, Up_ref, f[j]) for j in range(2)])
+    got = host(lq.unpack_spinor(g, lq.doe(g, Up, lq.pack_spinor(g, cu(f), 0)), 1))
+    assert H.max_rel(got, ref) <= 1e-13
+    U32 = lq.convert_links(g, Up, lq.F64, lq.LINKS18, lq.F32, lq.LINKS18)
+    got32 = host(lq.unpack_spinor(g, lq.doe(g, U32, lq.pack_spinor(g, cu(f), 0, lq.F32)), 1))
+    assert H.max_rel(got32, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("inner", [(0, 0), (1, 0)])
+def test_multishift_with_chemical_potential(lq, inner):
+    """Every (rhs, shift) meets 1e-10 on the FP64 phased operator (true
+    residual recomputed by the oracle); mixed precision with 18-real inner
+    links (phased links are not SU(3))."""
+    L = (8, 8, 8, 8)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 804)
+    th = synth.u1_phases_chemical(L, 0.5) + synth.u1_phases_magnetic(L, 1)
+    Up_ref = oracle.phase_links(U, th)
+    Up = lq.apply_u1_phases(g, lq.pack_links(g, cu(U)), cu(th))
+    b = synth.gaussian_even_source(L, 2, 805)
+    sig = synth.rational_shifts(6, 1e-3, 1.0)
+    m = 0.05
+    p = lq.solver_params(mass=m, tol=1e-10, inner_prec=inner[0], inner_fmt=inner[1])
+    X, _, stats = lq.cg_multishift(g, p, Up, sig, lq.pack_spinor(g, cu(b), 0))
+    Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(2, len(sig), -1, 3)
+    for j in range(2):
+        for i, s in enumerate(sig):
+            assert oracle.true_residual(L, Up_ref, m, s, b[j], Xn[j, i]) <= 1e-10
+    assert all(s["converged"] == 1 for row in stats for s in row)
+
+
+def test_fermion_force_on_phased_links(lq):
+    L = (4, 4, 4, 4)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 806)
+    th = synth.u1_phases_magnetic(L, 1) + synth.u1_phases_chemical(L, 0.8)
+    Up_ref = oracle.phase_links(U, th)
+    Up = lq.apply_u1_phases(g, lq.pack_links(g, cu(U)), cu(th))
+    X = synth.gaussian_even_source(L, 2 * 3, 807).reshape(2, 3, -1, 3)
+    al = np.array([0.4, 1.2, 2.0])
+    F = lq.fermion_force(g, Up, al, lq.pack_spinor(g, cu(X.reshape(-1, g.V, 3)), 0))
+    assert H.max_rel(host(lq.unpack_links(g, F)), oracle.force(L, Up_ref, al, X)) <= 1e-12
