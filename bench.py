@@ -337,7 +337,13 @@ def rhmc_trajectory_bench(lq, torch, g48, U48):
     F = lq.empty_links(g48, lq.F64, lq.LINKS18, "cuda")
     ms = event_time_ms(lambda: lq.gauge_force(g48, U48, 5.0, out=F), 10)
     flops = 8 * g48.Vh * 85 * 198
-    del F
+    # stout smearing (one level) and its chain-rule step on the workload lattice
+    chain = lq.stout_smear(g48, U48, 0.15)
+    Us = torch.empty_like(U48)
+    ms_smear = event_time_ms(lambda: lq._check(lq._fn("lqcd_stout_smear")(
+        g48.c(), lq._ptr(U48), 0.15, lq._ptr(Us), lq._stream())), 10)
+    ms_chain = event_time_ms(lambda: lq.stout_force(g48, chain, 0.15, F, mode=1), 5)
+    del F, Us, chain
     out = dict(lattice=list(L), beta=beta, mass=m, tau=1.0, integrator="omelyan",
                seconds_20_steps=res[20][0], seconds_40_steps=res[40][0],
                dH_20=res[20][1]["dH"], dH_40=res[40][1]["dH"],
@@ -345,7 +351,8 @@ def rhmc_trajectory_bench(lq, torch, g48, U48):
                accepted_20=res[20][1]["accepted"],
                force_evaluations_20=res[20][1]["force_evaluations"],
                gauge_force_48x4_ms=ms, gauge_force_TFLOPs=flops / (ms * 1e-3) / 1e12,
-               gauge_force_frac_fp64_peak=flops / (ms * 1e-3) / 1e12 / 78.6)
+               gauge_force_frac_fp64_peak=flops / (ms * 1e-3) / 1e12 / 78.6,
+               stout_smear_48x4_ms=ms_smear, stout_chain_rule_48x4_ms=ms_chain)
     log(f"RHMC trajectory 16^4: {res[20][0]:.2f} s (20 Omelyan steps), dH {out['dH_20']:.3e} / "
         f"{out['dH_40']:.3e} at 20 / 40 steps; gauge force 48^4 {ms:.2f} ms "
         f"({out['gauge_force_TFLOPs']:.1f} TFLOP/s)")

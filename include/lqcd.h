@@ -335,6 +335,31 @@ int lqcd_apply_u1_phases(const lqcd_geom *g, const void *U64, const double *thet
                          void *stream);
 
 /*
+ * Stout smearing (Sec. 2: the Dirac operator hops with the k-times stout
+ * smeared links U^(k), the MD evolves the unsmeared U^(0)).  One level:
+ *   U' = exp(X) U,  X = TA(Omega),  Omega = rho C U^dag,
+ * C = sum over nu != mu of the plaquette staples of the link (isotropic
+ * rho).  Packed FP64 18-real in and out; out must not alias U64.
+ */
+int lqcd_stout_smear(const lqcd_geom *g, const void *U64, double rho, void *out, void *stream);
+
+/*
+ * Chain rule of the force through one smearing level.  G_smeared is the raw
+ * gradient with respect to the smeared links, G' = M'^dag with dS = sum Re
+ * Tr[dU' M'] (lqcd_fermion_force mode 1, or this function's mode 1 one level
+ * up); U64 are the links before this level.  With E = exp(X) and
+ * Lam = TA(L(X, U M')), L(X, B) = sum_k 1/k! sum_j X^j B X^(k-1-j) (the
+ * Frechet derivative of exp, computed by scaling and squaring):
+ *   M = M' E + rho A Lam^dag + (the staple terms of Re Tr[dA K], K = rho Lam^dag U),
+ * A the staple sum; out = TA(U M) (mode 0, the force on U) or M^dag (mode 1,
+ * for the next level down).  ws holds lqcd_stout_workspace_bytes(g) (two link
+ * fields); out must not alias U64 or G_smeared.  Stream-ordered.
+ */
+size_t lqcd_stout_workspace_bytes(const lqcd_geom *g);
+int lqcd_stout_force(const lqcd_geom *g, const void *U64, double rho, const void *G_smeared,
+                     int32_t mode, void *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Gauge part of the molecular dynamics (Sec. 2, Sec. 5).  Links U64 and
  * momenta H use the packed FP64 18-real link layout [2][4][9][Vh] (complex);
  * gauge links carry no boundary sign or staggered phase.

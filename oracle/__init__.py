@@ -207,6 +207,113 @@ def phase_links(U, theta) -> np.ndarray:
     return U * np.exp(1j * np.asarray(theta, dtype=np.float64))[..., None, None]
 
 
+def _shift_index(L, mu, d):
+    """lex index of x + d mu^ for every x (periodic)."""
+    V = _V(L)
+    lex = np.arange(V)
+    c = [lex % L[0], (lex // L[0]) % L[1], (lex // (L[0] * L[1])) % L[2],
+         lex // (L[0] * L[1] * L[2])]
+    c[mu] = (c[mu] + d) % L[mu]
+    return c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))
+
+
+def _dag(A):
+    return np.conj(np.swapaxes(A, -1, -2))
+
+
+def _ta(W):
+    Y = 0.5 * (W - _dag(W))
+    tr = np.trace(Y, axis1=-2, axis2=-1)[..., None, None]
+    return Y - tr / 3.0 * np.eye(3)
+
+
+def _expm_ah(X):
+    """exp(X) for anti-Hermitian X (stack): eigendecomposition of -iX."""
+    w, v = np.linalg.eigh(-1j * X)
+    return np.einsum("...ij,...j,...kj->...ik", v, np.exp(1j * w), v.conj())
+
+
+def _stout_parts(L, U, rho, mu):
+    """Staple sum A_mu (plaquettes: Tr[U_mu A_mu] is the plaquette), X = TA(rho A^dag U^dag)."""
+    A = np.zeros_like(U[mu])
+    xp = _shift_index(L, mu, 1)
+    for nu in range(4):
+        if nu == mu:
+            continue
+        xn, xm = _shift_index(L, nu, 1), _shift_index(L, nu, -1)
+        xpm = xp[xm]
+        A += U[nu][xp] @ _dag(U[mu][xn]) @ _dag(U[nu])
+        A += _dag(U[nu][xpm]) @ _dag(U[mu][xm]) @ U[nu][xm]
+    X = _ta(rho * _dag(A) @ _dag(U[mu]))
+    return A, X
+
+
+def stout_smear(L, U, rho: float) -> np.ndarray:
+    """One level of stout smearing (the smeared links U^(k) of the Dirac
+    operator, Sec. 2): U' = exp(X) U, X = TA(Omega), Omega = rho C U^dag with
+    C = sum over nu != mu of the plaquette staples of the link (isotropic rho).
+    Natural [4][V][3][3]."""
+    U = np.asarray(U, dtype=np.complex128)
+    out = np.empty_like(U)
+    for mu in range(4):
+        _, X = _stout_parts(L, U, rho, mu)
+        out[mu] = _expm_ah(X) @ U[mu]
+    return out
+
+
+def stout_force(L, U, rho: float, G_smeared, mode: int = 0) -> np.ndarray:
+    """Chain rule through one smearing level: given the raw gradient with
+    respect to the smeared links, G' = M'^dag (dS = sum Re Tr[dU' M']), return
+    F = TA(U M) (mode 0) or M^dag (mode 1) with dS = sum Re Tr[dU M], the
+    exact derivative written out: U' = E U, E = exp(X):
+      Re Tr[M' E dU]                      -> M += M' E
+      Re Tr[U M' dE] = Re Tr[L(X, U M') dX], L(X, B) the top-right block of
+        exp([[X, B], [0, X]]); with dX = TA(dOmega) this is Re Tr[Lam dOmega],
+        Lam = TA(L(X, U M')), and dOmega = rho (dA^dag U^dag + A^dag dU^dag):
+        -> M += rho A Lam^dag, and Re Tr[dA K], K = rho Lam^dag U, spread over
+        every link of every staple in A (each link of the product in turn)."""
+    from scipy.linalg import expm
+    U = np.asarray(U, dtype=np.complex128)
+    Mp = _dag(np.asarray(G_smeared, dtype=np.complex128))
+    M = np.zeros_like(U)
+    V = _V(L)
+    for mu in range(4):
+        A, X = _stout_parts(L, U, rho, mu)
+        E = _expm_ah(X)
+        B = U[mu] @ Mp[mu]
+        G = np.empty_like(B)
+        Z = np.zeros((6, 6), np.complex128)
+        for x in range(V):
+            Z[:3, :3] = X[x]
+            Z[3:, 3:] = X[x]
+            Z[:3, 3:] = B[x]
+            G[x] = expm(Z)[:3, 3:]
+        Lam = _ta(G)
+        M[mu] += Mp[mu] @ E + rho * A @ _dag(Lam)
+        K = rho * _dag(Lam) @ U[mu]
+        xp = _shift_index(L, mu, 1)
+        for nu in range(4):
+            if nu == mu:
+                continue
+            xn, xm = _shift_index(L, nu, 1), _shift_index(L, nu, -1)
+            xpm = xp[xm]
+            x = np.arange(V)
+            for path in ([(nu, xp, False), (mu, xn, True), (nu, x, True)],
+                         [(nu, xpm, True), (mu, xm, True), (nu, xm, False)]):
+                mats = [_dag(U[d][i]) if dg else U[d][i] for d, i, dg in path]
+                for k in range(3):
+                    # R = P_{k+1} ... P_3 K P_1 ... P_{k-1}
+                    R = np.broadcast_to(np.eye(3), K.shape).copy()
+                    for q in range(k + 1, 3):
+                        R = R @ mats[q]
+                    R = R @ K
+                    for q in range(0, k):
+                        R = R @ mats[q]
+                    d, i, dg = path[k]
+                    np.add.at(M[d], i, _dag(R) if dg else R)
+    return _ta(U @ M) if mode == 0 else _dag(M)
+
+
 def md_momenta(H, F, eps: float) -> np.ndarray:
     """Momentum step of the MD (Sec. 5, "new momenta"): with U' = i H U and the
     force F = TA(U M) of ``force`` / ``gauge_force`` (dS/deps = sum Tr[T F]

@@ -120,6 +120,10 @@ _SIGS = {
                                    ctypes.c_size_t, _vp]),
     "lqcd_rational_combine": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _vp, _vp]),
     "lqcd_apply_u1_phases": (ctypes.c_int, [_gp, _vp, _vp, _vp, _vp]),
+    "lqcd_stout_smear": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _vp]),
+    "lqcd_stout_workspace_bytes": (ctypes.c_size_t, [_gp]),
+    "lqcd_stout_force": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _i32, _vp, _vp, ctypes.c_size_t,
+                                        _vp]),
     "lqcd_gauge_workspace_bytes": (ctypes.c_size_t, [_gp]),
     "lqcd_gauge_action": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _dp, _vp, ctypes.c_size_t, _vp]),
     "lqcd_gauge_force": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
@@ -467,6 +471,34 @@ def apply_u1_phases(geom: Geometry, U64, theta, out=None):
     out = torch.empty_like(U64) if out is None else out
     _check(_fn("lqcd_apply_u1_phases")(geom.c(), _ptr(U64), _ptr(theta), _ptr(out), _stream()))
     return out
+
+
+def stout_smear(geom: Geometry, U64, rho: float, levels: int = 1):
+    """[U^(0), U^(1), ..., U^(levels)]: repeated stout smearing (packed FP64
+    18-real); U^(0) is U64 itself."""
+    out = [U64]
+    for _ in range(levels):
+        nxt = torch.empty_like(U64)
+        _check(_fn("lqcd_stout_smear")(geom.c(), _ptr(out[-1]), float(rho), _ptr(nxt), _stream()))
+        out.append(nxt)
+    return out
+
+
+def stout_force(geom: Geometry, chain, rho: float, G_top, mode: int = 0):
+    """Carry a raw gradient G_top (M^dag with respect to the most smeared
+    links chain[-1], e.g. fermion_force(..., mode=1)) down the smearing chain
+    [U^(0), ..., U^(k)] of stout_smear; returns TA(U^(0) M) (mode 0) or the raw
+    gradient M^dag with respect to U^(0) (mode 1)."""
+    nbytes = int(_fn("lqcd_stout_workspace_bytes")(geom.c()))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=G_top.device)
+    G = G_top
+    for j in range(len(chain) - 2, -1, -1):
+        out = torch.empty_like(G_top)
+        _check(_fn("lqcd_stout_force")(geom.c(), _ptr(chain[j]), float(rho), _ptr(G),
+                                       mode if j == 0 else 1, _ptr(out), _ptr(ws), ws.numel(),
+                                       _stream()))
+        G = out
+    return G
 
 
 SYMANZIK_C1 = -1.0 / 12.0

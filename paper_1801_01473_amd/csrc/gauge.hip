@@ -455,6 +455,162 @@ __global__ void __launch_bounds__(kMdBlock) k_u1_phases(KGeom g, const double2* 
   for (int e = 0; e < 9; ++e) out[base + int64_t(e) * g.Vh] = cmul<double>(u, U[base + int64_t(e) * g.Vh]);
 }
 
+// ---- stout smearing (Sec. 2: the Dirac operator uses k-times stout-smeared
+// links) and the chain rule of the force through one smearing level.
+// U' = exp(X) U, X = TA(Omega), Omega = rho A^dag U^dag = rho (U A)^dag, A the
+// plaquette staple sum of the link (so X = -rho TA(U A)).
+
+__device__ __forceinline__ M3 m_dag(const M3& a) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.e[3 * i + j] = make_double2(a.e[3 * j + i].x, -a.e[3 * j + i].y);
+  return r;
+}
+
+__device__ __forceinline__ M3 m_scale(double s, M3 a) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) a.e[e] = make_double2(s * a.e[e].x, s * a.e[e].y);
+  return a;
+}
+
+__device__ __forceinline__ M3 m_add(M3 a, const M3& b) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) a.e[e] = make_double2(a.e[e].x + b.e[e].x, a.e[e].y + b.e[e].y);
+  return a;
+}
+
+__device__ __forceinline__ void stout_x(const KGeom& g, const double2* __restrict__ U, const C4& x,
+                                        int mu, double rho, M3& A, M3& u, M3& X) {
+  A = staples(g, U, x, mu, 1.0, 0.0);
+  u = link(g, U, x, mu);
+  X = m_scale(-rho, traceless_antiherm(m_mul(u, A)));
+}
+
+__global__ void __launch_bounds__(kGaugeBlock) k_stout_smear(KGeom g, const double2* __restrict__ U,
+                                                             double rho, double2* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(8) * g.Vh) return;
+  const int h = int(idx % g.Vh);
+  const int pm = int(idx / g.Vh);
+  const C4 x = site_c4(g, h, pm >> 2);
+  M3 A, u, X;
+  stout_x(g, U, x, pm & 3, rho, A, u, X);
+  const M3 r = m_mul(expm_su3(X), u);
+  double2* o = out + int64_t(pm) * 9 * g.Vh + h;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) o[int64_t(e) * g.Vh] = r.e[e];
+}
+
+// (exp(X), L(X, B)) with L(X, B) = sum_k 1/k! sum_j X^j B X^(k-1-j), the
+// top-right block of exp([[X, B], [0, X]]): scaling and squaring of the block
+// matrix, (E, G) -> (E E, E G + G E), degree-12 Taylor on ||X|| <= 1/4.
+__device__ void expm_frechet(const M3& X, const M3& B, M3& E, M3& G) {
+  double nrm2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) nrm2 += X.e[e].x * X.e[e].x + X.e[e].y * X.e[e].y;
+  double nrm = sqrt(nrm2);
+  int sq = 0;
+  while (nrm > 0.25 && sq < 40) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double sc = ldexp(1.0, -sq);
+  const M3 Xs = m_scale(sc, X), Bs = m_scale(sc, B);
+  E = m_unit();
+  G = m_zero();
+  M3 P = m_unit();  // Xs^k
+  M3 D = Bs;        // D_k, k = 1
+  double f = 1.0;   // 1/k!
+#pragma unroll 1
+  for (int k = 1; k <= 12; ++k) {
+    f /= k;
+    P = m_mul(Xs, P);
+    E = m_add(E, m_scale(f, P));
+    G = m_add(G, m_scale(f, D));
+    D = m_add(m_mul(Xs, D), m_mul(Bs, P));  // D_{k+1} = X D_k + B X^k
+  }
+#pragma unroll 1
+  for (int k = 0; k < sq; ++k) {
+    const M3 G2 = m_add(m_mul(E, G), m_mul(G, E));
+    E = m_mul(E, E);
+    G = G2;
+  }
+}
+
+// Per link, from the raw gradient G' = M'^dag with respect to the smeared
+// link: K = rho Lam^dag U and the local part Mloc = M' E + rho A Lam^dag of
+// M, Lam = TA(L(X, U M')).
+__global__ void __launch_bounds__(kGaugeBlock) k_stout_lambda(KGeom g, const double2* __restrict__ U,
+                                                              double rho,
+                                                              const double2* __restrict__ Gp,
+                                                              double2* __restrict__ K,
+                                                              double2* __restrict__ Mloc) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(8) * g.Vh) return;
+  const int h = int(idx % g.Vh);
+  const int pm = int(idx / g.Vh);
+  const C4 x = site_c4(g, h, pm >> 2);
+  M3 A, u, X;
+  stout_x(g, U, x, pm & 3, rho, A, u, X);
+  const int64_t base = int64_t(pm) * 9 * g.Vh + h;
+  M3 gp;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) gp.e[e] = Gp[base + int64_t(e) * g.Vh];
+  const M3 Mp = m_dag(gp);
+  M3 E, Gm;
+  expm_frechet(X, m_mul(u, Mp), E, Gm);
+  const M3 lam_dag = m_dag(traceless_antiherm(Gm));
+  const M3 k = m_scale(rho, m_mul(lam_dag, u));
+  const M3 ml = m_add(m_mul(Mp, E), m_scale(rho, m_mul(A, lam_dag)));
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    K[base + int64_t(e) * g.Vh] = k.e[e];
+    Mloc[base + int64_t(e) * g.Vh] = ml.e[e];
+  }
+}
+
+// M of link (y, a) = Mloc + the terms of Re Tr[dA_mu(x) K_mu(x)] in which the
+// link appears, for every other direction m:
+//   U_m(y-m+a)^dag U_a(y-m)^dag K_m(y-m)        (first link of an upper staple)
+//   (K_m(y) U_a(y+m) U_m(y+a)^dag)^dag           (last link of an upper staple)
+//   (U_m(y-m)^dag U_a(y-m) K_m(y-m+a))^dag       (first link of a lower staple)
+//   K_m(y+a) U_a(y+m)^dag U_m(y)^dag             (last link of a lower staple)
+//   (U_m(y-m)^dag K_a(y-m) U_m(y-m+a))^dag       (middle of an upper staple)
+//   (U_m(y) K_a(y+m) U_m(y+a)^dag)^dag           (middle of a lower staple)
+// Output: mode 0 F = TA(U M), mode 1 the raw gradient M^dag.
+__global__ void __launch_bounds__(kGaugeBlock) k_stout_gather(KGeom g, const double2* __restrict__ U,
+                                                              const double2* __restrict__ K,
+                                                              const double2* __restrict__ Mloc,
+                                                              int mode, double2* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(8) * g.Vh) return;
+  const int h = int(idx % g.Vh);
+  const int pm = int(idx / g.Vh);
+  const int a = pm & 3;
+  const C4 y = site_c4(g, h, pm >> 2);
+  const int64_t base = int64_t(pm) * 9 * g.Vh + h;
+  M3 M;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) M.e[e] = Mloc[base + int64_t(e) * g.Vh];
+#pragma unroll 1
+  for (int m = 0; m < 4; ++m) {
+    if (m == a) continue;
+    const C4 ym = shift(g, y, m, -1), yp = shift(g, y, m, 1), ya = shift(g, y, a, 1);
+    const C4 yma = shift(g, ym, a, 1);
+    M = m_add(M, m_mul(m_dag_mul(link(g, U, yma, m), m_dag(link(g, U, ym, a))), link(g, K, ym, m)));
+    M = m_add(M, m_dag(m_mul_dag(m_mul(link(g, K, y, m), link(g, U, yp, a)), link(g, U, ya, m))));
+    M = m_add(M, m_dag(m_mul(m_dag_mul(link(g, U, ym, m), link(g, U, ym, a)), link(g, K, yma, m))));
+    M = m_add(M, m_mul_dag(m_mul_dag(link(g, K, ya, m), link(g, U, yp, a)), link(g, U, y, m)));
+    M = m_add(M, m_dag(m_mul(m_dag_mul(link(g, U, ym, m), link(g, K, ym, a)), link(g, U, yma, m))));
+    M = m_add(M, m_dag(m_mul_dag(m_mul(link(g, U, y, m), link(g, K, yp, a)), link(g, U, ya, m))));
+  }
+  const M3 r = mode == 0 ? traceless_antiherm(m_mul(link(g, U, y, a), M)) : m_dag(M);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) out[base + int64_t(e) * g.Vh] = r.e[e];
+}
+
 int check_c1(double beta, double c1) {
   if (!std::isfinite(beta) || !std::isfinite(c1)) {
     set_error("beta and c1 must be finite");
@@ -494,6 +650,74 @@ int lqcd_apply_u1_phases(const lqcd_geom* g, const void* U64, const double* thet
   const int64_t n = int64_t(8) * k.Vh;
   hipLaunchKernelGGL(k_u1_phases, dim3(unsigned((n + kMdBlock - 1) / kMdBlock)), dim3(kMdBlock),
                      0, (hipStream_t)stream, k, (const double2*)U64, theta, (double2*)out);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int lqcd_stout_smear(const lqcd_geom* g, const void* U64, double rho, void* out, void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(U64, "U64")) || (rc = check_ptr(out, "out")))
+    return rc;
+  if (!std::isfinite(rho)) {
+    set_error("rho must be finite");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (out == U64) {
+    set_error("out must not alias U64 (every link reads its neighbours)");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const int64_t n = int64_t(8) * k.Vh;
+  hipLaunchKernelGGL(k_stout_smear, dim3(unsigned((n + kGaugeBlock - 1) / kGaugeBlock)),
+                     dim3(kGaugeBlock), 0, (hipStream_t)stream, k, (const double2*)U64, rho,
+                     (double2*)out);
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+size_t lqcd_stout_workspace_bytes(const lqcd_geom* g) {
+  if (check_geom(g)) return 0;
+  const KGeom k = make_kgeom(g);
+  return size_t(2) * 8 * 9 * size_t(k.Vh) * sizeof(double2);
+}
+
+int lqcd_stout_force(const lqcd_geom* g, const void* U64, double rho, const void* G_smeared,
+                     int32_t mode, void* out, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_geom(g)) || (rc = check_ptr(U64, "U64")) ||
+      (rc = check_ptr(G_smeared, "G_smeared")) || (rc = check_ptr(out, "out")) ||
+      (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (!std::isfinite(rho)) {
+    set_error("rho must be finite");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (mode != 0 && mode != 1) {
+    set_error("mode must be 0 (projected) or 1 (raw), got %d", mode);
+    return LQCD_ERR_INVALID_ARG;
+  }
+  if (ws_bytes < lqcd_stout_workspace_bytes(g)) {
+    set_error("stout workspace of %zu bytes is too small: %zu needed", ws_bytes,
+              lqcd_stout_workspace_bytes(g));
+    return LQCD_ERR_WORKSPACE;
+  }
+  if (out == U64 || out == G_smeared) {
+    set_error("out must not alias U64 or G_smeared");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const int64_t n = int64_t(8) * k.Vh;
+  double2* K = static_cast<double2*>(ws);
+  double2* Mloc = K + n * 9;
+  const hipStream_t s = (hipStream_t)stream;
+  const dim3 grid(unsigned((n + kGaugeBlock - 1) / kGaugeBlock));
+  hipLaunchKernelGGL(k_stout_lambda, grid, dim3(kGaugeBlock), 0, s, k, (const double2*)U64, rho,
+                     (const double2*)G_smeared, K, Mloc);
+  LQCD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_stout_gather, grid, dim3(kGaugeBlock), 0, s, k, (const double2*)U64,
+                     (const double2*)K, (const double2*)Mloc, mode, (double2*)out);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
