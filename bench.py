@@ -339,11 +339,9 @@ def rhmc_trajectory_bench(lq, torch, g48, U48):
     flops = 8 * g48.Vh * 85 * 198
     # stout smearing (one level) and its chain-rule step on the workload lattice
     chain = lq.stout_smear(g48, U48, 0.15)
-    Us = torch.empty_like(U48)
-    ms_smear = event_time_ms(lambda: lq._check(lq._fn("lqcd_stout_smear")(
-        g48.c(), lq._ptr(U48), 0.15, lq._ptr(Us), lq._stream())), 10)
+    ms_smear = event_time_ms(lambda: lq.stout_smear(g48, U48, 0.15), 10)
     ms_chain = event_time_ms(lambda: lq.stout_force(g48, chain, 0.15, F, mode=1), 5)
-    del F, Us, chain
+    del F, chain
     out = dict(lattice=list(L), beta=beta, mass=m, tau=1.0, integrator="omelyan",
                seconds_20_steps=res[20][0], seconds_40_steps=res[40][0],
                dH_20=res[20][1]["dH"], dH_40=res[40][1]["dH"],

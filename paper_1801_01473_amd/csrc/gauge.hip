@@ -138,6 +138,13 @@ __device__ __forceinline__ C4 site_c4(const KGeom& g, int h, int par) {
 // Weighted staple sum of the link U_mu(x): Tr[U_mu(x) A] runs over every
 // plaquette (weight c0) and every 1x2 rectangle (weight c1) through the link,
 // each as the loop that starts along the link.
+// SEL picks the staple shapes (bits): 1 plaquettes, 2 / 4 2x1 with the link
+// first / second (upper), 8 / 16 the same lower, 32 / 64 1x2 upper / lower.
+// The force splits the shapes over three launches to bound the live matrices.
+constexpr int kStaplePlaq = 1;
+constexpr int kStaplePass1 = 1 | 2 | 4, kStaplePass2 = 8 | 16, kStaplePass3 = 32 | 64;
+
+template <int SEL>
 __device__ M3 staples(const KGeom& g, const double2* __restrict__ U, const C4& x, int mu,
                       double c0, double c1) {
   M3 A = m_zero();
@@ -148,19 +155,19 @@ __device__ M3 staples(const KGeom& g, const double2* __restrict__ U, const C4& x
     const C4 xpm = shift(g, xp, nu, -1);
     // plaquettes: up U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag,
     //             down U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
-    {
+    if (SEL & 1) {
       M3 t = m_mul_dag(link(g, U, xp, nu), link(g, U, xn, mu));
       t = m_mul_dag(t, link(g, U, x, nu));
       m_axpy(c0, t, A);
       t = m_dag_mul(link(g, U, xpm, nu), m_dag_mul(link(g, U, xm, mu), link(g, U, xm, nu)));
       m_axpy(c0, t, A);
     }
-    if (c1 == 0.0) continue;
+    if (c1 == 0.0 || (SEL & ~1) == 0) continue;
     const C4 xmu = shift(g, x, mu, -1);
     const C4 x2p = shift(g, xp, mu, 1);
     // 2 x 1, link first, up:
     //   U_mu(x+mu) U_nu(x+2mu) U_mu(x+mu+nu)^dag U_mu(x+nu)^dag U_nu(x)^dag
-    {
+    if (SEL & 2) {
       M3 t = m_mul(link(g, U, xp, mu), link(g, U, x2p, nu));
       t = m_mul_dag(t, link(g, U, shift(g, xp, nu, 1), mu));
       t = m_mul_dag(t, link(g, U, xn, mu));
@@ -169,7 +176,7 @@ __device__ M3 staples(const KGeom& g, const double2* __restrict__ U, const C4& x
     }
     // 2 x 1, link second, up:
     //   U_nu(x+mu) U_mu(x+nu)^dag U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu)
-    {
+    if (SEL & 4) {
       M3 t = m_mul_dag(link(g, U, xp, nu), link(g, U, xn, mu));
       t = m_mul_dag(t, link(g, U, shift(g, xmu, nu, 1), mu));
       t = m_mul_dag(t, link(g, U, xmu, nu));
@@ -178,7 +185,7 @@ __device__ M3 staples(const KGeom& g, const double2* __restrict__ U, const C4& x
     }
     // 2 x 1, link first, down:
     //   U_mu(x+mu) U_nu(x+2mu-nu)^dag U_mu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
-    {
+    if (SEL & 8) {
       M3 t = m_mul_dag(link(g, U, xp, mu), link(g, U, shift(g, x2p, nu, -1), nu));
       t = m_mul_dag(t, link(g, U, xpm, mu));
       t = m_mul_dag(t, link(g, U, xm, mu));
@@ -187,7 +194,7 @@ __device__ M3 staples(const KGeom& g, const double2* __restrict__ U, const C4& x
     }
     // 2 x 1, link second, down:
     //   U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_mu(x-mu-nu)^dag U_nu(x-mu-nu) U_mu(x-mu)
-    {
+    if (SEL & 16) {
       const C4 xmm = shift(g, xmu, nu, -1);
       M3 t = m_dag_mul(link(g, U, xpm, nu), m_dag_mul(link(g, U, xm, mu), m_unit()));
       t = m_mul_dag(t, link(g, U, xmm, mu));
@@ -196,7 +203,7 @@ __device__ M3 staples(const KGeom& g, const double2* __restrict__ U, const C4& x
       m_axpy(c1, t, A);
     }
     // 1 x 2, up: U_nu(x+mu) U_nu(x+mu+nu) U_mu(x+2nu)^dag U_nu(x+nu)^dag U_nu(x)^dag
-    {
+    if (SEL & 32) {
       M3 t = m_mul(link(g, U, xp, nu), link(g, U, shift(g, xp, nu, 1), nu));
       t = m_mul_dag(t, link(g, U, shift(g, xn, nu, 1), mu));
       t = m_mul_dag(t, link(g, U, xn, nu));
@@ -205,7 +212,7 @@ __device__ M3 staples(const KGeom& g, const double2* __restrict__ U, const C4& x
     }
     // 1 x 2, down:
     //   U_nu(x+mu-nu)^dag U_nu(x+mu-2nu)^dag U_mu(x-2nu)^dag U_nu(x-2nu) U_nu(x-nu)
-    {
+    if (SEL & 64) {
       const C4 xm2 = shift(g, xm, nu, -1);
       M3 t = m_dag_mul(link(g, U, xpm, nu), m_dag_mul(link(g, U, shift(g, xpm, nu, -1), nu),
                                                       m_unit()));
@@ -234,6 +241,7 @@ __device__ __forceinline__ M3 traceless_antiherm(const M3& w) {
 
 // One thread per link: idx = (parity * 4 + mu) * Vh + h, so each (parity,
 // mu, element) plane is written coalesced.
+template <int SEL>
 __global__ void __launch_bounds__(kGaugeBlock) k_gauge_force(KGeom g, const double2* __restrict__ U,
                                                              double beta, double c0, double c1,
                                                              int accumulate, double2* F) {
@@ -243,7 +251,7 @@ __global__ void __launch_bounds__(kGaugeBlock) k_gauge_force(KGeom g, const doub
   const int pm = int(idx / g.Vh);
   const int par = pm >> 2, mu = pm & 3;
   const C4 x = site_c4(g, h, par);
-  const M3 A = staples(g, U, x, mu, c0, c1);
+  const M3 A = staples<SEL>(g, U, x, mu, c0, c1);
   M3 W = m_mul(link(g, U, x, mu), A);
   const double s = -beta / 3.0;
 #pragma unroll
@@ -483,7 +491,7 @@ __device__ __forceinline__ M3 m_add(M3 a, const M3& b) {
 
 __device__ __forceinline__ void stout_x(const KGeom& g, const double2* __restrict__ U, const C4& x,
                                         int mu, double rho, M3& A, M3& u, M3& X) {
-  A = staples(g, U, x, mu, 1.0, 0.0);
+  A = staples<kStaplePlaq>(g, U, x, mu, 1.0, 0.0);
   u = link(g, U, x, mu);
   X = m_scale(-rho, traceless_antiherm(m_mul(u, A)));
 }
@@ -771,9 +779,24 @@ int lqcd_gauge_force(const lqcd_geom* g, const void* U64, double beta, double c1
   }
   const KGeom k = make_kgeom(g);
   const int64_t n = int64_t(8) * k.Vh;
-  hipLaunchKernelGGL(k_gauge_force, dim3(unsigned((n + kGaugeBlock - 1) / kGaugeBlock)),
-                     dim3(kGaugeBlock), 0, (hipStream_t)stream, k, (const double2*)U64, beta,
-                     1.0 - 8.0 * c1, c1, accumulate, (double2*)F);
+  // F is linear in the staple sum, so the shapes split over three launches:
+  // the later ones add TA(U (-beta/3) A_k) onto the first's result.
+  const dim3 grid(unsigned((n + kGaugeBlock - 1) / kGaugeBlock));
+  const hipStream_t s = (hipStream_t)stream;
+  if (c1 == 0.0) {
+    hipLaunchKernelGGL(k_gauge_force<kStaplePlaq>, grid, dim3(kGaugeBlock), 0, s, k,
+                       (const double2*)U64, beta, 1.0, 0.0, accumulate, (double2*)F);
+    LQCD_LAUNCH_CHECK();
+    return LQCD_OK;
+  }
+  hipLaunchKernelGGL(k_gauge_force<kStaplePass1>, grid, dim3(kGaugeBlock), 0, s, k,
+                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, accumulate, (double2*)F);
+  LQCD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gauge_force<kStaplePass2>, grid, dim3(kGaugeBlock), 0, s, k,
+                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, 1, (double2*)F);
+  LQCD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gauge_force<kStaplePass3>, grid, dim3(kGaugeBlock), 0, s, k,
+                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, 1, (double2*)F);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
