@@ -420,6 +420,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rhmc", action="store_true",
                     help="skip the RHMC heatbath / action measurement")
+    ap.add_argument("--rhmc-only", action="store_true",
+                    help="only the RHMC measurements (heatbath, action, trajectory, gauge "
+                         "force, stout smearing), for profiling them")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="one solve + standalone D_oe + copy kernel, for counter runs")
     args = ap.parse_args()
@@ -448,6 +451,13 @@ def main():
     params = lq.solver_params(mass=w["mass"], tol=1e-10, inner_prec=lq.F32,
                               inner_fmt=lq.LINKS12, reliable_interval=100, use_graph=1)
     dom = dict(prec=lq.F32, fmt=lq.LINKS12, nrhs=nrhs)
+
+    if args.rhmc_only:
+        U64 = lq.pack_links(g, U_dev)
+        rh = rhmc_heatbath(lq, torch, g, U64, w["mass"], nrhs)
+        tr = rhmc_trajectory_bench(lq, torch, g, U64)
+        print(json.dumps({"rhmc_heatbath": rh, "rhmc_trajectory": tr}), flush=True)
+        return
 
     if args.profile_kernels:
         U64 = lq.pack_links(g, U_dev)
