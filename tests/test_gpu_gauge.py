@@ -165,3 +165,29 @@ def test_rhmc_trajectory_reversible_and_conserving(lq):
     Hp.neg_()
     lq.md_integrate(g, U, Hp, 0.5, 4, force)
     assert (U - U0).abs().max().item() <= 1e-9
+
+
+def test_gauge_force_is_derivative_at_workload_size(lq):
+    """48^4 (the workload lattice): dS_g/deps along U -> exp(eps T) U on 16
+    scattered links equals sum Tr[T F] there (a property at any size; the
+    action and force both from the GPU, the perturbation applied in place)."""
+    L = (48, 48, 48, 48)
+    g = lq.Geometry(L)
+    beta = 5.0
+    U64 = lq.pack_links(g, cu(synth.links_exp(L, 0.5, 511)))
+    F = lq.gauge_force(g, U64, beta)
+    rng = np.random.default_rng(512)
+    picks = [(int(rng.integers(2)), int(rng.integers(4)), int(rng.integers(g.Vh))) for _ in range(16)]
+    T = torch.from_numpy(synth.su3_from_coeffs(rng.standard_normal((16, 8)))).to("cuda")
+    U0 = [U64[p, m, :, h].clone() for p, m, h in picks]
+    pred = sum(float(torch.real(torch.trace(T[k] @ F[p, m, :, h].reshape(3, 3))).item())
+               for k, (p, m, h) in enumerate(picks))
+    eps = 1e-3
+    S = []
+    for sgn in (1.0, -1.0):
+        for k, (p, m, h) in enumerate(picks):
+            E = torch.linalg.matrix_exp(sgn * eps * T[k])
+            U64[p, m, :, h] = (E @ U0[k].reshape(3, 3)).reshape(9)
+        S.append(lq.gauge_action(g, U64, beta))
+    d = (S[0] - S[1]) / (2 * eps)
+    assert abs(d - pred) <= 1e-5 * max(1.0, abs(pred)), (d, pred)
