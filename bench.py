@@ -629,7 +629,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
-        "data": "synthetic (seeded; see DESIGN.md input recipe)",
+        "data": "synthetic (seeded generators in synth/: Haar links, Gaussian even-site sources)",
         "config": {"workload": w["name"], "lattice": list(L), "nrhs": nrhs, "nshift": nshift,
                    "mass": w["mass"], "tol": 1e-10, "inner": "fp32 12-real",
                    "reliable_interval": 100, "reliable_delta": 1e-3, "mixed_switch": 1e-3},

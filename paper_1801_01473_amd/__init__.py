@@ -588,9 +588,49 @@ def md_integrate(geom: Geometry, U64, H, tau: float, nsteps: int, force,
     return nforce
 
 
+def md_integrate_nested(geom: Geometry, U64, H, tau: float, steps, forces,
+                        lam: float = OMELYAN_LAMBDA):
+    """Multi-step (nested time-scale) integration: level 0 takes steps[0]
+    Omelyan steps over tau with forces[0]; every drift of level k is a full
+    integration of level k + 1 (steps[k + 1] steps) over that time; the
+    innermost drift is the link update.  Typical use: the fermion force
+    (expensive, smooth) outside, the gauge force inside.  Each level is the
+    second-order minimum-norm scheme of md_integrate, so the composition is
+    reversible and second order.  Returns the force evaluations per level."""
+    if len(steps) != len(forces) or not steps or min(steps) < 1:
+        raise ValueError("need one step count >= 1 per force")
+    F = empty_links(geom, F64, LINKS18, U64.device)
+    counts = [0] * len(steps)
+
+    def kick(k, dt):
+        forces[k](U64, F)
+        counts[k] += 1
+        md_update_momenta(geom, H, F, dt)
+
+    def drift(k, t):
+        if k == len(steps) - 1:
+            md_update_links(geom, U64, H, t)
+        else:
+            level(k + 1, t)
+
+    def level(k, T):
+        n = steps[k]
+        eps = T / n
+        kick(k, lam * eps)
+        for i in range(n):
+            drift(k, 0.5 * eps)
+            kick(k, (1.0 - 2.0 * lam) * eps)
+            drift(k, 0.5 * eps)
+            kick(k, (2.0 * lam if i < n - 1 else lam) * eps)
+
+    level(0, float(tau))
+    return counts
+
+
 def rhmc_trajectory(geom: Geometry, params: SolverParams, U64, beta: float, approx_eighth,
                     approx_quarter, xi, H, u: float, tau: float = 1.0, nsteps: int = 10,
-                    c1: float = SYMANZIK_C1, integrator: str = "omelyan"):
+                    c1: float = SYMANZIK_C1, integrator: str = "omelyan",
+                    gauge_substeps: int = 1):
     """One RHMC trajectory (Sec. 2, Sec. 5) for one staggered field with the
     pseudofermion action phi^dag A^(-1/4) phi (Eq. (1)):
       heatbath phi = r_{1/8}(A) xi; H_0 = H^2/2 + S_g + S_f;
@@ -600,7 +640,10 @@ def rhmc_trajectory(geom: Geometry, params: SolverParams, U64, beta: float, appr
       uniform u, else restore the links.
     U64 (packed FP64 18-real) and H (packed momenta, Hermitian traceless) are
     updated in place; xi [n][3][Vh] packed even FP64 noise of density
-    exp(-|xi|^2).  Returns a dict with the energies, dH, accepted and counts."""
+    exp(-|xi|^2).  gauge_substeps > 1: multi-step integration, the fermion
+    force on the nsteps outer steps and the gauge force on gauge_substeps
+    inner steps per outer drift (Omelyan at both levels).  Returns a dict with
+    the energies, dH, accepted and counts."""
     U0 = U64.clone()
     phi, _ = pseudofermion_heatbath(geom, params, U64, approx_eighth, xi)
     q = approx_quarter
@@ -609,14 +652,22 @@ def rhmc_trajectory(geom: Geometry, params: SolverParams, U64, beta: float, appr
         S_f, _, st = rational_action(geom, params, U64, q, phi)
         return kinetic_energy(geom, H), gauge_action(geom, U64, beta, c1), S_f
 
-    def force(U, F):
+    def fermion_only(U, F):
         X, _, _ = cg_multishift(geom, params, U, q.sigma, phi)
         fermion_force(geom, U, q.alpha, X, mode=0, out=F)
         del X
+
+    def force(U, F):
+        fermion_only(U, F)
         gauge_force(geom, U, beta, c1, out=F, accumulate=True)
 
     e0 = energy()
-    nforce = md_integrate(geom, U64, H, tau, nsteps, force, integrator)
+    if gauge_substeps > 1:
+        nforce = md_integrate_nested(
+            geom, U64, H, tau, [nsteps, gauge_substeps],
+            [fermion_only, lambda U, F: gauge_force(geom, U, beta, c1, out=F)])[0]
+    else:
+        nforce = md_integrate(geom, U64, H, tau, nsteps, force, integrator)
     e1 = energy()
     h0, h1 = sum(e0), sum(e1)
     acc = metropolis_accept(h0, h1, u)

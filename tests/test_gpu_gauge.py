@@ -191,3 +191,40 @@ def test_gauge_force_is_derivative_at_workload_size(lq):
         S.append(lq.gauge_action(g, U64, beta))
     d = (S[0] - S[1]) / (2 * eps)
     assert abs(d - pred) <= 1e-5 * max(1.0, abs(pred)), (d, pred)
+
+
+def test_nested_integrator_reversible_and_second_order(lq):
+    """Multi-step integration (fermion force outside, gauge force on 4
+    substeps inside): reversible, dH falls as eps^2 in the outer step, and the
+    fermion force is evaluated only on the outer level."""
+    L = (8, 8, 8, 8)
+    g = lq.Geometry(L)
+    beta, m = 2.0, 0.1
+    lo, hi = lq.spectral_bounds(m)
+    e8 = lq.minimax(0.125, lo, hi, 10)
+    q4 = lq.minimax(-0.25, lo, hi, 10)
+    p = lq.solver_params(mass=m, tol=1e-12)
+    U0 = lq.pack_links(g, cu(synth.links_exp(L, 0.3, 513)))
+    H0 = lq.pack_links(g, cu(synth.momenta(L, 514)))
+    xi = lq.pack_spinor(g, cu(synth.gaussian_even_source(L, 1, 515)), 0)
+    dH = []
+    for n in (6, 12):
+        U, Hp = U0.clone(), H0.clone()
+        r = lq.rhmc_trajectory(g, p, U, beta, e8, q4, xi, Hp, u=0.0, tau=0.5, nsteps=n,
+                               gauge_substeps=4)
+        assert r["force_evaluations"] == 2 * n + 1
+        dH.append(r["dH"])
+    assert 2.5 < dH[0] / dH[1] < 6.0
+    phi, _ = lq.pseudofermion_heatbath(g, p, U0, e8, xi)
+
+    def ferm(Ux, F):
+        X, _, _ = lq.cg_multishift(g, p, Ux, q4.sigma, phi)
+        lq.fermion_force(g, Ux, q4.alpha, X, out=F)
+
+    gauge = lambda Ux, F: lq.gauge_force(g, Ux, beta, out=F)
+    U, Hp = U0.clone(), H0.clone()
+    counts = lq.md_integrate_nested(g, U, Hp, 0.5, [3, 4], [ferm, gauge])
+    assert counts == [7, 3 * 2 * 9]
+    Hp.neg_()
+    lq.md_integrate_nested(g, U, Hp, 0.5, [3, 4], [ferm, gauge])
+    assert (U - U0).abs().max().item() <= 1e-9
