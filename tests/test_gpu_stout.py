@@ -74,3 +74,37 @@ def test_fermion_force_through_two_smearing_levels(lq):
     Gref = oracle.stout_force(L, U1, rho, Gref, mode=1)
     Fref = oracle.stout_force(L, U, rho, Gref, mode=0)
     assert H.max_rel(F, Fref) <= 1e-11
+
+
+def test_chain_rule_is_derivative_at_workload_size(lq):
+    """48^4: S(U) = sum Re Tr[W U'(U)] for a random W and one smearing level;
+    dS/deps along U -> exp(eps T) U on 16 scattered links equals sum Tr[T F],
+    F from the chain rule with G' = W^dag (GPU only; a property at any size)."""
+    L = (48, 48, 48, 48)
+    g = lq.Geometry(L)
+    rho = 0.12
+    U64 = lq.pack_links(g, cu(synth.links_exp(L, 0.5, 956)))
+    gen = torch.Generator(device="cuda").manual_seed(957)
+    W = torch.randn(U64.shape, dtype=torch.complex128, device="cuda", generator=gen)
+    W9 = W.view(2, 4, 3, 3, g.Vh)
+
+    def S(Ux):
+        Us = lq.stout_smear(g, Ux, rho)[1].view(2, 4, 3, 3, g.Vh)
+        return float((W9 * Us.transpose(2, 3)).sum().real.item())
+
+    Gp = W9.transpose(2, 3).conj().contiguous().view(U64.shape)
+    F = lq.stout_force(g, [U64, lq.stout_smear(g, U64, rho)[1]], rho, Gp, mode=0)
+    rng = np.random.default_rng(958)
+    picks = [(int(rng.integers(2)), int(rng.integers(4)), int(rng.integers(g.Vh))) for _ in range(16)]
+    T = torch.from_numpy(synth.su3_from_coeffs(rng.standard_normal((16, 8)))).to("cuda")
+    U0 = [U64[p, m, :, h].clone() for p, m, h in picks]
+    pred = sum(float(torch.real(torch.trace(T[k] @ F[p, m, :, h].reshape(3, 3))).item())
+               for k, (p, m, h) in enumerate(picks))
+    eps = 1e-4
+    vals = []
+    for sgn in (1.0, -1.0):
+        for k, (p, m, h) in enumerate(picks):
+            U64[p, m, :, h] = (torch.linalg.matrix_exp(sgn * eps * T[k]) @ U0[k].reshape(3, 3)).reshape(9)
+        vals.append(S(U64))
+    d = (vals[0] - vals[1]) / (2 * eps)
+    assert abs(d - pred) <= 1e-5 * max(1.0, abs(pred)), (d, pred)
