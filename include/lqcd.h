@@ -36,7 +36,10 @@
  *           direction, element, half index.  NE = 9 (LQCD_LINKS18, full
  *           matrix, element = 3*row+col) or NE = 6 (LQCD_LINKS12, rows 0-1;
  *           row 2 is rebuilt as the complex conjugate of the cross product of
- *           rows 0 and 1, Sec. 4.1 -- only valid for SU(3) links).
+ *           rows 0 and 1, Sec. 4.1 -- only valid for SU(3) links) or NE = 7
+ *           (LQCD_LINKS12D, rows 0-1 and the determinant d as element 6; row
+ *           2 = d conj(row0 x row1), exact for every unitary link, so links
+ *           carrying U(1) phases (lqcd_apply_u1_phases) stay compressed).
  *   complex = two IEEE doubles (LQCD_F64) or two floats (LQCD_F32).
  *
  * Memory and streams: every data pointer is a device pointer owned by the
@@ -71,7 +74,7 @@ enum lqcd_status {
 };
 
 enum lqcd_prec { LQCD_F64 = 0, LQCD_F32 = 1 };
-enum lqcd_link_fmt { LQCD_LINKS18 = 0, LQCD_LINKS12 = 1 };
+enum lqcd_link_fmt { LQCD_LINKS18 = 0, LQCD_LINKS12 = 1, LQCD_LINKS12D = 2 };
 
 typedef struct {
     int32_t L[4];           /* Lx, Ly, Lz, Lt: each even and >= 2;
@@ -106,6 +109,8 @@ int lqcd_pack_links(const lqcd_geom *g, const void *U_nat, int prec, int fmt,
 /*
  * Convert an already packed field into another precision/format
  * (e.g. LQCD_F64/LQCD_LINKS18 -> LQCD_F32/LQCD_LINKS12 for the inner solver).
+ * Every source format is first completed to the full matrix; LQCD_LINKS12D
+ * destinations store its determinant.
  */
 int lqcd_convert_links(const lqcd_geom *g, const void *src, int src_prec, int src_fmt,
                        void *dst, int dst_prec, int dst_fmt, void *stream);
@@ -327,9 +332,10 @@ int lqcd_rational_combine(const lqcd_geom *g, int32_t nrhs, int32_t nshift, doub
  *   out    packed FP64 18-real (may be U64).
  * Every entry point then takes `out` as its FP64 links: D_oe/D_eo, the
  * solvers and the fermion force (whose TA(U M) is unchanged by the factor).
- * Phased links are not in SU(3) (det = exp(3 i theta)), so the 12-real
- * formats -- which rebuild row 2 from det = 1 -- must not be used with them:
- * convert to LQCD_LINKS18 for any inner solver precision.  Stream-ordered.
+ * Phased links are not in SU(3) (det = exp(3 i theta)), so LQCD_LINKS12 --
+ * which rebuilds row 2 from det = 1 -- must not be used with them; the
+ * compressed format for them is LQCD_LINKS12D (rows 0-1 and the determinant,
+ * 7 complex per link), e.g. as the inner solver format.  Stream-ordered.
  */
 int lqcd_apply_u1_phases(const lqcd_geom *g, const void *U64, const double *theta, void *out,
                          void *stream);

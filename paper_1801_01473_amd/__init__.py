@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblqcd.so")
 
 F64, F32 = 0, 1
-LINKS18, LINKS12 = 0, 1
+LINKS18, LINKS12, LINKS12D = 0, 1, 2
 
 OK = 0
 ERR_INVALID_ARG = 1
@@ -211,7 +211,7 @@ def _cdtype(prec):
 
 
 def _ne(fmt):
-    return 9 if fmt == LINKS18 else 6
+    return {LINKS18: 9, LINKS12: 6, LINKS12D: 7}[fmt]
 
 
 def links_bytes(geom: Geometry, prec=F64, fmt=LINKS18) -> int:
@@ -277,7 +277,7 @@ def _prec_of(t):
 
 
 def _fmt_of(U):
-    return LINKS18 if U.shape[2] == 9 else LINKS12
+    return {9: LINKS18, 6: LINKS12, 7: LINKS12D}[int(U.shape[2])]
 
 
 def doe(geom: Geometry, U, psi_even, out=None):

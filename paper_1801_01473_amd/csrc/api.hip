@@ -66,8 +66,9 @@ int check_prec_fmt(int prec, int fmt) {
     set_error("precision must be LQCD_F64 (0) or LQCD_F32 (1), got %d", prec);
     return LQCD_ERR_INVALID_ARG;
   }
-  if (fmt != LQCD_LINKS18 && fmt != LQCD_LINKS12) {
-    set_error("link format must be LQCD_LINKS18 (0) or LQCD_LINKS12 (1), got %d", fmt);
+  if (fmt != LQCD_LINKS18 && fmt != LQCD_LINKS12 && fmt != LQCD_LINKS12D) {
+    set_error("link format must be LQCD_LINKS18 (0), LQCD_LINKS12 (1) or LQCD_LINKS12D (2), got %d",
+              fmt);
     return LQCD_ERR_INVALID_ARG;
   }
   return LQCD_OK;

@@ -196,7 +196,9 @@ int check_prec_fmt(int prec, int fmt);
 int check_ptr(const void* p, const char* name);
 int check_nrhs(int32_t nrhs);
 
-inline size_t link_elems(int fmt) { return fmt == LQCD_LINKS12 ? 6 : 9; }
+inline size_t link_elems(int fmt) {
+  return fmt == LQCD_LINKS12 ? 6 : fmt == LQCD_LINKS12D ? 7 : 9;
+}
 inline size_t real_bytes(int prec) { return prec == LQCD_F32 ? 4 : 8; }
 
 }  // namespace lqcd

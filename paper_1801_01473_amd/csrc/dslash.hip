@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
         for (int b = 0; b < B; ++b)
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) v[b][cc] = ld_buf<R>(rin[b], on, uint32_t(cc) * csoff);
-        if (NE == 6) reconstruct_row2<R>(u);
+        complete_link<R, NE>(u);
         if (!fw) {  // U^dag
           Su3<R> t = u;
 #pragma unroll
@@ -224,10 +224,8 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
             vb[b][c] = ld_buf<R>(rin[b], ob, uint32_t(c) * csoff);
           }
       }
-      if (NE == 6) {
-        reconstruct_row2<R>(uf);
-        reconstruct_row2<R>(ub);
-      }
+      complete_link<R, NE>(uf);
+      complete_link<R, NE>(ub);
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         cplx<R> y[3];
@@ -353,6 +351,20 @@ int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     set_error("non-temporal own-site streams (ns) need non-temporal link loads (nt)");
     return LQCD_ERR_UNSUPPORTED;
   }
+  if constexpr (NE == 7) {
+    // the phased-link format instantiates the plain schedule only (loads
+    // first is dropped): half the variants, the same results
+    switch ((cfg.nt ? 1 : 0) | (cfg.hh ? 4 : 0) | (cfg.ns ? 8 : 0)) {
+      case 0: LQCD_K(0); break;
+      case 1: LQCD_K(1); break;
+      case 4: LQCD_K(4); break;
+      case 5: LQCD_K(5); break;
+      case 9: LQCD_K(9); break;
+      default: LQCD_K(13); break;
+    }
+    LQCD_LAUNCH_CHECK();
+    return LQCD_OK;
+  } else {
   switch ((cfg.nt ? 1 : 0) | (cfg.lf ? 2 : 0) | (cfg.hh ? 4 : 0) | (cfg.ns ? 8 : 0)) {
     case 0: LQCD_K(0); break;
     case 1: LQCD_K(1); break;
@@ -367,9 +379,10 @@ int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     case 13: LQCD_K(13); break;
     default: LQCD_K(15); break;
   }
-#undef LQCD_K
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
+  }
+#undef LQCD_K
 }
 
 template <typename R, int NE, int MODE, typename RO>
@@ -418,10 +431,12 @@ int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     return launch_b<double, 9, DM_RES, double>(c, cfg, st);
   }
   if (c.prec == LQCD_F64)
-    return c.fmt == LQCD_LINKS12 ? launch_mode<double, 6>(c, cfg, st)
-                                 : launch_mode<double, 9>(c, cfg, st);
-  return c.fmt == LQCD_LINKS12 ? launch_mode<float, 6>(c, cfg, st)
-                               : launch_mode<float, 9>(c, cfg, st);
+    return c.fmt == LQCD_LINKS12    ? launch_mode<double, 6>(c, cfg, st)
+           : c.fmt == LQCD_LINKS12D ? launch_mode<double, 7>(c, cfg, st)
+                                    : launch_mode<double, 9>(c, cfg, st);
+  return c.fmt == LQCD_LINKS12    ? launch_mode<float, 6>(c, cfg, st)
+         : c.fmt == LQCD_LINKS12D ? launch_mode<float, 7>(c, cfg, st)
+                                  : launch_mode<float, 9>(c, cfg, st);
 }
 
 // ----------------------------------------------------------------- tuner

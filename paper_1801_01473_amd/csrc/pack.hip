@@ -14,6 +14,25 @@ constexpr int kBlock = 256;
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Writes the NE stored elements of the full matrix u at stride Vh: 9 or 6 as
+// is, 7 = rows 0-1 and det u.
+template <typename R, int NE>
+__device__ __forceinline__ void store_link(const Su3<double>& u, cplx<R>* dst, int Vh) {
+#pragma unroll
+  for (int e = 0; e < (NE == 7 ? 6 : NE); ++e)
+    dst[int64_t(e) * Vh] = mk<R>((R)u.e[e].x, (R)u.e[e].y);
+  if constexpr (NE == 7) {
+    const double2 m0 = csub<double>(cmul<double>(u.e[4], u.e[8]), cmul<double>(u.e[5], u.e[7]));
+    const double2 m1 = csub<double>(cmul<double>(u.e[3], u.e[8]), cmul<double>(u.e[5], u.e[6]));
+    const double2 m2 = csub<double>(cmul<double>(u.e[3], u.e[7]), cmul<double>(u.e[4], u.e[6]));
+    double2 d = cmul<double>(u.e[0], m0);
+    const double2 t1 = cmul<double>(u.e[1], m1), t2 = cmul<double>(u.e[2], m2);
+    d.x += t2.x - t1.x;
+    d.y += t2.y - t1.y;
+    dst[int64_t(6) * Vh] = mk<R>((R)d.x, (R)d.y);
+  }
+}
+
 // natural complex128 [4][V][3][3] -> packed [2][4][NE][Vh] of R
 template <typename R, int NE>
 __global__ void __launch_bounds__(kBlock) k_pack_links(KGeom g, const double2* __restrict__ nat,
@@ -33,9 +52,10 @@ __global__ void __launch_bounds__(kBlock) k_pack_links(KGeom g, const double2* _
   const int par = (x + y + z + t) & 1;
   const int h = lex >> 1;
   const double2* src = nat + i * 9;
-  cplx<R>* dst = out + (int64_t(par) * 4 + mu) * NE * g.Vh + h;
+  Su3<double> u;
 #pragma unroll
-  for (int e = 0; e < NE; ++e) dst[int64_t(e) * g.Vh] = mk<R>((R)src[e].x, (R)src[e].y);
+  for (int e = 0; e < 9; ++e) u.e[e] = src[e];
+  store_link<R, NE>(u, out + (int64_t(par) * 4 + mu) * NE * g.Vh + h, g.Vh);
 }
 
 // packed F64-18 -> natural complex128
@@ -76,10 +96,8 @@ __global__ void __launch_bounds__(kBlock) k_convert_links(int Vh, const cplx<RS>
     const cplx<RS> v = src[int64_t(e) * Vh];
     u.e[e] = mk<double>((double)v.x, (double)v.y);
   }
-  if (NS == 6) reconstruct_row2(u);
-  cplx<RD>* dst = out + pm * ND * Vh + h;
-#pragma unroll
-  for (int e = 0; e < ND; ++e) dst[int64_t(e) * Vh] = mk<RD>((RD)u.e[e].x, (RD)u.e[e].y);
+  complete_link<double, NS>(u);
+  store_link<RD, ND>(u, out + pm * ND * Vh + h, Vh);
 }
 
 // natural complex128 [nrhs][V][3] -> packed [nrhs][3][Vh] of R, one parity
@@ -132,32 +150,40 @@ __global__ void __launch_bounds__(kBlock) k_unpack_spinor(KGeom g, int par, int 
 
 }  // namespace
 
+namespace {
+
+template <typename RS, int NS, typename RD, int ND>
+void conv_launch(const KGeom& k, const void* src, void* dst, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert_links<RS, NS, RD, ND>), dim3(grid_for(int64_t(8) * k.Vh)),
+                     dim3(kBlock), 0, st, k.Vh, (const cplx<RS>*)src, (cplx<RD>*)dst);
+}
+
+template <typename RS, int NS>
+void conv_dst(const KGeom& k, const void* src, void* dst, int dp, int df, hipStream_t st) {
+  if (dp == LQCD_F64) {
+    if (df == LQCD_LINKS12) conv_launch<RS, NS, double, 6>(k, src, dst, st);
+    else if (df == LQCD_LINKS12D) conv_launch<RS, NS, double, 7>(k, src, dst, st);
+    else conv_launch<RS, NS, double, 9>(k, src, dst, st);
+  } else {
+    if (df == LQCD_LINKS12) conv_launch<RS, NS, float, 6>(k, src, dst, st);
+    else if (df == LQCD_LINKS12D) conv_launch<RS, NS, float, 7>(k, src, dst, st);
+    else conv_launch<RS, NS, float, 9>(k, src, dst, st);
+  }
+}
+
+}  // namespace
+
 int convert_links_async(const KGeom& k, const void* src, int sp, int sf, void* dst, int dp,
                         int df, hipStream_t st) {
-  const unsigned grid = grid_for(int64_t(8) * k.Vh);
-#define LQCD_CONV(RS, NS, RD, ND)                                                      \
-  hipLaunchKernelGGL((k_convert_links<RS, NS, RD, ND>), dim3(grid), dim3(kBlock), 0, st, \
-                     k.Vh, (const cplx<RS>*)src, (cplx<RD>*)dst)
-  const int key = (sp << 3) | (sf << 2) | (dp << 1) | df;
-  switch (key) {
-    case 0b0000: LQCD_CONV(double, 9, double, 9); break;
-    case 0b0001: LQCD_CONV(double, 9, double, 6); break;
-    case 0b0010: LQCD_CONV(double, 9, float, 9); break;
-    case 0b0011: LQCD_CONV(double, 9, float, 6); break;
-    case 0b0100: LQCD_CONV(double, 6, double, 9); break;
-    case 0b0101: LQCD_CONV(double, 6, double, 6); break;
-    case 0b0110: LQCD_CONV(double, 6, float, 9); break;
-    case 0b0111: LQCD_CONV(double, 6, float, 6); break;
-    case 0b1000: LQCD_CONV(float, 9, double, 9); break;
-    case 0b1001: LQCD_CONV(float, 9, double, 6); break;
-    case 0b1010: LQCD_CONV(float, 9, float, 9); break;
-    case 0b1011: LQCD_CONV(float, 9, float, 6); break;
-    case 0b1100: LQCD_CONV(float, 6, double, 9); break;
-    case 0b1101: LQCD_CONV(float, 6, double, 6); break;
-    case 0b1110: LQCD_CONV(float, 6, float, 9); break;
-    default: LQCD_CONV(float, 6, float, 6); break;
+  if (sp == LQCD_F64) {
+    if (sf == LQCD_LINKS12) conv_dst<double, 6>(k, src, dst, dp, df, st);
+    else if (sf == LQCD_LINKS12D) conv_dst<double, 7>(k, src, dst, dp, df, st);
+    else conv_dst<double, 9>(k, src, dst, dp, df, st);
+  } else {
+    if (sf == LQCD_LINKS12) conv_dst<float, 6>(k, src, dst, dp, df, st);
+    else if (sf == LQCD_LINKS12D) conv_dst<float, 7>(k, src, dst, dp, df, st);
+    else conv_dst<float, 9>(k, src, dst, dp, df, st);
   }
-#undef LQCD_CONV
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
@@ -179,18 +205,20 @@ int lqcd_pack_links(const lqcd_geom* g, const void* U_nat, int prec, int fmt, vo
   const unsigned grid = grid_for(int64_t(8) * k.Vh);
   hipStream_t s = (hipStream_t)stream;
   const double2* src = (const double2*)U_nat;
-  if (prec == LQCD_F64 && fmt == LQCD_LINKS18)
-    hipLaunchKernelGGL((k_pack_links<double, 9>), dim3(grid), dim3(kBlock), 0, s, k, src,
-                       (double2*)U_packed);
-  else if (prec == LQCD_F64)
-    hipLaunchKernelGGL((k_pack_links<double, 6>), dim3(grid), dim3(kBlock), 0, s, k, src,
-                       (double2*)U_packed);
-  else if (fmt == LQCD_LINKS18)
-    hipLaunchKernelGGL((k_pack_links<float, 9>), dim3(grid), dim3(kBlock), 0, s, k, src,
-                       (float2*)U_packed);
-  else
-    hipLaunchKernelGGL((k_pack_links<float, 6>), dim3(grid), dim3(kBlock), 0, s, k, src,
-                       (float2*)U_packed);
+#define LQCD_PACK(R, NE)                                                                  \
+  hipLaunchKernelGGL((k_pack_links<R, NE>), dim3(grid), dim3(kBlock), 0, s, k, src,       \
+                     (cplx<R>*)U_packed)
+  const int ne = fmt == LQCD_LINKS12 ? 6 : fmt == LQCD_LINKS12D ? 7 : 9;
+  if (prec == LQCD_F64) {
+    if (ne == 9) LQCD_PACK(double, 9);
+    else if (ne == 6) LQCD_PACK(double, 6);
+    else LQCD_PACK(double, 7);
+  } else {
+    if (ne == 9) LQCD_PACK(float, 9);
+    else if (ne == 6) LQCD_PACK(float, 6);
+    else LQCD_PACK(float, 7);
+  }
+#undef LQCD_PACK
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }

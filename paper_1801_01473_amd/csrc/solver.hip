@@ -773,8 +773,10 @@ Layout make_layout(const KGeom& g, const lqcd_solver_params& p, int nshift, int 
   L.has_links = !(iprec == LQCD_F64 && ifmt == LQCD_LINKS18);
   L.links = L.has_links ? take(size_t(8) * link_elems(ifmt) * g.Vh * 2 * ri) : 0;
   // the FP64 opening phase streams FP64 links in the inner format (12-real:
-  // a third fewer link bytes than the 18-real copy used for residuals)
-  L.links_pre = (L.has_pre && ifmt == LQCD_LINKS12) ? take(size_t(8) * 6 * g.Vh * 16) : 0;
+  // a third fewer link bytes than the 18-real copy used for residuals;
+  // 12-real + determinant for links with U(1) phases)
+  L.links_pre =
+      (L.has_pre && ifmt != LQCD_LINKS18) ? take(size_t(8) * link_elems(ifmt) * g.Vh * 16) : 0;
   // deferred shift updates: base directions and window coefficients
   if (L.win > 1) {
     L.pc = take(nrhs * vin);
@@ -1282,7 +1284,7 @@ int setup_core(const Ctx& c, Core& k) {
     Phase& q = k.pre;
     q.prec = LQCD_F64;
     q.fmt = c.ifmt;
-    q.U = c.ifmt == LQCD_LINKS12 ? static_cast<const void*>(c.ws + c.L.links_pre) : c.U64;
+    q.U = c.ifmt != LQCD_LINKS18 ? static_cast<const void*>(c.ws + c.L.links_pre) : c.U64;
     q.r = c.L.r64;
     q.t = c.L.t64;
     q.p = c.L.p64;
@@ -1596,7 +1598,7 @@ int solve(const lqcd_geom* geom, const lqcd_solver_params* params, const void* U
 
   if (c.L.links_pre) {
     if ((rc = convert_links_async(c.g, U64, LQCD_F64, LQCD_LINKS18, c.ws + c.L.links_pre,
-                                  LQCD_F64, LQCD_LINKS12, c.s)))
+                                  LQCD_F64, c.ifmt, c.s)))
       return rc;
   }
 

@@ -23,6 +23,28 @@ __device__ __forceinline__ void reconstruct_row2(Su3<R>& u) {
   u.e[8] = conj_of<R>(csub<R>(cmul<R>(u.e[0], u.e[4]), cmul<R>(u.e[1], u.e[3])));
 }
 
+// Row 2 of a unitary link from rows 0 and 1 and d = det U (element 6 of the
+// 7-element format): for V = e^{i phi} W, W in SU(3), row 2 = d conj(row0 x
+// row1); d = 1 is reconstruct_row2.  Serves links that carry U(1) phases.
+template <typename R>
+__device__ __forceinline__ void reconstruct_row2_det(Su3<R>& u) {
+  const cplx<R> d = u.e[6];
+  const cplx<R> c0 = conj_of<R>(csub<R>(cmul<R>(u.e[1], u.e[5]), cmul<R>(u.e[2], u.e[4])));
+  const cplx<R> c1 = conj_of<R>(csub<R>(cmul<R>(u.e[2], u.e[3]), cmul<R>(u.e[0], u.e[5])));
+  const cplx<R> c2 = conj_of<R>(csub<R>(cmul<R>(u.e[0], u.e[4]), cmul<R>(u.e[1], u.e[3])));
+  u.e[6] = cmul<R>(d, c0);
+  u.e[7] = cmul<R>(d, c1);
+  u.e[8] = cmul<R>(d, c2);
+}
+
+// The full matrix from the NE stored elements (9: as is; 6: SU(3) rows 0-1;
+// 7: rows 0-1 and the determinant).
+template <typename R, int NE>
+__device__ __forceinline__ void complete_link(Su3<R>& u) {
+  if constexpr (NE == 6) reconstruct_row2<R>(u);
+  if constexpr (NE == 7) reconstruct_row2_det<R>(u);
+}
+
 // Buffer resources: a scalar 64-bit base and byte range for a whole array
 // block, so that each load needs one 32-bit per-lane offset (shared by every
 // element and colour) plus a scalar offset.  Reads outside [0, bytes) return
@@ -83,7 +105,7 @@ __device__ __forceinline__ void load_link(const cplx<R>* __restrict__ base, int 
                                           Su3<R>& u) {
 #pragma unroll
   for (int e = 0; e < NE; ++e) u.e[e] = base[int64_t(e) * Vh + h];
-  if (NE == 6) reconstruct_row2<R>(u);
+  complete_link<R, NE>(u);
 }
 
 // y = U v

@@ -93,3 +93,67 @@ def test_fermion_force_on_phased_links(lq):
     al = np.array([0.4, 1.2, 2.0])
     F = lq.fermion_force(g, Up, al, lq.pack_spinor(g, cu(X.reshape(-1, g.V, 3)), 0))
     assert H.max_rel(host(lq.unpack_links(g, F)), oracle.force(L, Up_ref, al, X)) <= 1e-12
+
+
+def test_links12d_round_trip_and_dslash(lq):
+    """The 12-real + determinant format keeps phased (non-SU(3)) links exact:
+    pack / convert round trips, D_oe in FP64 and FP32 against the oracle, and
+    the SU(3)-only 12-real format is wrong on the same links."""
+    L = (6, 4, 4, 8)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 808)
+    th = synth.u1_phases_magnetic(L, 3) + synth.u1_phases_chemical(L, 0.45)
+    Up_ref = oracle.phase_links(U, th)
+    Up = lq.apply_u1_phases(g, lq.pack_links(g, cu(U)), cu(th))
+    U12d = lq.pack_links(g, cu(Up_ref), lq.F64, lq.LINKS12D)
+    back = lq.convert_links(g, U12d, lq.F64, lq.LINKS12D, lq.F64, lq.LINKS18)
+    assert H.max_rel(host(lq.unpack_links(g, back)), Up_ref) <= 1e-14
+    c12d = lq.convert_links(g, Up, lq.F64, lq.LINKS18, lq.F64, lq.LINKS12D)
+    assert torch.equal(c12d, U12d) or (c12d - U12d).abs().max().item() <= 1e-15
+    f = synth.gaussian_even_source(L, 3, 809)
+    ref = np.stack([oracle.doe(L, Up_ref, f[j]) for j in range(3)])
+    for prec, tol in ((lq.F64, 1e-13), (lq.F32, 1e-6)):
+        Ul = lq.convert_links(g, Up, lq.F64, lq.LINKS18, prec, lq.LINKS12D)
+        got = host(lq.unpack_spinor(g, lq.doe(g, Ul, lq.pack_spinor(g, cu(f), 0, prec)), 1))
+        assert H.max_rel(got, ref) <= tol
+    U12 = lq.convert_links(g, Up, lq.F64, lq.LINKS18, lq.F64, lq.LINKS12)
+    bad = host(lq.unpack_spinor(g, lq.doe(g, U12, lq.pack_spinor(g, cu(f), 0)), 1))
+    assert H.max_rel(bad, ref) > 1e-3
+
+
+@pytest.mark.parametrize("cfg", ["64,1,0,0", "128,2,1,2,1,0,0,1,1,2", "256,8,1,4,1,3,0,0,1,0,1",
+                                 "128,4,0,2,1,0,1,0,0,2,1", "64,8,0,0,0,2,0,1,0,0"])
+def test_links12d_every_launch_configuration(lq, cfg, monkeypatch):
+    monkeypatch.setenv("LQCD_DSLASH_CFG", cfg)
+    L = (6, 4, 8, 6)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 810)
+    th = synth.u1_phases_chemical(L, -0.7)
+    Up_ref = oracle.phase_links(U, th)
+    Ul = lq.convert_links(g, lq.apply_u1_phases(g, lq.pack_links(g, cu(U)), cu(th)),
+                          lq.F64, lq.LINKS18, lq.F32, lq.LINKS12D)
+    f = synth.gaussian_field(L, 5, 811)
+    got = host(lq.unpack_spinor(g, lq.deo(g, Ul, lq.pack_spinor(g, cu(f), 1, lq.F32)), 0))
+    ref = np.stack([oracle.deo(L, Up_ref, f[j]) for j in range(5)])
+    assert H.max_rel(got, ref) <= 1e-6
+
+
+def test_multishift_phased_links12d_inner(lq):
+    """Mixed precision with the compressed phased format as the inner links
+    (and as the FP64 opening phase's links): every (rhs, shift) <= 1e-10."""
+    L = (8, 8, 8, 8)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 812)
+    th = synth.u1_phases_chemical(L, 0.5) + synth.u1_phases_magnetic(L, 1)
+    Up_ref = oracle.phase_links(U, th)
+    Up = lq.apply_u1_phases(g, lq.pack_links(g, cu(U)), cu(th))
+    b = synth.gaussian_even_source(L, 2, 813)
+    sig = synth.rational_shifts(6, 1e-3, 1.0)
+    m = 0.05
+    p = lq.solver_params(mass=m, tol=1e-10, inner_prec=lq.F32, inner_fmt=lq.LINKS12D)
+    X, _, stats = lq.cg_multishift(g, p, Up, sig, lq.pack_spinor(g, cu(b), 0))
+    Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(2, len(sig), -1, 3)
+    for j in range(2):
+        for i, s in enumerate(sig):
+            assert oracle.true_residual(L, Up_ref, m, s, b[j], Xn[j, i]) <= 1e-10
+    assert all(s["converged"] == 1 for row in stats for s in row)
