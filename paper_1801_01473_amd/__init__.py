@@ -434,7 +434,7 @@ def pseudofermion_heatbath(geom: Geometry, params: SolverParams, U64, approx_eig
     Then phi^dag A^(-1/4) phi = |xi|^2 up to the approximation errors, so phi
     has the density exp(-phi^dag A^(-1/4) phi) of the pseudofermion action.
     Returns (phi, stats)."""
-    if not (0.12 < approx_eighth.power < 0.13):
+    if approx_eighth.power != 0.125:
         raise ValueError("the heatbath needs the x^(1/8) approximation")
     return rational_apply(geom, params, U64, approx_eighth, xi, Uinner)
 
