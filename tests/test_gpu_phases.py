@@ -157,3 +157,26 @@ def test_multishift_phased_links12d_inner(lq):
         for i, s in enumerate(sig):
             assert oracle.true_residual(L, Up_ref, m, s, b[j], Xn[j, i]) <= 1e-10
     assert all(s["converged"] == 1 for row in stats for s in row)
+
+
+def test_phased_dslash_at_workload_size(lq):
+    """48^4 (the workload lattice), magnetic + chemical phases: D_oe on the
+    phased links in the 12-real + determinant format (FP64, FP32) and in
+    18-real FP64 against the oracle, every output site."""
+    L = (48, 48, 48, 48)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 814)
+    th = synth.u1_phases_magnetic(L, 5) + synth.u1_phases_chemical(L, 0.3)
+    Up = lq.apply_u1_phases(g, lq.pack_links(g, cu(U)), cu(th))
+    Up_ref = oracle.phase_links(U, th)
+    del U
+    f = synth.gaussian_even_source(L, 1, 815)
+    ref = oracle.doe(L, Up_ref, f[0])[None]
+    del Up_ref
+    for prec, fmt, tol in ((lq.F64, lq.LINKS18, 1e-13), (lq.F64, lq.LINKS12D, 1e-13),
+                           (lq.F32, lq.LINKS12D, 1e-6)):
+        Ul = Up if (prec, fmt) == (lq.F64, lq.LINKS18) else lq.convert_links(
+            g, Up, lq.F64, lq.LINKS18, prec, fmt)
+        got = host(lq.unpack_spinor(g, lq.doe(g, Ul, lq.pack_spinor(g, cu(f), 0, prec)), 1))
+        assert H.max_rel(got, ref) <= tol, (prec, fmt)
+        del Ul
