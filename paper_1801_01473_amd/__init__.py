@@ -630,7 +630,7 @@ def md_integrate_nested(geom: Geometry, U64, H, tau: float, steps, forces,
 def rhmc_trajectory(geom: Geometry, params: SolverParams, U64, beta: float, approx_eighth,
                     approx_quarter, xi, H, u: float, tau: float = 1.0, nsteps: int = 10,
                     c1: float = SYMANZIK_C1, integrator: str = "omelyan",
-                    gauge_substeps: int = 1):
+                    gauge_substeps: int = 1, stout_rho: float = 0.0, stout_levels: int = 0):
     """One RHMC trajectory (Sec. 2, Sec. 5) for one staggered field with the
     pseudofermion action phi^dag A^(-1/4) phi (Eq. (1)):
       heatbath phi = r_{1/8}(A) xi; H_0 = H^2/2 + S_g + S_f;
@@ -642,19 +642,31 @@ def rhmc_trajectory(geom: Geometry, params: SolverParams, U64, beta: float, appr
     updated in place; xi [n][3][Vh] packed even FP64 noise of density
     exp(-|xi|^2).  gauge_substeps > 1: multi-step integration, the fermion
     force on the nsteps outer steps and the gauge force on gauge_substeps
-    inner steps per outer drift (Omelyan at both levels).  Returns a dict with
-    the energies, dH, accepted and counts."""
+    inner steps per outer drift (Omelyan at both levels).  stout_levels > 0:
+    the Dirac operator uses the stout-smeared links U^(k) (rho = stout_rho),
+    the gauge action the unsmeared ones, and the fermion force is carried back
+    through the smearing levels (Sec. 2).  Returns a dict with the energies,
+    dH, accepted and counts."""
     U0 = U64.clone()
-    phi, _ = pseudofermion_heatbath(geom, params, U64, approx_eighth, xi)
     q = approx_quarter
 
+    def dirac_links(U):
+        return stout_smear(geom, U, stout_rho, stout_levels) if stout_levels > 0 else [U]
+
+    phi, _ = pseudofermion_heatbath(geom, params, dirac_links(U64)[-1], approx_eighth, xi)
+
     def energy():
-        S_f, _, st = rational_action(geom, params, U64, q, phi)
+        S_f, _, st = rational_action(geom, params, dirac_links(U64)[-1], q, phi)
         return kinetic_energy(geom, H), gauge_action(geom, U64, beta, c1), S_f
 
     def fermion_only(U, F):
-        X, _, _ = cg_multishift(geom, params, U, q.sigma, phi)
-        fermion_force(geom, U, q.alpha, X, mode=0, out=F)
+        chain = dirac_links(U)
+        X, _, _ = cg_multishift(geom, params, chain[-1], q.sigma, phi)
+        if stout_levels > 0:
+            G = fermion_force(geom, chain[-1], q.alpha, X, mode=1)
+            F.copy_(stout_force(geom, chain, stout_rho, G, mode=0))
+        else:
+            fermion_force(geom, U, q.alpha, X, mode=0, out=F)
         del X
 
     def force(U, F):
