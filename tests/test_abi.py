@@ -184,3 +184,91 @@ def test_bench_traffic_record_is_tied_to_the_profiled_sources():
     assert bench.measured_traffic("not_the_profiled_kernel") is None
     got = bench.measured_traffic(rec["kernel_class"])
     assert got is None or got == rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def test_gauge_phase_stout_and_rational_validation(lq):
+    """The entry points of the rational, gauge-MD, U(1)-phase and stout rows
+    reject bad arguments on the host, before any device work; every call
+    below is invalid in exactly one respect."""
+    g = lq.Geometry((4, 4, 4, 4))
+    v = ctypes.c_void_p
+    nan, inf = float("nan"), float("inf")
+    E, W = lq.ERR_INVALID_ARG, lq.ERR_WORKSPACE
+
+    def rejected(name, *args, code=E, msg=None):
+        st = lq._fn(name)(*args)
+        assert st == code, (name, args, st, lq.last_error())
+        if msg is not None:
+            assert msg in lq.last_error(), (name, lq.last_error())
+
+    bad = lq.Geometry((4, 4, 3, 4)).c()         # odd extent
+
+    al = (ctypes.c_double * 2)(1.0, 2.0)
+    al_nan = (ctypes.c_double * 2)(1.0, nan)
+    rc = "lqcd_rational_combine"
+    rejected(rc, bad, 1, 2, 0.5, al, v(256), v(512), v(1 << 30), None, msg="L[2]")
+    rejected(rc, g.c(), 0, 2, 0.5, al, v(256), v(512), v(1 << 30), None, msg="nrhs")
+    rejected(rc, g.c(), 65, 2, 0.5, al, v(256), v(512), v(1 << 30), None, msg="nrhs")
+    rejected(rc, g.c(), 1, 0, 0.5, al, v(256), v(512), v(1 << 30), None, msg="nshift")
+    rejected(rc, g.c(), 1, 33, 0.5, al, v(256), v(512), v(1 << 30), None, msg="nshift")
+    rejected(rc, g.c(), 1, 2, 0.5, None, v(256), v(512), v(1 << 30), None, msg="alpha")
+    rejected(rc, g.c(), 1, 2, 0.5, al_nan, v(256), v(512), v(1 << 30), None, msg="alpha[1]")
+    rejected(rc, g.c(), 1, 2, inf, al, v(256), v(512), v(1 << 30), None, msg="alpha0")
+    rejected(rc, g.c(), 1, 2, 0.5, al, None, v(512), v(1 << 30), None, msg="b")
+    rejected(rc, g.c(), 1, 2, 0.5, al, v(256), v(520), v(1 << 30), None, msg="aligned")
+    # y inside X's nrhs*nshift vectors of 3*Vh complex doubles
+    rejected(rc, g.c(), 1, 2, 0.5, al, v(256), v(4096), v(4096 + 3 * g.Vh * 16), None,
+             msg="overlap")
+
+    ph = "lqcd_apply_u1_phases"
+    rejected(ph, g.c(), v(256), None, v(1024), None, msg="theta")
+    rejected(ph, g.c(), v(256), v(516), v(1024), None, msg="theta")
+    rejected(ph, g.c(), None, v(512), v(1024), None, msg="U64")
+    rejected(ph, g.c(), v(256), v(512), v(1032), None, msg="aligned")
+
+    sm = "lqcd_stout_smear"
+    rejected(sm, g.c(), v(256), nan, v(1024), None, msg="rho")
+    rejected(sm, g.c(), v(256), 0.1, v(256), None, msg="alias")
+    rejected(sm, g.c(), v(256), 0.1, None, None, msg="out")
+    rejected(sm, bad, v(256), 0.1, v(1024), None)
+
+    ws_need = lq._fn("lqcd_stout_workspace_bytes")(g.c())
+    assert ws_need == 2 * 8 * 9 * g.Vh * 16
+    assert lq._fn("lqcd_stout_workspace_bytes")(bad) == 0
+    sf = "lqcd_stout_force"
+    rejected(sf, g.c(), v(256), inf, v(512), 0, v(1024), v(2048), ws_need, None, msg="rho")
+    rejected(sf, g.c(), v(256), 0.1, v(512), 2, v(1024), v(2048), ws_need, None, msg="mode")
+    rejected(sf, g.c(), v(256), 0.1, v(512), 0, v(1024), v(2048), ws_need - 1, None, code=W)
+    rejected(sf, g.c(), v(256), 0.1, v(512), 1, v(256), v(2048), ws_need, None, msg="alias")
+    rejected(sf, g.c(), v(256), 0.1, v(512), 1, v(512), v(2048), ws_need, None, msg="alias")
+    rejected(sf, g.c(), v(256), 0.1, None, 0, v(1024), v(2048), ws_need, None, msg="G_smeared")
+    rejected(sf, g.c(), v(256), 0.1, v(512), 0, v(1024), None, ws_need, None, msg="ws")
+
+    gw = lq._fn("lqcd_gauge_workspace_bytes")(g.c())
+    assert gw >= (8 * g.Vh // 256 + 1) * 8 and lq._fn("lqcd_gauge_workspace_bytes")(bad) == 0
+    S = ctypes.c_double(0)
+    ga = "lqcd_gauge_action"
+    rejected(ga, g.c(), v(256), nan, -1 / 12, ctypes.byref(S), v(512), gw, None, msg="beta")
+    rejected(ga, g.c(), v(256), 5.0, inf, ctypes.byref(S), v(512), gw, None, msg="c1")
+    rejected(ga, g.c(), v(256), 5.0, -1 / 12, None, v(512), gw, None, msg="host")
+    rejected(ga, g.c(), v(256), 5.0, -1 / 12, ctypes.byref(S), v(512), gw - 1, None, code=W)
+    rejected(ga, g.c(), v(256), 5.0, -1 / 12, ctypes.byref(S), None, gw, None, msg="ws")
+
+    gf = "lqcd_gauge_force"
+    rejected(gf, g.c(), v(256), 5.0, -1 / 12, 2, v(1024), None, msg="accumulate")
+    rejected(gf, g.c(), v(256), 5.0, -1 / 12, 0, v(256), None, msg="alias")
+    rejected(gf, g.c(), v(256), inf, 0.0, 0, v(1024), None, msg="beta")
+    rejected(gf, g.c(), v(256), 5.0, 0.0, 0, None, None, msg="F")
+
+    rejected("lqcd_md_update_momenta", g.c(), v(256), nan, v(1024), None, msg="eps")
+    rejected("lqcd_md_update_momenta", g.c(), v(256), 0.1, v(256), None, msg="alias")
+    rejected("lqcd_md_update_momenta", g.c(), None, 0.1, v(1024), None, msg="F")
+    rejected("lqcd_md_update_links", g.c(), v(256), inf, v(1024), None, msg="eps")
+    rejected("lqcd_md_update_links", g.c(), v(256), 0.1, v(256), None, msg="alias")
+    rejected("lqcd_md_update_links", bad, v(256), 0.1, v(1024), None)
+
+    K = ctypes.c_double(0)
+    ke = "lqcd_kinetic_energy"
+    rejected(ke, g.c(), v(256), None, v(512), gw, None, msg="host")
+    rejected(ke, g.c(), v(256), ctypes.byref(K), v(512), gw - 1, None, code=W)
+    rejected(ke, g.c(), v(264), ctypes.byref(K), v(512), gw, None, msg="aligned")
