@@ -272,3 +272,79 @@ def test_gauge_phase_stout_and_rational_validation(lq):
     rejected(ke, g.c(), v(256), None, v(512), gw, None, msg="host")
     rejected(ke, g.c(), v(256), ctypes.byref(K), v(512), gw - 1, None, code=W)
     rejected(ke, g.c(), v(264), ctypes.byref(K), v(512), gw, None, msg="aligned")
+
+
+def test_pack_stencil_and_cg_validation(lq):
+    """Pack/convert/unpack, D_eo, the operator A and the single-shift solver
+    reject bad arguments on the host; every call is invalid in one respect."""
+    g = lq.Geometry((4, 4, 4, 4))
+    v = ctypes.c_void_p
+    E, W = lq.ERR_INVALID_ARG, lq.ERR_WORKSPACE
+    bad = lq.Geometry((4, 0, 4, 4)).c()
+
+    def rejected(name, *args, code=E, msg=None):
+        st = lq._fn(name)(*args)
+        assert st == code, (name, args, st, lq.last_error())
+        if msg is not None:
+            assert msg in lq.last_error(), (name, lq.last_error())
+
+    pl = "lqcd_pack_links"
+    rejected(pl, bad, v(256), 0, 0, v(1024), None, msg="L[1]")
+    rejected(pl, g.c(), v(256), 2, 0, v(1024), None)
+    rejected(pl, g.c(), v(256), 0, 9, v(1024), None)
+    rejected(pl, g.c(), None, 0, 0, v(1024), None, msg="U_nat")
+    rejected(pl, g.c(), v(256), 0, 0, v(1025), None, msg="aligned")
+    cl = "lqcd_convert_links"
+    rejected(cl, g.c(), v(256), 0, 0, v(256), 1, 1, None, msg="different")
+    rejected(cl, g.c(), v(256), 0, 0, v(1024), 1, 7, None)
+    rejected(cl, g.c(), v(256), 5, 0, v(1024), 1, 1, None)
+    rejected(cl, g.c(), v(256), 0, 0, None, 1, 1, None, msg="dst")
+    rejected("lqcd_unpack_links", g.c(), None, v(1024), None, msg="U_packed")
+    rejected("lqcd_unpack_links", bad, v(256), v(1024), None)
+    for name in ("lqcd_pack_spinor", "lqcd_unpack_spinor"):
+        rejected(name, g.c(), 2, 0, v(256), v(1024), 1, None, msg="parity")
+        rejected(name, g.c(), 0, 3, v(256), v(1024), 1, None)
+        rejected(name, g.c(), 0, 0, v(256), v(1024), 0, None)
+        rejected(name, g.c(), 0, 0, v(256), v(1024), 65, None)
+        rejected(name, g.c(), 0, 0, v(256), None, 1, None)
+
+    de = "lqcd_deo"
+    rejected(de, g.c(), 0, 0, v(256), v(512), v(512), 1, None, msg="alias")
+    rejected(de, g.c(), 0, 0, None, v(512), v(1024), 1, None)
+    rejected(de, g.c(), 0, 0, v(256), v(512), v(1024), 65, None)
+    rejected(de, g.c(), 1, 4, v(256), v(512), v(1024), 1, None)
+    rejected(de, bad, 0, 0, v(256), v(512), v(1024), 1, None)
+
+    aa = "lqcd_apply_A"
+    ok = (v(256), 0.1, 0.0, v(512), v(1024), v(2048), 1, None)
+    rejected(aa, g.c(), 0, 0, v(256), 0.1, 0.0, v(512), v(512), v(2048), 1, None,
+             msg="distinct")
+    rejected(aa, g.c(), 0, 0, v(256), 0.1, 0.0, v(512), v(1024), v(512), 1, None,
+             msg="distinct")
+    rejected(aa, g.c(), 0, 0, v(256), float("nan"), 0.0, v(512), v(1024), v(2048), 1, None,
+             msg="finite")
+    rejected(aa, g.c(), 0, 0, v(256), 0.1, float("nan"), v(512), v(1024), v(2048), 1, None,
+             msg="finite")
+    rejected(aa, g.c(), 0, 0, v(256), 0.1, 0.0, v(512), v(1024), None, 1, None, msg="tmp_odd")
+    rejected(aa, g.c(), 0, 0, *ok[:-2], 0, None)
+    rejected(aa, g.c(), 2, 0, *ok)
+
+    p = lq.solver_params(mass=0.1)
+    stats = (lq.SolveStats * 1)()
+    cg = "lqcd_cg"
+    big = 1 << 40
+    rejected(cg, g.c(), ctypes.byref(p), v(256), None, -0.5, v(512), v(1024), 1, stats,
+             v(4096), big, None, msg="sigma")
+    rejected(cg, g.c(), ctypes.byref(p), v(256), None, 0.0, v(512), v(512), 1, stats,
+             v(4096), big, None, msg="alias")
+    rejected(cg, g.c(), ctypes.byref(p), v(256), None, 0.0, v(512), v(1024), 1, None,
+             v(4096), big, None, msg="host")
+    rejected(cg, g.c(), ctypes.byref(p), v(256), v(264), 0.0, v(512), v(1024), 1, stats,
+             v(4096), big, None, msg="Uinner")
+    rejected(cg, g.c(), ctypes.byref(p), v(256), None, 0.0, v(512), v(1024), 1, stats,
+             v(4096), 64, None, code=W)
+    rejected(cg, g.c(), ctypes.byref(p), v(256), None, 0.0, v(512), v(1024), 1, stats,
+             None, big, None, code=W)
+    q = lq.solver_params(mass=0.1, tol=2.0)
+    rejected(cg, g.c(), ctypes.byref(q), v(256), None, 0.0, v(512), v(1024), 1, stats,
+             v(4096), big, None)
