@@ -231,3 +231,29 @@ def test_tuning_cache_file(lq, tmp_path, monkeypatch):
     assert len(path.read_text().splitlines()) == 2
     assert torch.equal(y1, y3)
     lq.finalize()
+
+
+def test_paper_lattice_shape_every_format_8rhs(lq):
+    """The paper's lattice shape 32^3 x 48 (Sec. 5; time the longest axis,
+    antiperiodic), Haar links, 8 right-hand sides with the tuned launch: D_oe
+    and D_eo in the FP64 and FP32 18-real and 12-real formats against the
+    oracle on every output site of every right-hand side."""
+    L = (32, 32, 32, 48)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 4801)
+    fe = synth.gaussian_even_source(L, 8, 4802)
+    fo = synth.gaussian_field(L, 8, 4803)
+    fo[:, synth.site_parity(L) == 0, :] = 0.0
+    ref_oe = np.stack([oracle.doe(L, U, fe[j]) for j in range(8)])
+    ref_eo = np.stack([oracle.deo(L, U, fo[j]) for j in range(8)])
+    U64 = lq.pack_links(g, cu(U))
+    del U
+    for prec, fmt, tol in ((lq.F64, lq.LINKS18, 1e-13), (lq.F64, lq.LINKS12, 1e-13),
+                           (lq.F32, lq.LINKS18, 1e-6), (lq.F32, lq.LINKS12, 1e-6)):
+        Ul = U64 if (prec, fmt) == (lq.F64, lq.LINKS18) else lq.convert_links(
+            g, U64, lq.F64, lq.LINKS18, prec, fmt)
+        got = host(lq.unpack_spinor(g, lq.doe(g, Ul, lq.pack_spinor(g, cu(fe), 0, prec)), 1))
+        assert H.max_rel(got, ref_oe) <= tol, ("D_oe", prec, fmt)
+        got = host(lq.unpack_spinor(g, lq.deo(g, Ul, lq.pack_spinor(g, cu(fo), 1, prec)), 0))
+        assert H.max_rel(got, ref_eo) <= tol, ("D_eo", prec, fmt)
+        del Ul, got

@@ -343,3 +343,22 @@ def test_inner_tol_factor_margin(lq):
                 assert oracle.true_residual(L, U, m, sg, b_nat[j], Xn[j, s_]) <= 1e-10
         its[f] = stats[0][0]["iters"]
     assert its[0.5] > its[1.0]
+
+
+def test_multishift_paper_lattice_shape_mixed(lq):
+    """The paper's lattice shape 32^3 x 48, Haar links, m = 0.02, 12 shifts in
+    [1e-4, 10], 2 right-hand sides, FP32 12-real inner with FP64 reliable
+    updates: every (rhs, shift) <= 1e-10 by the oracle's true residual."""
+    L = (32, 32, 32, 48)
+    m = 0.02
+    U = synth.links_haar(L, 4811)
+    g, U64, b_nat, b = setup(lq, L, U, 4812, 2)
+    sig = synth.rational_shifts(12)
+    p = lq.solver_params(mass=m, tol=1e-10, inner_prec=1, inner_fmt=1, reliable_interval=100)
+    X, st, stats = lq.cg_multishift(g, p, U64, sig, b)
+    assert st == 0
+    Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(2, len(sig), -1, 3)
+    for j in range(2):
+        for s, sg in enumerate(sig):
+            tr = oracle.true_residual(L, U, m, sg, b_nat[j], Xn[j, s])
+            assert tr <= 1e-10, (j, s, tr)
