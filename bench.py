@@ -591,6 +591,15 @@ def main():
     dsl["fp64_18_1rhs_32x4"] = dslash_entry(lq, torch, g32, U32, lq.F64, lq.LINKS18, 1,
                                             copy_gbs, "32^4, Gaussian 3x3 links (timing only)")
     del U32
+    # the paper's own lattice (32^3 x 48, Sec. 5), where its FP64 Dirac figures are quoted
+    gp = lq.Geometry((32, 32, 32, 48))
+    Up = lq.pack_links(gp, torch.randn(4, gp.V, 3, 3, dtype=torch.complex128, device="cuda"))
+    for name, fmt in (("fp64_18_1rhs_32x3x48", lq.LINKS18), ("fp64_12_1rhs_32x3x48", lq.LINKS12)):
+        Ul = Up if fmt == lq.LINKS18 else lq.convert_links(gp, Up, lq.F64, lq.LINKS18, lq.F64, fmt)
+        dsl[name] = dslash_entry(lq, torch, gp, Ul, lq.F64, fmt, 1, copy_gbs,
+                                 "32^3x48 (the paper's lattice), Gaussian 3x3 links (timing only)")
+        del Ul
+    del Up
     rhmc = traj = None
     if not args.no_rhmc:
         rhmc = rhmc_heatbath(lq, torch, g, U64, w["mass"], nrhs)
