@@ -348,3 +348,25 @@ def test_pack_stencil_and_cg_validation(lq):
     q = lq.solver_params(mass=0.1, tol=2.0)
     rejected(cg, g.c(), ctypes.byref(q), v(256), None, 0.0, v(512), v(1024), 1, stats,
              v(4096), big, None)
+
+
+def test_bench_algorithmic_bytes_per_site():
+    """The roofline's algorithmic bytes per output site of one D_oe: every link
+    once, the input spinor once, the output once.  A spinor site is the
+    paper's 48 B in FP64 (Sec. 3.1); 12-real links are 6 complex, and the
+    12-real + determinant format 7."""
+    import bench
+    gold = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_byte_counts.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, val = line.split()
+            gold[k] = int(val)
+    spin64 = gold["spinor_fp64_bytes_per_site"]
+    assert bench.dslash_bytes_per_site(0, 0, 1) == 8 * 18 * 8 + 2 * spin64 == 1248
+    assert bench.dslash_bytes_per_site(1, 0, 1) == 624
+    assert bench.dslash_bytes_per_site(1, 1, 1) == 432
+    assert bench.dslash_bytes_per_site(0, 1, 1) == 8 * 12 * 8 + 2 * spin64
+    for B in (1, 2, 4, 8):
+        assert bench.dslash_bytes_per_site(1, 1, B) == 384 + 48 * B
+        assert bench.dslash_bytes_per_site(1, 2, B) == 8 * 14 * 4 + 48 * B
+        assert bench.dslash_bytes_per_site(0, 1, B) == 768 + B * spin64 * 2
