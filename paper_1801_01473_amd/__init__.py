@@ -46,7 +46,7 @@ class LqcdError(RuntimeError):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it first (python -m paper_1801_01473_amd.build "
+        f"{LIB_PATH} is missing: build it first (python paper_1801_01473_amd/build.py "
         "or __graft_entry__.build()); there is no CPU fallback")
 
 _lib = ctypes.CDLL(LIB_PATH)
