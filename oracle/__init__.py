@@ -6,8 +6,13 @@ arrays are numpy complex128 in natural lexicographic layout (see the C file).
 
 Parity status: every function here is pinned in ``tests/test_oracle.py``
 (closed-form free-field spectrum, anti-Hermiticity, gauge covariance, dense
-LAPACK solves, exact derivatives and finite differences); ``rational_apply``
-in ``tests/test_rational.py`` (dense eigendecomposition of A).  The one convention
+LAPACK solves, exact derivatives and finite differences; ``true_residual``
+against the dense relative 2-norm and closed forms at x = 0 and on a
+free-field plane wave); ``rational_apply`` in ``tests/test_rational.py``
+(dense eigendecomposition of A); ``stout_smear`` / ``stout_force`` in
+``tests/test_stout.py`` (the single-link weak-field closed form, which fixes
+the sign and scale of rho, the rise of the plaquette, covariance, finite
+differences).  The one convention
 those pins cannot fix is the order of the staggered phases over the axes,
 eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}) with (x, y, z, t) = (0, 1, 2, 3):
 any ordering gives the same spectrum and symmetries, so that ordering is a

@@ -158,6 +158,57 @@ def test_operator_bounds():
     assert ev.max() <= m ** 2 + sig + 16 + 1e-12
 
 
+# ---------------------------------------------------------------- true residual
+
+@pytest.mark.parametrize("L", [(2, 2, 2, 2), (4, 4, 4, 4)])
+@pytest.mark.parametrize("sig", [0.0, 0.3])
+def test_true_residual_is_dense_relative_two_norm(L, sig):
+    """The residual every solver test is judged by (Eq. (2)): ||b - (A + sigma) x||_2
+    / ||b||_2 over even sites and colours.  A is assembled densely at sigma = 0
+    (the operator is pinned above by its spectrum, covariance and bounds) and
+    sigma is added here in numpy, so sigma's handling, the norm (not squared),
+    the division by ||b|| and the parity restriction are all checked."""
+    m = 0.07
+    U = synth.links_haar(L, 61)
+    A0 = H.dense_even_operator(L, lambda f: oracle.apply_A(L, U, m, 0.0, f))
+    As = A0 + sig * np.eye(A0.shape[0])
+    for seed in (62, 63):
+        b = synth.gaussian_even_source(L, 1, seed)[0] * 3.7
+        x = synth.gaussian_even_source(L, 1, seed + 10)[0] * 0.2
+        bv, xv = H.to_even_vector(L, b), H.to_even_vector(L, x)
+        ref = np.linalg.norm(bv - As @ xv) / np.linalg.norm(bv)
+        got = oracle.true_residual(L, U, m, sig, b, x)
+        assert abs(got - ref) <= 1e-14 * ref
+        # odd-site entries of the inputs are not part of the even-site vectors
+        b2, x2 = b.copy(), x.copy()
+        odd = ~H.even_mask(L)
+        b2[odd] = 5.0
+        x2[odd] = -2.0
+        assert abs(oracle.true_residual(L, U, m, sig, b2, x2) - ref) <= 1e-14 * ref
+    # near-solution: a dense LAPACK solve leaves a residual at rounding level
+    xs = np.linalg.solve(As, bv)
+    assert oracle.true_residual(L, U, m, sig, b, H.from_even_vector(L, xs)) <= 1e-13
+
+
+def test_true_residual_closed_forms():
+    """x = 0 gives exactly 1 whatever the scale of b; on the free field a plane
+    wave b is an eigenvector (eigenvalue lam = m^2 + sum sin^2 p), so x = c b
+    leaves the residual |1 - c (lam + sigma)| exactly."""
+    L = (4, 6, 4, 8)
+    m, sig = 0.3, 0.25
+    U = synth.links_unit(L)
+    b = synth.gaussian_even_source(L, 1, 64)[0]
+    zero = np.zeros_like(b)
+    for scale in (1e-3, 1.0, 42.0):
+        assert oracle.true_residual(L, U, m, sig, scale * b, zero) == pytest.approx(1.0, abs=1e-15)
+    p = [2 * np.pi / L[0], 0.0, 4 * np.pi / L[2], 3 * np.pi / L[3]]
+    f = H.plane_wave_even(L, p, np.array([1.0, 0.5j, -0.25]))
+    lam = m ** 2 + np.sum(np.sin(p) ** 2)
+    for c in (0.0, 0.5, 1.0 / (lam + sig), 2.0):
+        got = oracle.true_residual(L, U, m, sig, f, c * f)
+        assert abs(got - abs(1 - c * (lam + sig))) <= 1e-13
+
+
 # ---------------------------------------------------------------- solvers
 
 @pytest.mark.parametrize("L,gen", [((2, 2, 2, 2), "haar"), ((4, 4, 4, 4), "exp")])
