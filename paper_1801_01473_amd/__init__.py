@@ -230,43 +230,66 @@ def empty_spinor(geom: Geometry, n=1, prec=F64, device="cuda"):
     return torch.empty((n, 3, geom.Vh), dtype=_cdtype(prec), device=device)
 
 
+def _natural_links_arg(geom: Geometry, t, name):
+    _tensor(t, name)
+    if t.dtype != torch.complex128 or tuple(t.shape) != (4, geom.V, 3, 3):
+        raise ValueError(f"{name} must be complex128 [4][{geom.V}][3][3], "
+                         f"got {t.dtype} {tuple(t.shape)}")
+    _finish(t, name)
+
+
 def pack_links(geom: Geometry, U_nat: torch.Tensor, prec=F64, fmt=LINKS18, out=None):
-    if U_nat.dtype != torch.complex128 or tuple(U_nat.shape) != (4, geom.V, 3, 3):
-        raise ValueError("U_nat must be complex128 [4][V][3][3]")
+    _natural_links_arg(geom, U_nat, "U_nat")
+    if prec not in (F64, F32) or fmt not in (LINKS18, LINKS12, LINKS12D):
+        raise ValueError("unknown precision or link format")
     out = empty_links(geom, prec, fmt, U_nat.device) if out is None else out
+    _links_arg(geom, out, "out", prec, fmt)
     _check(_fn("lqcd_pack_links")(geom.c(), _ptr(U_nat), prec, fmt, _ptr(out), _stream()))
     return out
 
 
 def convert_links(geom: Geometry, src, src_prec, src_fmt, dst_prec, dst_fmt, out=None):
+    _links_arg(geom, src, "src", src_prec, src_fmt)
     out = empty_links(geom, dst_prec, dst_fmt, src.device) if out is None else out
+    _links_arg(geom, out, "out", dst_prec, dst_fmt)
     _check(_fn("lqcd_convert_links")(geom.c(), _ptr(src), src_prec, src_fmt, _ptr(out),
                                      dst_prec, dst_fmt, _stream()))
     return out
 
 
 def unpack_links(geom: Geometry, U_packed, out=None):
+    _u64_arg(geom, U_packed, "U_packed")
     out = torch.empty((4, geom.V, 3, 3), dtype=torch.complex128,
                       device=U_packed.device) if out is None else out
+    _natural_links_arg(geom, out, "out")
     _check(_fn("lqcd_unpack_links")(geom.c(), _ptr(U_packed), _ptr(out), _stream()))
     return out
 
 
 def pack_spinor(geom: Geometry, nat: torch.Tensor, parity: int, prec=F64, out=None):
-    nat = nat.reshape(-1, geom.V, 3)
+    _tensor(nat, "nat")
     if nat.dtype != torch.complex128:
         raise ValueError("natural fields must be complex128")
+    if nat.numel() == 0 or nat.numel() % (3 * geom.V):
+        raise ValueError(f"natural fields must be [n][{geom.V}][3], got {tuple(nat.shape)}")
+    nat = _finish(nat, "nat").reshape(-1, geom.V, 3)
     n = nat.shape[0]
     out = empty_spinor(geom, n, prec, nat.device) if out is None else out
+    _spinor_arg(geom, out, prec, "out", n)
     _check(_fn("lqcd_pack_spinor")(geom.c(), parity, prec, _ptr(nat), _ptr(out), n, _stream()))
     return out
 
 
 def unpack_spinor(geom: Geometry, packed: torch.Tensor, parity: int, out=None):
+    _tensor(packed, "packed")
     prec = F64 if packed.dtype == torch.complex128 else F32
-    n = packed.numel() // (3 * geom.Vh)
+    n = _spinor_arg(geom, packed, prec, "packed")
     out = torch.empty((n, geom.V, 3), dtype=torch.complex128,
                       device=packed.device) if out is None else out
+    _tensor(out, "out")
+    if out.dtype != torch.complex128 or out.numel() != n * geom.V * 3:
+        raise ValueError(f"out must be complex128 [{n}][{geom.V}][3]")
+    _finish(out, "out")
     _check(_fn("lqcd_unpack_spinor")(geom.c(), parity, prec, _ptr(packed), _ptr(out), n,
                                      _stream()))
     return out
@@ -280,10 +303,81 @@ def _fmt_of(U):
     return {9: LINKS18, 6: LINKS12, 7: LINKS12D}[int(U.shape[2])]
 
 
+# ---------------------------------------------------------------- argument checks
+# Every tensor handed to the library is checked here -- dtype, element count or
+# shape, contiguity -- and then its device, before any call into it, so that a
+# mismatch (say FP64 links with complex64 spinors) raises ValueError instead of
+# letting a kernel read or write past a buffer.
+
+def _tensor(t, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    return t
+
+
+def _finish(t, name):
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _gpu(*ts):
+    """Device check, after the dtype/size checks and before any allocation
+    (_ptr repeats it for every pointer passed)."""
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("tensor must live on the GPU")
+
+
+def _links_arg(geom: Geometry, U, name="U", prec=None, fmt=None):
+    """Packed links [2][4][NE][Vh]; returns (prec, fmt)."""
+    _tensor(U, name)
+    if U.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError(f"{name} must be complex128 or complex64 packed links, got {U.dtype}")
+    if U.dim() != 4 or tuple(U.shape[:2]) != (2, 4) or int(U.shape[3]) != geom.Vh \
+            or int(U.shape[2]) not in (9, 6, 7):
+        raise ValueError(f"{name} must be packed links [2][4][9|6|7][{geom.Vh}], "
+                         f"got {tuple(U.shape)}")
+    p, f = _prec_of(U), _fmt_of(U)
+    if prec is not None and p != prec:
+        raise ValueError(f"{name} must be {_cdtype(prec)}, got {U.dtype}")
+    if fmt is not None and f != fmt:
+        raise ValueError(f"{name} must have {_ne(fmt)} elements per link, got {int(U.shape[2])}")
+    _finish(U, name)
+    return p, f
+
+
+def _u64_arg(geom: Geometry, U, name="U64"):
+    _links_arg(geom, U, name, F64, LINKS18)
+
+
+def _spinor_arg(geom: Geometry, t, prec, name, n=None):
+    """Packed single-parity spinors [n][3][Vh] of precision prec; returns n."""
+    _tensor(t, name)
+    if t.dtype != _cdtype(prec):
+        raise ValueError(f"{name} must be {_cdtype(prec)} to match the links, got {t.dtype}")
+    per = 3 * geom.Vh
+    if t.numel() == 0 or t.numel() % per:
+        raise ValueError(f"{name} must hold a whole number of packed spinors of 3 x {geom.Vh} "
+                         f"entries, got {t.numel()} entries")
+    if n is not None and t.numel() != n * per:
+        raise ValueError(f"{name} must hold {n} packed spinors ({n * per} entries), "
+                         f"got {t.numel()}")
+    _finish(t, name)
+    return t.numel() // per
+
+
+def _real_links_out(geom: Geometry, t, name):
+    """An FP64 18-real packed link-shaped output (forces, momenta)."""
+    _links_arg(geom, t, name, F64, LINKS18)
+
+
 def doe(geom: Geometry, U, psi_even, out=None):
     """D_oe: packed even spinors [n][3][Vh] -> packed odd spinors."""
-    n = psi_even.numel() // (3 * geom.Vh)
+    prec, _ = _links_arg(geom, U)
+    n = _spinor_arg(geom, psi_even, prec, "psi_even")
     out = torch.empty_like(psi_even) if out is None else out
+    _spinor_arg(geom, out, prec, "out", n)
     _check(_fn("lqcd_doe")(geom.c(), _prec_of(U), _fmt_of(U), _ptr(U), _ptr(psi_even),
                            _ptr(out), n, _stream()))
     return out
@@ -291,8 +385,10 @@ def doe(geom: Geometry, U, psi_even, out=None):
 
 def deo(geom: Geometry, U, psi_odd, out=None):
     """D_eo: packed odd spinors -> packed even spinors."""
-    n = psi_odd.numel() // (3 * geom.Vh)
+    prec, _ = _links_arg(geom, U)
+    n = _spinor_arg(geom, psi_odd, prec, "psi_odd")
     out = torch.empty_like(psi_odd) if out is None else out
+    _spinor_arg(geom, out, prec, "out", n)
     _check(_fn("lqcd_deo")(geom.c(), _prec_of(U), _fmt_of(U), _ptr(U), _ptr(psi_odd),
                            _ptr(out), n, _stream()))
     return out
@@ -300,9 +396,12 @@ def deo(geom: Geometry, U, psi_odd, out=None):
 
 def apply_A(geom: Geometry, U, mass, sigma, x_even, out=None, tmp=None):
     """((m^2 + sigma) - D_eo D_oe) x on packed even spinors."""
-    n = x_even.numel() // (3 * geom.Vh)
+    prec, _ = _links_arg(geom, U)
+    n = _spinor_arg(geom, x_even, prec, "x_even")
     out = torch.empty_like(x_even) if out is None else out
     tmp = torch.empty_like(x_even) if tmp is None else tmp
+    _spinor_arg(geom, out, prec, "out", n)
+    _spinor_arg(geom, tmp, prec, "tmp", n)
     _check(_fn("lqcd_apply_A")(geom.c(), _prec_of(U), _fmt_of(U), _ptr(U), float(mass),
                                float(sigma), _ptr(x_even), _ptr(out), _ptr(tmp), n, _stream()))
     return out
@@ -346,8 +445,13 @@ def cg(geom: Geometry, params: SolverParams, U64, b, x=None, sigma=0.0, Uinner=N
     Returns (x, status, [stats per right-hand side]).  x holds the initial
     guess on entry when given.
     """
-    n = b.numel() // (3 * geom.Vh)
+    _u64_arg(geom, U64)
+    n = _spinor_arg(geom, b, F64, "b")
     x = torch.zeros_like(b) if x is None else x
+    _spinor_arg(geom, x, F64, "x", n)
+    if Uinner is not None:
+        _links_arg(geom, Uinner, "Uinner", params.inner_prec, params.inner_fmt)
+    _gpu(U64, b, x)
     ws_bytes = solver_workspace_bytes(geom, params, 1, n)
     ws = _workspace(ws_bytes, b.device)
     stats = (SolveStats * n)()
@@ -361,11 +465,16 @@ def cg(geom: Geometry, params: SolverParams, U64, b, x=None, sigma=0.0, Uinner=N
 def cg_multishift(geom: Geometry, params: SolverParams, U64, sigmas, b, x=None, Uinner=None,
                   check=True):
     """Multi-shift CG.  b: packed FP64 even [n][3][Vh]; returns x [n][nshift][3][Vh]."""
-    n = b.numel() // (3 * geom.Vh)
+    _u64_arg(geom, U64)
+    n = _spinor_arg(geom, b, F64, "b")
     sig = (ctypes.c_double * len(sigmas))(*[float(s) for s in sigmas])
     ns = len(sigmas)
     if x is None:
         x = torch.empty((n, ns, 3, geom.Vh), dtype=torch.complex128, device=b.device)
+    _spinor_arg(geom, x, F64, "x", n * ns)
+    if Uinner is not None:
+        _links_arg(geom, Uinner, "Uinner", params.inner_prec, params.inner_fmt)
+    _gpu(U64, b, x)
     ws_bytes = solver_workspace_bytes(geom, params, ns, n)
     ws = _workspace(ws_bytes, b.device)
     stats = (SolveStats * (n * ns))()
@@ -383,10 +492,17 @@ def fermion_force(geom: Geometry, U64, alpha, X, mode=0, out=None, accumulate=Fa
     mode 0: TA(U M) (su(3) force); mode 1: M^dag (raw gradient).  Output in the
     packed FP64 18-real link layout [2][4][9][Vh].
     """
+    _u64_arg(geom, U64)
     nshift = len(alpha)
-    npf = X.numel() // (nshift * 3 * geom.Vh)
+    if nshift < 1:
+        raise ValueError("need at least one shift coefficient")
+    nX = _spinor_arg(geom, X, F64, "X")
+    if nX % nshift:
+        raise ValueError(f"X must hold npf x {nshift} even vectors, got {nX}")
+    npf = nX // nshift
     al = (ctypes.c_double * nshift)(*[float(a) for a in alpha])
     out = empty_links(geom, F64, LINKS18, X.device) if out is None else out
+    _real_links_out(geom, out, "out")
     _check(_fn("lqcd_fermion_force")(geom.c(), _ptr(U64), npf, nshift, al, _ptr(X), int(mode),
                                      1 if accumulate else 0, _ptr(out), _stream()))
     return out
@@ -394,7 +510,9 @@ def fermion_force(geom: Geometry, U64, alpha, X, mode=0, out=None, accumulate=Fa
 
 def action(geom: Geometry, alpha0, alpha, phi, X) -> float:
     nshift = len(alpha)
-    npf = phi.numel() // (3 * geom.Vh)
+    npf = _spinor_arg(geom, phi, F64, "phi")
+    _spinor_arg(geom, X, F64, "X", npf * nshift)
+    _gpu(phi, X)
     al = (ctypes.c_double * nshift)(*[float(a) for a in alpha])
     nbytes = int(_fn("lqcd_action_workspace_bytes")(geom.c()))
     ws = _workspace(nbytes, phi.device)
@@ -408,10 +526,10 @@ def rational_combine(geom: Geometry, alpha0, alpha, b, X, out=None):
     """y_j = alpha0 b_j + sum_i alpha_i X_ji on the GPU (packed FP64 even
     vectors; b [n][3][Vh], X [n][nshift][3][Vh]); out may be b."""
     nshift = len(alpha)
-    n = b.numel() // (3 * geom.Vh)
-    if X.numel() != n * nshift * 3 * geom.Vh:
-        raise ValueError(f"X must hold {n} x {nshift} even vectors")
+    n = _spinor_arg(geom, b, F64, "b")
+    _spinor_arg(geom, X, F64, "X", n * nshift)
     out = torch.empty_like(b) if out is None else out
+    _spinor_arg(geom, out, F64, "out", n)
     al = (ctypes.c_double * nshift)(*[float(a) for a in alpha])
     _check(_fn("lqcd_rational_combine")(geom.c(), n, nshift, float(alpha0), al, _ptr(b),
                                         _ptr(X), _ptr(out), _stream()))
@@ -465,10 +583,13 @@ def apply_u1_phases(geom: Geometry, U64, theta, out=None):
     """Links u_mu(x) U_mu(x), u = exp(i theta_mu(x)), theta real [4][V] (natural
     order, FP64, on the device); packed FP64 18-real in and out.  Use 18-real
     formats for every precision with phased links (they are not SU(3))."""
+    _u64_arg(geom, U64)
+    _tensor(theta, "theta")
     if theta.dtype != torch.float64 or tuple(theta.shape) != (4, geom.V):
         raise ValueError("theta must be float64 [4][V]")
     theta = theta.contiguous()
     out = torch.empty_like(U64) if out is None else out
+    _u64_arg(geom, out, "out")
     _check(_fn("lqcd_apply_u1_phases")(geom.c(), _ptr(U64), _ptr(theta), _ptr(out), _stream()))
     return out
 
@@ -476,6 +597,7 @@ def apply_u1_phases(geom: Geometry, U64, theta, out=None):
 def stout_smear(geom: Geometry, U64, rho: float, levels: int = 1):
     """[U^(0), U^(1), ..., U^(levels)]: repeated stout smearing (packed FP64
     18-real); U^(0) is U64 itself."""
+    _u64_arg(geom, U64)
     out = [U64]
     for _ in range(levels):
         nxt = torch.empty_like(U64)
@@ -489,6 +611,10 @@ def stout_force(geom: Geometry, chain, rho: float, G_top, mode: int = 0):
     links chain[-1], e.g. fermion_force(..., mode=1)) down the smearing chain
     [U^(0), ..., U^(k)] of stout_smear; returns TA(U^(0) M) (mode 0) or the raw
     gradient M^dag with respect to U^(0) (mode 1)."""
+    for k, Uk in enumerate(chain):
+        _u64_arg(geom, Uk, f"chain[{k}]")
+    _real_links_out(geom, G_top, "G_top")
+    _gpu(G_top, *chain)
     nbytes = int(_fn("lqcd_stout_workspace_bytes")(geom.c()))
     ws = torch.empty(nbytes, dtype=torch.uint8, device=G_top.device)
     G = G_top
@@ -507,6 +633,8 @@ SYMANZIK_C1 = -1.0 / 12.0
 def gauge_action(geom: Geometry, U64, beta: float, c1: float = SYMANZIK_C1) -> float:
     """Tree-level Symanzik gauge action S_g (c1 = 0: Wilson) of packed FP64
     18-real links."""
+    _u64_arg(geom, U64)
+    _gpu(U64)
     ws = _workspace(int(_fn("lqcd_gauge_workspace_bytes")(geom.c())), U64.device)
     S = ctypes.c_double(0.0)
     _check(_fn("lqcd_gauge_action")(geom.c(), _ptr(U64), float(beta), float(c1), ctypes.byref(S),
@@ -517,7 +645,9 @@ def gauge_action(geom: Geometry, U64, beta: float, c1: float = SYMANZIK_C1) -> f
 def gauge_force(geom: Geometry, U64, beta: float, c1: float = SYMANZIK_C1, out=None,
                 accumulate=False):
     """F = TA(U M) of S_g, packed like the links; accumulate adds into out."""
+    _u64_arg(geom, U64)
     out = empty_links(geom, F64, LINKS18, U64.device) if out is None else out
+    _real_links_out(geom, out, "out")
     _check(_fn("lqcd_gauge_force")(geom.c(), _ptr(U64), float(beta), float(c1),
                                    1 if accumulate else 0, _ptr(out), _stream()))
     return out
@@ -525,18 +655,24 @@ def gauge_force(geom: Geometry, U64, beta: float, c1: float = SYMANZIK_C1, out=N
 
 def md_update_momenta(geom: Geometry, H, F, eps: float):
     """H <- H - i eps F in place."""
+    _real_links_out(geom, H, "H")
+    _real_links_out(geom, F, "F")
     _check(_fn("lqcd_md_update_momenta")(geom.c(), _ptr(F), float(eps), _ptr(H), _stream()))
     return H
 
 
 def md_update_links(geom: Geometry, U64, H, eps: float):
     """U <- exp(i eps H) U in place (re-orthonormalised to SU(3))."""
+    _u64_arg(geom, U64)
+    _real_links_out(geom, H, "H")
     _check(_fn("lqcd_md_update_links")(geom.c(), _ptr(H), float(eps), _ptr(U64), _stream()))
     return U64
 
 
 def kinetic_energy(geom: Geometry, H) -> float:
     """H^2 / 2 = half the sum over links of Tr H^2."""
+    _real_links_out(geom, H, "H")
+    _gpu(H)
     ws = _workspace(int(_fn("lqcd_gauge_workspace_bytes")(geom.c())), H.device)
     K = ctypes.c_double(0.0)
     _check(_fn("lqcd_kinetic_energy")(geom.c(), _ptr(H), ctypes.byref(K), _ptr(ws), ws.numel(),
