@@ -303,6 +303,22 @@ int lqcd_action(const lqcd_geom *g, int32_t npf, int32_t nshift, double alpha0,
                 void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * lqcd_action without a workspace argument and without any device allocation,
+ * for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * result as lqcd_action, bit for bit; the block partials live in a fixed 1 MiB
+ * device array of the library (one copy per device, held until the process
+ * ends), which covers every lattice the library accepts.  The first call on a
+ * device looks up that copy's address.  A lattice that would need more
+ * returns LQCD_ERR_WORKSPACE.  Every call on one device shares the array:
+ * calls that overlap on one device (other streams or host threads) race and
+ * must be serialised by the caller.  Synchronises the stream before returning.
+ */
+int lqcd_action_noalloc(const lqcd_geom *g, int32_t npf, int32_t nshift, double alpha0,
+                        const double *alpha, const void *phi, const void *X, double *S,
+                        void *stream);
+
+/*
  * Rational function of A applied to vectors, from the multi-shift solutions
  * (Sec. 2: the shifts of Eq. (2) are the poles of the rational approximation
  * used by RHMC):

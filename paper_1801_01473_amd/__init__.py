@@ -118,6 +118,7 @@ _SIGS = {
     "lqcd_action_workspace_bytes": (ctypes.c_size_t, [_gp]),
     "lqcd_action": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp,
                                    ctypes.c_size_t, _vp]),
+    "lqcd_action_noalloc": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp]),
     "lqcd_rational_combine": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _vp, _vp]),
     "lqcd_apply_u1_phases": (ctypes.c_int, [_gp, _vp, _vp, _vp, _vp]),
     "lqcd_stout_smear": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _vp]),
@@ -519,6 +520,21 @@ def action(geom: Geometry, alpha0, alpha, phi, X) -> float:
     S = ctypes.c_double(0.0)
     _check(_fn("lqcd_action")(geom.c(), npf, nshift, float(alpha0), al, _ptr(phi), _ptr(X),
                               ctypes.byref(S), _ptr(ws), ws.numel(), _stream()))
+    return float(S.value)
+
+
+def action_noalloc(geom: Geometry, alpha0, alpha, phi, X) -> float:
+    """``action`` through the entry point that allocates nothing (its partial
+    sums live in the library's fixed device array; concurrent calls on one
+    device race)."""
+    nshift = len(alpha)
+    npf = _spinor_arg(geom, phi, F64, "phi")
+    _spinor_arg(geom, X, F64, "X", npf * nshift)
+    _gpu(phi, X)
+    al = (ctypes.c_double * nshift)(*[float(a) for a in alpha])
+    S = ctypes.c_double(0.0)
+    _check(_fn("lqcd_action_noalloc")(geom.c(), npf, nshift, float(alpha0), al, _ptr(phi),
+                                      _ptr(X), ctypes.byref(S), _stream()))
     return float(S.value)
 
 

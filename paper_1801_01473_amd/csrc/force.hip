@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 #include "solver.h"
@@ -37,6 +38,19 @@ constexpr int kCombineBlock = 256;
 struct Alphas {
   double a[kMaxShift];
 };
+
+// Block partials and the final sum of lqcd_action_noalloc live here instead of
+// in a caller workspace: 1 MiB, i.e. ceil(Vh/256) + 32 doubles for any Vh up to
+// 33.5 million, more than the largest lattice the library accepts.  Each device
+// holds its own copy until the process ends.  Host code never passes this name
+// to a kernel (on the host it is only a stand-in for the symbol): it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kActionScratchDoubles = size_t(1) << 17;
+static __device__ __align__(256) double scratch[kActionScratchDoubles];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxScratchDevices] = {};
 
 __device__ __forceinline__ double quad_sum(double v) {
   v += __shfl_xor(v, 1, 64);
@@ -227,6 +241,28 @@ __global__ void __launch_bounds__(kCombineBlock) k_rational_combine(
   y[j * n + e] = make_double2(re, im);
 }
 
+// Device address of the current device's copy of `scratch`, looked up once per
+// device.  Returns NULL (error text set) if the device or the lookup fails.
+double* action_scratch_ptr() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) {
+    set_error("no usable current HIP device (device %d) for the action scratch array", dev);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_dev[dev];
+}
+
 int check_alpha(int32_t nshift, const double* alpha) {
   if (nshift < 1 || nshift > kMaxShift) {
     set_error("nshift = %d must be in [1, %d]", nshift, kMaxShift);
@@ -294,13 +330,16 @@ size_t lqcd_action_workspace_bytes(const lqcd_geom* g) {
   return (size_t((k.Vh + kActionBlock - 1) / kActionBlock) + 32) * sizeof(double);
 }
 
-int lqcd_action(const lqcd_geom* g, int32_t npf, int32_t nshift, double alpha0,
-                const double* alpha, const void* phi, const void* X, double* S, void* ws,
-                size_t ws_bytes, void* stream) {
-  clear_error();
+}  // extern "C"
+
+namespace lqcd {
+namespace {
+
+int check_action_args(const lqcd_geom* g, int32_t npf, int32_t nshift, double alpha0,
+                      const double* alpha, const void* phi, const void* X, const double* S) {
   int rc;
   if ((rc = check_geom(g)) || (rc = check_ptr(phi, "phi")) || (rc = check_ptr(X, "X")) ||
-      (rc = check_alpha(nshift, alpha)) || (rc = check_ptr(ws, "ws")))
+      (rc = check_alpha(nshift, alpha)))
     return rc;
   if (!S) {
     set_error("S must be a host pointer");
@@ -314,18 +353,19 @@ int lqcd_action(const lqcd_geom* g, int32_t npf, int32_t nshift, double alpha0,
     set_error("alpha0 is not finite");
     return LQCD_ERR_INVALID_ARG;
   }
-  const size_t need = lqcd_action_workspace_bytes(g);
-  if (ws_bytes < need) {
-    set_error("action workspace of %zu bytes is too small: %zu needed", ws_bytes, need);
-    return LQCD_ERR_WORKSPACE;
-  }
+  return LQCD_OK;
+}
+
+// The two reduction launches of the action into `part` (ceil(Vh/256) + 32
+// doubles of device memory), then the result to the host.
+int run_action(const lqcd_geom* g, int32_t npf, int32_t nshift, double alpha0,
+               const double* alpha, const void* phi, const void* X, double* S, double* part,
+               hipStream_t s) {
   const KGeom k = make_kgeom(g);
   Alphas al{};
   for (int i = 0; i < nshift; ++i) al.a[i] = alpha[i];
   const int nb = (k.Vh + kActionBlock - 1) / kActionBlock;
-  double* part = static_cast<double*>(ws);
   double* out = part + nb + 16;
-  const hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_action, dim3(nb), dim3(kActionBlock), 0, s, k.Vh, (const double2*)phi,
                      (const double2*)X, npf, nshift, alpha0, al, part);
   LQCD_LAUNCH_CHECK();
@@ -334,6 +374,45 @@ int lqcd_action(const lqcd_geom* g, int32_t npf, int32_t nshift, double alpha0,
   LQCD_HIP_TRY(hipMemcpyAsync(S, out, sizeof(double), hipMemcpyDeviceToHost, s));
   LQCD_HIP_TRY(hipStreamSynchronize(s));
   return LQCD_OK;
+}
+
+}  // namespace
+}  // namespace lqcd
+
+extern "C" {
+
+int lqcd_action(const lqcd_geom* g, int32_t npf, int32_t nshift, double alpha0,
+                const double* alpha, const void* phi, const void* X, double* S, void* ws,
+                size_t ws_bytes, void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_action_args(g, npf, nshift, alpha0, alpha, phi, X, S)) ||
+      (rc = check_ptr(ws, "ws")))
+    return rc;
+  const size_t need = lqcd_action_workspace_bytes(g);
+  if (ws_bytes < need) {
+    set_error("action workspace of %zu bytes is too small: %zu needed", ws_bytes, need);
+    return LQCD_ERR_WORKSPACE;
+  }
+  return run_action(g, npf, nshift, alpha0, alpha, phi, X, S, static_cast<double*>(ws),
+                    (hipStream_t)stream);
+}
+
+int lqcd_action_noalloc(const lqcd_geom* g, int32_t npf, int32_t nshift, double alpha0,
+                        const double* alpha, const void* phi, const void* X, double* S,
+                        void* stream) {
+  clear_error();
+  int rc;
+  if ((rc = check_action_args(g, npf, nshift, alpha0, alpha, phi, X, S))) return rc;
+  const size_t need = lqcd_action_workspace_bytes(g);
+  if (need > kActionScratchDoubles * sizeof(double)) {
+    set_error("lattice needs %zu bytes of action scratch, above the fixed %zu-byte array", need,
+              kActionScratchDoubles * sizeof(double));
+    return LQCD_ERR_WORKSPACE;
+  }
+  double* part = action_scratch_ptr();
+  if (!part) return LQCD_ERR_HIP;
+  return run_action(g, npf, nshift, alpha0, alpha, phi, X, S, part, (hipStream_t)stream);
 }
 
 int lqcd_rational_combine(const lqcd_geom* g, int32_t nrhs, int32_t nshift, double alpha0,

@@ -171,6 +171,16 @@ def test_force_and_action_validation(lq):
     a = lq._fn("lqcd_action")
     assert a(g.c(), 1, 2, 0.0, al, v(256), v(512), ctypes.byref(S), v(1024), 8,
              None) == lq.ERR_WORKSPACE
+    # the entry point without a workspace: same argument checks, nothing launched
+    n = lq._fn("lqcd_action_noalloc")
+    assert n(g.c(), 0, 2, 0.0, al, v(256), v(512), ctypes.byref(S), None) == lq.ERR_INVALID_ARG
+    assert n(g.c(), 1, 0, 0.0, al, v(256), v(512), ctypes.byref(S), None) == lq.ERR_INVALID_ARG
+    assert n(g.c(), 1, 2, 0.0, al, None, v(512), ctypes.byref(S), None) == lq.ERR_INVALID_ARG
+    assert n(g.c(), 1, 2, 0.0, al, v(256), v(520), ctypes.byref(S), None) == lq.ERR_INVALID_ARG
+    assert n(g.c(), 1, 2, float("nan"), al, v(256), v(512), ctypes.byref(S),
+             None) == lq.ERR_INVALID_ARG
+    assert n(g.c(), 1, 2, 0.0, al, v(256), v(512), None, None) == lq.ERR_INVALID_ARG
+    assert "S must be" in lq.last_error()
 
 
 def test_bench_traffic_record_is_tied_to_the_profiled_sources():
