@@ -357,13 +357,17 @@ def rhmc_trajectory_bench(lq, torch, g48, U48):
     return out
 
 
-def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, X0=None, budget_s=20.0):
+def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, gpu_shift_updates_per_rhs, X0=None,
+                 budget_s=20.0):
     """Oracle multi-shift CG timed on a bounded sample: a few iterations on one
-    right-hand side of the same lattice, scaled to the GPU run's iteration
-    count and number of right-hand sides.  Also times the oracle's D_oe on all
-    host threads and on one, and recomputes with the oracle the FP64 true
-    residual of the GPU's solutions for the first right-hand side (X0: natural
-    layout [nshift][V][3])."""
+    right-hand side of the same lattice with all shifts active and with the
+    base shift alone, which gives the oracle's cost per iteration and per
+    active shifted system; the estimate for the whole batch weights them with
+    the GPU run's iteration and active-shift counts (the oracle freezes
+    converged shifts the same way).  Also times the oracle's D_oe on all host
+    threads and on one, and recomputes with the oracle the FP64 true residual
+    of the GPU's solutions for the first right-hand side (X0: natural layout
+    [nshift][V][3])."""
     import numpy as np
     import oracle
     L = w["L"]
@@ -386,28 +390,63 @@ def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, X0=None, budget_s=20.0):
               for s, sg in enumerate(sig)]
         check = {"rhs": 0, "shifts": len(tr), "max_true_rel_residual": float(np.max(tr)),
                  "all_below_1e-10": bool(np.max(tr) <= 1e-10)}
-    t0 = time.time()
-    oracle.cg_multishift(L, U, w["mass"], sig, phi[0], tol=1e-10, max_iter=1, verify=False)
-    t1 = time.time() - t0
-    n = max(1, min(4, int(budget_s / max(t1, 1e-3))))
-    t0 = time.time()
-    _, _, (its, _), _ = oracle.cg_multishift(L, U, w["mass"], sig, phi[0], tol=1e-10,
-                                             max_iter=n, verify=False)
-    tn = time.time() - t0
-    per_iter = (tn - t1) / max(n - 1, 1) if n > 1 else t1
-    est_solve = per_iter * gpu_iters_per_rhs * w["nrhs"]
+
+    def per_iteration(sigmas, n):
+        t0 = time.time()
+        oracle.cg_multishift(L, U, w["mass"], sigmas, phi[0], tol=1e-10, max_iter=1,
+                             verify=False)
+        t1 = time.time() - t0
+        t0 = time.time()
+        oracle.cg_multishift(L, U, w["mass"], sigmas, phi[0], tol=1e-10, max_iter=n,
+                             verify=False)
+        tn = time.time() - t0
+        return (tn - t1) / (n - 1), t1
+
+    _, t1 = per_iteration(sig, 2)
+    n = max(2, min(5, int(budget_s / 2 / max(t1, 1e-3))))
+    it_all, _ = per_iteration(sig, n)
+    it_base, _ = per_iteration(sig[:1], n)
+    per_shift = max(it_all - it_base, 0.0) / max(len(sig) - 1, 1)
+    est_rhs = (gpu_iters_per_rhs * it_base
+               + max(gpu_shift_updates_per_rhs - gpu_iters_per_rhs, 0) * per_shift)
+    est_solve = est_rhs * w["nrhs"]
     value = w["nrhs"] * w["nshift"] / est_solve
     return {
         "value": value, "unit": "shift-solves/s", "cores": threads, "kind": "oracle",
-        "sample": (f"oracle FP64 multi-shift CG on 1 RHS x {w['nshift']} shifts of the same "
-                   f"{'x'.join(map(str, L))} lattice, {n} iterations ({per_iter:.2f} s/iter on "
-                   f"{threads} threads, {platform.processor() or platform.machine()}), scaled to the "
-                   f"GPU run's {gpu_iters_per_rhs} iterations per RHS x {w['nrhs']} RHS"),
-        "seconds_per_iteration": per_iter,
+        "sample": (f"estimate: oracle FP64 multi-shift CG on 1 RHS of the same "
+                   f"{'x'.join(map(str, L))} lattice, {n} iterations with all {w['nshift']} "
+                   f"shifts ({it_all:.3f} s/iter) and {n} with the base shift alone "
+                   f"({it_base:.3f} s/iter) on {threads} threads "
+                   f"({platform.processor() or platform.machine()}), weighted by the GPU run's "
+                   f"{gpu_iters_per_rhs} iterations and {gpu_shift_updates_per_rhs} active "
+                   f"shifted-system iterations per RHS, x {w['nrhs']} RHS"),
+        "seconds_per_iteration_all_shifts": it_all,
+        "seconds_per_iteration_base_only": it_base,
+        "seconds_per_active_shift_iteration": per_shift,
         "estimated_solve_s": est_solve,
         "doe_s": {"threads": threads, "all_threads": doe_all, "one_thread": doe_one},
         "oracle_true_residual_check": check,
     }
+
+
+def oracle_config3_solve():
+    """The oracle's whole multi-shift solve of the 32^4 single-RHS configuration
+    (links exp(0.5iH), m = 0.02, 12 shifts, tol 1e-10, verification and
+    refinement included), timed on every host thread: a measured CPU
+    time-to-solution next to the GPU's for the same systems."""
+    import numpy as np
+    import oracle
+    w = WORKLOADS["c3"]
+    U, phi, sig, _ = make_inputs(w)
+    threads = len(os.sched_getaffinity(0))
+    oracle.set_threads(threads)
+    t0 = time.time()
+    _, st, (its, ref), tr = oracle.cg_multishift(w["L"], U, w["mass"], sig, phi[0], tol=1e-10)
+    sec = time.time() - t0
+    log(f"oracle config 3 solve: {sec:.1f} s on {threads} threads ({its} iterations)")
+    return {"seconds": sec, "cores": threads, "status": st, "iters": its, "refine_iters": ref,
+            "max_true_rel_residual": float(np.max(tr)),
+            "what": "oracle FP64 multi-shift CG, 32^4, 1 RHS x 12 shifts, tol 1e-10, measured"}
 
 
 def main():
@@ -614,6 +653,9 @@ def main():
         "unit": "GB/s",
         "frac": kd["GBps"] / HBM_PEAK_GBS,
         "traffic": traffic,
+        "traffic_source": ("rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 per launch from "
+                           "profiles/dominant_kernel_traffic.json, taken with the stencil "
+                           "sources whose sha256 it records (null when they changed)"),
         "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
         "avg_launch_us": kd["avg_us"],
         "share_of_solve_kernel_time": kd["total_ms"] / sum(v["total_ms"] for v in kernels.values()),
@@ -623,8 +665,14 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         X0 = lq.unpack_spinor(g, state["X"][0], 0).cpu().numpy()
-        cpu = cpu_baseline(w, U, phi, sig, int(round(np.mean(iters))), X0=X0)
+        upd = (sum(row[0]["shift_updates_fp64"] + row[0]["shift_updates_fp32"] for row in stats)
+               / len(stats))
+        cpu = cpu_baseline(w, U, phi, sig, int(round(np.mean(iters))), int(round(upd)), X0=X0)
         del X0
+        if fp64 and fp64.get("config3_32x4_1rhs"):
+            fp64["config3_32x4_1rhs"]["oracle"] = oracle_config3_solve()
+            c3 = fp64["config3_32x4_1rhs"]
+            c3["speedup_mixed_vs_oracle"] = c3["oracle"]["seconds"] / c3["mixed"]["seconds"]
 
     mixed_solve = float(np.median(solve_times))
     out = {

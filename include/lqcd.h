@@ -231,7 +231,7 @@ size_t lqcd_solver_workspace_bytes(const lqcd_geom *g, const lqcd_solver_params 
  * whenever the iterated residual has fallen by reliable_delta since the last
  * update, or reliable_interval iterations have passed, or the iteration
  * believes it has converged, the FP32 correction is added into the FP64
- * solution and the residual is recomputed in FP64 (Sec. 6: the production
+ * solution and the residual is recomputed in FP64 (Sec. 5.4: the production
  * split, single precision for MD and double for the accept step).
  * Dot products, norms and the CG scalars are always FP64.  A mixed multi-shift
  * solve first iterates in FP64 until the base residual is below mixed_switch
@@ -382,7 +382,7 @@ int lqcd_stout_force(const lqcd_geom *g, const void *U64, double rho, const void
                      int32_t mode, void *out, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Gauge part of the molecular dynamics (Sec. 2, Sec. 5).  Links U64 and
+ * Gauge part of the molecular dynamics (Sec. 2, Sec. 4.3).  Links U64 and
  * momenta H use the packed FP64 18-real link layout [2][4][9][Vh] (complex);
  * gauge links carry no boundary sign or staggered phase.
  *
@@ -409,7 +409,7 @@ int lqcd_gauge_force(const lqcd_geom *g, const void *U64, double beta, double c1
                      int32_t accumulate, void *F, void *stream);
 
 /*
- * MD steps (Sec. 5: "new momenta", "new configuration").  With U' = i H U,
+ * MD steps (Sec. 4.3 and Alg. 2: "new momenta", "new configuration").  With U' = i H U,
  * H Hermitian traceless, and F the force above, H^2/2 + S is conserved by
  * H' = -i F:
  *   lqcd_md_update_momenta: H <- H - i eps F           (F must not alias H)

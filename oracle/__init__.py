@@ -320,7 +320,7 @@ def stout_force(L, U, rho: float, G_smeared, mode: int = 0) -> np.ndarray:
 
 
 def md_momenta(H, F, eps: float) -> np.ndarray:
-    """Momentum step of the MD (Sec. 5, "new momenta"): with U' = i H U and the
+    """Momentum step of the MD (Sec. 4.3 and Alg. 2, "new momenta"): with U' = i H U and the
     force F = TA(U M) of ``force`` / ``gauge_force`` (dS/deps = sum Tr[T F]
     for U -> exp(eps T) U), energy conservation of H^2/2 + S gives
     H' = -i F, so H <- H - i eps F.  Natural [4][V][3][3]."""

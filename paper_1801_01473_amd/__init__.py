@@ -702,7 +702,7 @@ OMELYAN_LAMBDA = 0.1931833275037836
 def md_integrate(geom: Geometry, U64, H, tau: float, nsteps: int, force,
                  integrator: str = "omelyan", lam: float = OMELYAN_LAMBDA):
     """Integrate U' = i H U, H' = -i F(U) from 0 to tau in nsteps steps, in
-    place (Sec. 5: force, new momenta, new configuration).  force(U64, F)
+    place (Sec. 4.3, Alg. 2: force, new momenta, new configuration).  force(U64, F)
     writes the total force into F.  "leapfrog": kick eps/2, (drift eps,
     kick eps) ..., last kick eps/2; "omelyan": the second-order minimum-norm
     scheme kick lam eps, drift eps/2, kick (1 - 2 lam) eps, drift eps/2,
@@ -783,7 +783,7 @@ def rhmc_trajectory(geom: Geometry, params: SolverParams, U64, beta: float, appr
                     approx_quarter, xi, H, u: float, tau: float = 1.0, nsteps: int = 10,
                     c1: float = SYMANZIK_C1, integrator: str = "omelyan",
                     gauge_substeps: int = 1, stout_rho: float = 0.0, stout_levels: int = 0):
-    """One RHMC trajectory (Sec. 2, Sec. 5) for one staggered field with the
+    """One RHMC trajectory (Sec. 2, Sec. 4.3) for one staggered field with the
     pseudofermion action phi^dag A^(-1/4) phi (Eq. (1)):
       heatbath phi = r_{1/8}(A) xi; H_0 = H^2/2 + S_g + S_f;
       MD over tau with the gauge + fermion force (the fermion force from a

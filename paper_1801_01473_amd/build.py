@@ -4,11 +4,21 @@ Every source under ``csrc/`` is built for gfx950 only.  Object files go to
 ``_build/`` (git-ignored) and are rebuilt when a source or header changes;
 ``force=True`` rebuilds everything.  Packed FP32 instructions are disabled
 (``-packed-fp32-ops``) for every device compile.
+
+Every device compile also asks the compiler for its per-kernel resource
+report (``-Rpass-analysis=kernel-resource-usage``).  The build fails if any
+kernel uses private scratch memory or needs a dynamic stack: a kernel that
+spills to memory runs several times slower, and scratch traffic is invisible
+to the bandwidth accounting.  Register spills that stay in registers (VGPRs
+parked in AGPRs, SGPRs in VGPR lanes; the report then shows spills with zero
+scratch) are allowed.  The parsed report (kernel, VGPRs, AGPRs, scratch,
+spills, occupancy) is written next to the objects.
 """
 from __future__ import annotations
 
 import glob
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -28,7 +38,35 @@ DEVICE_FLAGS = [
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    "-Rpass-analysis=kernel-resource-usage",
 ]
+
+_REMARK = re.compile(r"remark:\s+(Function Name|ScratchSize \[bytes/lane\]|VGPRs|AGPRs|"
+                     r"SGPRs Spill|VGPRs Spill|Dynamic Stack|Occupancy \[waves/SIMD\]):"
+                     r"\s+(\S+)")
+
+
+def resource_usage(compiler_output: str):
+    """Per-kernel records {name, VGPRs, AGPRs, scratch, sgpr_spill,
+    vgpr_spill, dynamic_stack, occupancy} from the compiler's resource
+    remarks, in the order the compiler printed them."""
+    recs = []
+    keys = {"ScratchSize [bytes/lane]": "scratch", "SGPRs Spill": "sgpr_spill",
+            "VGPRs Spill": "vgpr_spill", "Dynamic Stack": "dynamic_stack",
+            "Occupancy [waves/SIMD]": "occupancy", "VGPRs": "VGPRs", "AGPRs": "AGPRs"}
+    for key, val in _REMARK.findall(compiler_output):
+        if key == "Function Name":
+            recs.append({"name": val})
+        elif recs:
+            recs[-1][keys[key]] = val
+    return recs
+
+
+def resource_violations(recs):
+    """Kernels that use scratch memory (spills to memory included) or need a
+    dynamic stack."""
+    return [r for r in recs
+            if r.get("scratch", "0") != "0" or r.get("dynamic_stack", "False") != "False"]
 
 
 def _headers():
@@ -42,6 +80,16 @@ def _compile(src: str, obj: str) -> None:
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError(f"hipcc failed for {os.path.basename(src)}")
+    recs = resource_usage(res.stderr)
+    with open(obj + ".resources.txt", "w") as f:
+        for r in recs:
+            f.write(" ".join(f"{k}={v}" for k, v in r.items()) + "\n")
+    bad = resource_violations(recs)
+    if bad:
+        os.remove(obj)
+        lines = "\n".join(" ".join(f"{k}={v}" for k, v in r.items()) for r in bad)
+        raise RuntimeError(f"{os.path.basename(src)}: kernels with scratch memory or a dynamic "
+                           f"stack:\n{lines}")
 
 
 def build(force: bool = False, verbose: bool = True) -> str:

@@ -1,8 +1,8 @@
-// Gauge part of the molecular dynamics (Sec. 2 and Sec. 5): the tree-level
+// Gauge part of the molecular dynamics (Sec. 2 and Sec. 4.3): the tree-level
 // Symanzik action (1x1 plaquettes and 1x2 rectangles of the links), its
 // force, the momentum and link steps of the integrator and the kinetic
 // energy.  FP64 throughout (the accept/reject test compares energies in
-// double precision, Sec. 6).
+// double precision, Sec. 5.4).
 //
 // Links and momenta use the packed 18-real FP64 link layout
 // [parity][mu][9][Vh] (complex), the layout of LQCD_LINKS18 links, so the

@@ -27,7 +27,7 @@
 // 12-real) and accumulates each shift's solution in an FP32 partial sum;
 // every reliable_interval iterations (and at convergence) those sums are
 // added into the FP64 solutions and the base residual is recomputed in FP64
-// with FP64 links (Sec. 6: floating point for the molecular dynamics, double
+// with FP64 links (Sec. 5.4: floating point for the molecular dynamics, double
 // precision for the accept/reject step).  After the base system converges the
 // FP64 true residual of every (right-hand side, shift) is computed, and the
 // ones above tol are refined together as independent systems by CG started

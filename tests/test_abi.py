@@ -380,3 +380,63 @@ def test_bench_algorithmic_bytes_per_site():
         assert bench.dslash_bytes_per_site(1, 1, B) == 384 + 48 * B
         assert bench.dslash_bytes_per_site(1, 2, B) == 8 * 14 * 4 + 48 * B
         assert bench.dslash_bytes_per_site(0, 1, B) == 768 + B * spin64 * 2
+
+
+def _builder():
+    import importlib.util
+    path = os.path.join(ROOT, "paper_1801_01473_amd", "build.py")
+    spec = importlib.util.spec_from_file_location("_lqcd_build_t", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_build_resource_guard_parses_and_flags():
+    """The build's guard reads the compiler's per-kernel resource remarks and
+    flags a kernel with scratch memory (a spill to memory) or a dynamic stack;
+    register spills kept in registers (zero scratch) pass."""
+    b = _builder()
+    text = "\n".join([
+        "x.hip:1:1: remark: Function Name: k_good [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:1:1: remark:     VGPRs: 128 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:1:1: remark:     Dynamic Stack: False [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:1:1: remark:     SGPRs Spill: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:1:1: remark:     VGPRs Spill: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark: Function Name: k_spill [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark:     VGPRs: 512 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark:     ScratchSize [bytes/lane]: 96 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark:     Dynamic Stack: False [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark:     SGPRs Spill: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark:     VGPRs Spill: 24 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:19:1: remark: Function Name: k_agpr [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:19:1: remark:     VGPRs: 256 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:19:1: remark:     AGPRs: 90 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:19:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:19:1: remark:     Dynamic Stack: False [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:19:1: remark:     VGPRs Spill: 36 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:29:1: remark: Function Name: k_stack [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:29:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:29:1: remark:     Dynamic Stack: True [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    recs = b.resource_usage(text)
+    assert [r["name"] for r in recs] == ["k_good", "k_spill", "k_agpr", "k_stack"]
+    assert recs[1]["vgpr_spill"] == "24" and recs[1]["scratch"] == "96"
+    assert [r["name"] for r in b.resource_violations(recs)] == ["k_spill", "k_stack"]
+    assert "-Rpass-analysis=kernel-resource-usage" in b.DEVICE_FLAGS
+
+
+def test_built_kernels_use_no_scratch():
+    """Every kernel of the last build: no scratch, no spills, no dynamic stack
+    (the reports the build writes beside its objects)."""
+    import glob
+    reports = glob.glob(os.path.join(ROOT, "_build", "lqcd", "*.o.resources.txt"))
+    if not reports:
+        pytest.skip("no build reports (library not built in this tree)")
+    b = _builder()
+    n = 0
+    for path in reports:
+        recs = [dict(kv.split("=", 1) for kv in line.split()) for line in open(path) if line.strip()]
+        n += len(recs)
+        assert not b.resource_violations(recs), path
+    assert n > 100

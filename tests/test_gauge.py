@@ -1,4 +1,4 @@
-"""Oracle pins for the gauge part of the MD (Sec. 2, Sec. 5): the tree-level
+"""Oracle pins for the gauge part of the MD (Sec. 2, Sec. 4.3): the tree-level
 Symanzik action, its force and the momentum / link steps.
 
 Closed forms: zero action and force on unit links; with a single non-unit

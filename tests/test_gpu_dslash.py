@@ -202,6 +202,31 @@ def test_every_launch_configuration(lq, cfg, prec, fmt, tol, monkeypatch):
     assert H.max_rel(got, ref) <= tol
 
 
+@pytest.mark.parametrize("cfg", ["256,8,1,6,1,0,0,0,0,0,1", "256,8,1,6,1,0,0,0,0,6,1",
+                                 "128,8,1,6,1,0,0,1,0,4,1", "256,8,1,6,1,0,0,0,1,3,1",
+                                 "64,4,0,6,0,0,1,0,0,2,0", "256,8,1,6,1,2,0,0,0,12,1",
+                                 "128,2,1,6,1,0,1,0,1,12,1"])
+@pytest.mark.parametrize("prec,fmt,tol", [(0, 1, 1e-13), (1, 1, 1e-6)])
+def test_six_slice_tiles(lq, cfg, prec, fmt, tol, monkeypatch):
+    """(y, z) tiles of six z slices (the tile the tuner picks on 48^4) with
+    every row count that divides Ly, each schedule, RHS block 8 over 7
+    right-hand sides, on a lattice whose site count is not a multiple of the
+    workgroup: D_oe and D_eo against the oracle."""
+    monkeypatch.setenv("LQCD_DSLASH_CFG", cfg)
+    L = (6, 12, 12, 6)
+    g = lq.Geometry(L)
+    U = _links(L, "haar", 61)
+    f = synth.gaussian_field(L, 7, 62)
+    Up = lq.pack_links(g, cu(U), prec, fmt)
+    fr = f.astype(np.complex64).astype(np.complex128) if prec == 1 else f
+    got = host(lq.unpack_spinor(g, lq.doe(g, Up, lq.pack_spinor(g, cu(f), 0, prec)), 1))
+    ref = np.stack([oracle.doe(L, U, fr[j]) for j in range(7)])
+    assert H.max_rel(got, ref) <= tol
+    got = host(lq.unpack_spinor(g, lq.deo(g, Up, lq.pack_spinor(g, cu(f), 1, prec)), 0))
+    ref = np.stack([oracle.deo(L, U, fr[j]) for j in range(7)])
+    assert H.max_rel(got, ref) <= tol
+
+
 def test_tuning_cache_file(lq, tmp_path, monkeypatch):
     """LQCD_TUNE_CACHE: a tuned shape is appended to the file; a valid entry
     for the key is used without tuning again (and, every launch variant

@@ -127,8 +127,9 @@ def test_fermion_action_gradcheck(lq):
 
 def test_force_config5_32(lq):
     """32^4, exp(0.5iH), 12 shifts, 4 pseudofermions: GPU solves to 1e-12,
-    then the GPU force equals the oracle force on the same X, and its
-    projection matches central differences along 4 su(3) directions."""
+    then the GPU force equals the oracle force on the same X (all 4 x 12
+    (pseudofermion, shift) pairs, both output modes), and its projection
+    matches central differences (eps = 1e-5) along 16 random su(3) directions."""
     L = (32, 32, 32, 32)
     g = lq.Geometry(L)
     m = 0.02
@@ -139,13 +140,15 @@ def test_force_config5_32(lq):
     S0, X, U64 = _gpu_action(lq, g, U, phi_p, m, sig, al, tol=1e-12)
     Ug = cu(U)
     F = lq.fermion_force(g, U64, al, X, mode=0)
-    # oracle force on the first pseudofermion's first 4 solutions (host time bound)
-    X1 = host(lq.unpack_spinor(g, X[0, :4].contiguous(), 0)).reshape(1, 4, -1, 3)
-    F1 = lq.fermion_force(g, U64, al[:4], X[0:1, :4].contiguous(), mode=0)
-    ref = oracle.force(L, U, al[:4], X1, mode=0)
-    assert H.max_rel(host(lq.unpack_links(g, F1)), ref) <= 1e-12
+    Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(4, 12, -1, 3)
+    for mode in (0, 1):
+        Fm = F if mode == 0 else lq.fermion_force(g, U64, al, X, mode=1)
+        ref = oracle.force(L, U, al, Xn, mode=mode)
+        assert H.max_rel(host(lq.unpack_links(g, Fm)), ref) <= 1e-12, mode
+        del ref
+    del Xn
     Fn = host(lq.unpack_links(g, F))
-    C = synth.su3_algebra_coeffs(L, 4, 306)
+    C = synth.su3_algebra_coeffs(L, 16, 306)
     eps = 1e-5
     for d in range(C.shape[0]):
         T = synth.su3_from_coeffs(C[d])
@@ -153,6 +156,7 @@ def test_force_config5_32(lq):
         Sp = _gpu_action(lq, g, torch.matmul(cu(synth.expi_coeffs(C[d], eps)), Ug), phi_p, m, sig, al, 1e-12)[0]
         Sm = _gpu_action(lq, g, torch.matmul(cu(synth.expi_coeffs(C[d], -eps)), Ug), phi_p, m, sig, al, 1e-12)[0]
         fd = (Sp - Sm) / (2 * eps)
+        print(f"config 5 direction {d}: fd {fd:.10e} analytic {ana:.10e}", flush=True)
         assert abs(fd - ana) <= 1e-6 * abs(ana), (d, fd, ana)
 
 

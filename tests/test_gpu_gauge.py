@@ -148,7 +148,9 @@ def test_rhmc_trajectory_reversible_and_conserving(lq):
     for n in (8, 16):
         U, Hp = U0.clone(), H0.clone()
         r = lq.rhmc_trajectory(g, p, U, beta, e8, q4, xi, Hp, u=0.0, tau=0.5, nsteps=n)
-        assert r["accepted"] == (r["dH"] <= 0 or 0.0 < np.exp(-r["dH"]))
+        # u = 0 accepts every finite dH: the links keep the evolved values
+        assert np.isfinite(r["dH"]) and r["accepted"]
+        assert (U - U0).abs().max().item() > 1e-3
         assert r["force_evaluations"] == 2 * n + 1
         dH.append(r["dH"])
     assert 2.5 < dH[0] / dH[1] < 6.0  # O(eps^2)
@@ -165,6 +167,34 @@ def test_rhmc_trajectory_reversible_and_conserving(lq):
     Hp.neg_()
     lq.md_integrate(g, U, Hp, 0.5, 4, force)
     assert (U - U0).abs().max().item() <= 1e-9
+
+
+def test_rhmc_trajectory_reject_restores_links(lq):
+    """A coarse trajectory (one Omelyan step over tau = 1) raises H, and with
+    u just below 1 the accept/reject step rejects it (exp(-dH) < u): the links
+    come back bit for bit.  A finer trajectory (16 steps, dH = O(10), so that
+    exp(-dH) > 0) with u = 0 is accepted and leaves the evolved links."""
+    L = (8, 8, 8, 8)
+    g = lq.Geometry(L)
+    beta, m = 2.0, 0.1
+    lo, hi = lq.spectral_bounds(m)
+    e8 = lq.minimax(0.125, lo, hi, 10)
+    q4 = lq.minimax(-0.25, lo, hi, 10)
+    p = lq.solver_params(mass=m, tol=1e-12)
+    U0 = lq.pack_links(g, cu(synth.links_exp(L, 0.3, 516)))
+    H0 = lq.pack_links(g, cu(synth.momenta(L, 517)))
+    xi = lq.pack_spinor(g, cu(synth.gaussian_even_source(L, 1, 518)), 0)
+    u_hi = float(np.nextafter(1.0, 0.0))
+    U, Hp = U0.clone(), H0.clone()
+    r = lq.rhmc_trajectory(g, p, U, beta, e8, q4, xi, Hp, u=u_hi, tau=1.0, nsteps=1)
+    assert r["dH"] > 1e-6, r["dH"]
+    assert not r["accepted"]
+    assert torch.equal(U, U0)
+    U, Hp = U0.clone(), H0.clone()
+    r2 = lq.rhmc_trajectory(g, p, U, beta, e8, q4, xi, Hp, u=0.0, tau=1.0, nsteps=16)
+    assert abs(r2["dH"]) < 100.0 < r["dH"], (r2["dH"], r["dH"])
+    assert r2["accepted"]
+    assert not torch.equal(U, U0)
 
 
 def test_gauge_force_is_derivative_at_workload_size(lq):

@@ -162,6 +162,28 @@ def test_not_converged_reports_stats(lq):
     assert "true residual" in lq.last_error()
 
 
+@pytest.mark.parametrize("mode", [MODES[0], MODES[1]])
+def test_nan_source_returns_numeric(lq, mode):
+    """A NaN in one element of the second of two right-hand sides: the device
+    flags stop the solve, no refinement runs, and both solvers return
+    LQCD_ERR_NUMERIC with that system reported as not converged."""
+    L = (4, 4, 4, 4)
+    U = synth.links_haar(L, 108)
+    g, U64, b_nat, b = setup(lq, L, U, 208, nrhs=2)
+    b[1, 2, 5] = complex(float("nan"), 0.0)
+    p = lq.solver_params(mass=0.1, tol=1e-10, **mode)
+    x, st, stats = lq.cg(g, p, U64, b, check=False)
+    assert st == lq.ERR_NUMERIC, lq.status_string(st)
+    assert "non-finite" in lq.last_error()
+    assert stats[1]["converged"] == 0 and stats[1]["refine_iters"] == 0
+    X, st, stats = lq.cg_multishift(g, p, U64, [0.0, 0.5, 2.0], b, check=False)
+    assert st == lq.ERR_NUMERIC, lq.status_string(st)
+    assert all(s["converged"] == 0 and s["refine_iters"] == 0 for s in stats[1])
+    with pytest.raises(lq.LqcdError) as e:
+        lq.cg_multishift(g, p, U64, [0.0, 0.5], b)
+    assert e.value.status == lq.ERR_NUMERIC
+
+
 def test_cg_initial_guess(lq):
     L = (4, 4, 4, 4)
     U = synth.links_exp(L, 0.3, 101)
