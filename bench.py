@@ -305,35 +305,47 @@ def rhmc_heatbath(lq, torch, g, U64, mass, nrhs, degree=14, seed=205):
 
 
 def rhmc_trajectory_bench(lq, torch, g48, U48):
-    """RHMC trajectories (heatbath, tau = 1 of Omelyan steps with gauge +
-    fermion force, accept/reject) on a 16^4 lattice (links exp(0.3 i H),
-    beta = 2.0, m = 0.1, one pseudofermion, degree-12 rational approximations,
-    mixed-precision solves) at 20 and 40 steps: the time of one trajectory and
-    dH(20) / dH(40), which is ~4 for the second-order scheme.  Then the
-    tree-level Symanzik gauge force kernel alone on the workload lattice: 85
-    SU(3) products (198 flops each) per link, against the FP64 vector peak."""
+    """RHMC trajectories on a 16^4 lattice (beta = 4.0, m = 0.1, one
+    pseudofermion, degree-12 rational approximations, mixed-precision solves).
+    The start (links exp(0.3 i H)) is far from equilibrium, so it is first
+    thermalised by 40 pure-gauge MD trajectories (tau = 1, 10 Omelyan steps,
+    fresh momenta, no accept/reject: thermalisation only, not part of a
+    Markov chain).  Then full trajectories (heatbath, tau = 1 of gauge +
+    fermion force, accept/reject with u = 0.5) at 20 and 40 Omelyan steps
+    (dH(20) / dH(40) ~ 4 for the second-order scheme) and the multi-step
+    scheme (10 outer fermion steps, 4 gauge substeps each): time, dH and the
+    accept decision.  Then the tree-level Symanzik gauge force kernel alone on
+    the workload lattice: 85 SU(3) products (198 flops each) per link, against
+    the FP64 vector peak."""
     import synth
     L = (16, 16, 16, 16)
     g = lq.Geometry(L)
-    beta, m = 2.0, 0.1
+    beta, m = 4.0, 0.1
     lo, hi = lq.spectral_bounds(m)
     e8 = lq.minimax(0.125, lo, hi, 12)
     q4 = lq.minimax(-0.25, lo, hi, 12)
     p = lq.solver_params(mass=m, tol=1e-10, inner_prec=lq.F32, inner_fmt=lq.LINKS12,
                          use_graph=1)
     U0 = lq.pack_links(g, torch.from_numpy(synth.links_exp(L, 0.3, 601)).to("cuda"))
+    gforce = lambda Ux, F: lq.gauge_force(g, Ux, beta, out=F)
+    t0 = time.time()
+    for k in range(40):
+        Hk = lq.pack_links(g, torch.from_numpy(synth.momenta(L, 700 + k)).to("cuda"))
+        lq.md_integrate(g, U0, Hk, 1.0, 10, gforce)
+    torch.cuda.synchronize()
+    therm_s = time.time() - t0
     H0 = lq.pack_links(g, torch.from_numpy(synth.momenta(L, 602)).to("cuda"))
     xi = lq.pack_spinor(g, torch.from_numpy(synth.gaussian_even_source(L, 1, 603)).to("cuda"), 0)
     lq.rhmc_trajectory(g, p, U0.clone(), beta, e8, q4, xi, H0.clone(), u=0.5, tau=0.05,
                        nsteps=1)  # tuning and graph capture at this shape
     res = {}
-    for n in (20, 40):
+    for key, n, sub in ((20, 20, 1), (40, 40, 1), ("nested", 10, 4)):
         torch.cuda.synchronize()
         t0 = time.time()
         r = lq.rhmc_trajectory(g, p, U0.clone(), beta, e8, q4, xi, H0.clone(), u=0.5, tau=1.0,
-                               nsteps=n)
+                               nsteps=n, gauge_substeps=sub)
         torch.cuda.synchronize()
-        res[n] = (time.time() - t0, r)
+        res[key] = (time.time() - t0, r)
     F = lq.empty_links(g48, lq.F64, lq.LINKS18, "cuda")
     ms = event_time_ms(lambda: lq.gauge_force(g48, U48, 5.0, out=F), 10)
     flops = 8 * g48.Vh * 85 * 198
@@ -343,17 +355,23 @@ def rhmc_trajectory_bench(lq, torch, g48, U48):
     ms_chain = event_time_ms(lambda: lq.stout_force(g48, chain, 0.15, F, mode=1), 5)
     del F, chain
     out = dict(lattice=list(L), beta=beta, mass=m, tau=1.0, integrator="omelyan",
+               thermalisation="40 pure-gauge MD trajectories (tau 1, 10 steps, no "
+                              "accept/reject)", thermalisation_s=therm_s,
                seconds_20_steps=res[20][0], seconds_40_steps=res[40][0],
                dH_20=res[20][1]["dH"], dH_40=res[40][1]["dH"],
                dH_ratio=res[20][1]["dH"] / res[40][1]["dH"],
-               accepted_20=res[20][1]["accepted"],
+               accepted_20=res[20][1]["accepted"], accepted_40=res[40][1]["accepted"],
                force_evaluations_20=res[20][1]["force_evaluations"],
+               nested_10x4=dict(seconds=res["nested"][0], dH=res["nested"][1]["dH"],
+                                accepted=res["nested"][1]["accepted"],
+                                fermion_force_evaluations=res["nested"][1]["force_evaluations"]),
                gauge_force_48x4_ms=ms, gauge_force_TFLOPs=flops / (ms * 1e-3) / 1e12,
                gauge_force_frac_fp64_peak=flops / (ms * 1e-3) / 1e12 / 78.6,
                stout_smear_48x4_ms=ms_smear, stout_chain_rule_48x4_ms=ms_chain)
     log(f"RHMC trajectory 16^4: {res[20][0]:.2f} s (20 Omelyan steps), dH {out['dH_20']:.3e} / "
-        f"{out['dH_40']:.3e} at 20 / 40 steps; gauge force 48^4 {ms:.2f} ms "
-        f"({out['gauge_force_TFLOPs']:.1f} TFLOP/s)")
+        f"{out['dH_40']:.3e} at 20 / 40 steps (accepted {out['accepted_20']} / "
+        f"{out['accepted_40']}), nested 10x4 dH {out['nested_10x4']['dH']:.3e}; gauge force "
+        f"48^4 {ms:.2f} ms ({out['gauge_force_TFLOPs']:.1f} TFLOP/s)")
     return out
 
 

@@ -70,6 +70,9 @@ struct DslashCfg {
   int ns = 0;       // 1: the own-site operands and the outputs (each touched once) are loaded
                     // and stored non-temporal as well, leaving L2 to the neighbour spinors;
                     // only with nt = 1
+  int tm = 0;       // > 0: march along t, tm slices per thread (k_dslash_tm; needs
+                    // rhs_block 8, 12-real links, tz = ty = ilv = lf = hh = 0, nt = ns = 1)
+  int tp = 2;       // t-march: lanes per column sharing its eight right-hand sides (2 or 4)
 };
 
 // Dynamic LDS a workgroup reserves so that at most occ waves per SIMD are resident.
@@ -81,8 +84,15 @@ inline int dslash_lds_bytes(const DslashCfg& c) {
   return (160 * 1024) / wg_per_cu / 1024 * 1024;  // 160 KiB of LDS per CU
 }
 
+// Workgroups covering one time slice of columns in the t-march.
+inline int dslash_tm_column_blocks(const KGeom& g, const DslashCfg& c) {
+  const int cols = c.block / c.tp;
+  return (g.st + cols - 1) / cols;
+}
+
 // Number of workgroups along the site dimension for a configuration.
 inline int dslash_nblocks(const KGeom& g, const DslashCfg& c) {
+  if (c.tm > 0) return dslash_tm_column_blocks(g, c) * (g.Lt / c.tm);
   return (g.Vh + c.block - 1) / c.block;
 }
 // Largest partials array any configuration can need.
@@ -91,6 +101,10 @@ inline size_t dslash_partials_max(const KGeom& g, int nrhs) {
 }
 
 int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);
+
+// The t-march kernel family (dslash_tm.hip).
+bool dslash_tm_supported(const DslashCall& c, const DslashCfg& cfg);
+int dslash_tm_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);
 
 // Tuned configuration for this call's shape (times candidates on first use
 // with private scratch buffers; cached per process).  `forced_rhs_block` > 0

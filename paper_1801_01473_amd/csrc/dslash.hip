@@ -417,6 +417,7 @@ int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     set_error("unsupported dslash block size %d", cfg.block);
     return LQCD_ERR_UNSUPPORTED;
   }
+  if (cfg.tm > 0) return dslash_tm_launch(c, cfg, st);
   if (cfg.tz < 0 || (cfg.tz > 0 && c.g.Lz % cfg.tz != 0) || cfg.ty < 0 ||
       (cfg.ty > 0 && c.g.Ly % cfg.ty != 0)) {
     set_error("tile %d x %d (y, z) must divide Ly = %d, Lz = %d", cfg.ty, cfg.tz, c.g.Ly, c.g.Lz);
@@ -469,7 +470,8 @@ bool tuning_verbose() {
 }
 
 // ---- optional on-disk tuning cache (LQCD_TUNE_CACHE=file) ----------------
-// One line per tuned shape: "<key>;<block>,<B>,<xcd>,<tz>,<nt>,<occ>,<ilv>,<lf>,<hh>,<ty>[,<ns>]"
+// One line per tuned shape:
+// "<key>;<block>,<B>,<xcd>,<tz>,<nt>,<occ>,<ilv>,<lf>,<hh>,<ty>[,<ns>[,<tm>,<tp>]]"
 // where the key names the cache format, the GPU architecture and CU count,
 // the geometry, precision, link format, RHS count, forced RHS block and
 // mode.  Lines that do not parse, or whose configuration is not valid for
@@ -507,7 +509,8 @@ bool cfg_valid(const DslashCall& c, const DslashCfg& f, int forced) {
          (f.nt == 0 || f.nt == 1) && (f.lf == 0 || f.lf == 1) && (f.hh == 0 || f.hh == 1) &&
          (f.ns == 0 || (f.ns == 1 && f.nt == 1)) &&
          (f.ilv == 0 || f.ilv == 1) && f.occ >= 0 && dslash_lds_bytes(f) >= 0 &&
-         dslash_lds_bytes(f) <= 64 * 1024;
+         dslash_lds_bytes(f) <= 64 * 1024 && f.tm >= 0 &&
+         (f.tm == 0 || dslash_tm_supported(c, f));
 }
 
 // The last valid entry for the key, if any.
@@ -523,10 +526,10 @@ bool tune_cache_lookup(const char* path, const std::string& key, const DslashCal
     *semi = '\0';
     if (key != line) continue;
     DslashCfg v;
-    const int n = std::sscanf(semi + 1, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &v.block,
+    const int n = std::sscanf(semi + 1, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &v.block,
                               &v.rhs_block, &v.xcd, &v.tz, &v.nt, &v.occ, &v.ilv, &v.lf, &v.hh,
-                              &v.ty, &v.ns);
-    if (n != 10 && n != 11) continue;
+                              &v.ty, &v.ns, &v.tm, &v.tp);
+    if (n != 10 && n != 11 && n != 13) continue;
     if (!cfg_valid(c, v, forced)) continue;
     *out = v;
     found = true;
@@ -538,8 +541,8 @@ bool tune_cache_lookup(const char* path, const std::string& key, const DslashCal
 void tune_cache_store(const char* path, const std::string& key, const DslashCfg& v) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;  // the cache is an optimisation; an unwritable file only costs tuning
-  std::fprintf(f, "%s;%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d\n", key.c_str(), v.block, v.rhs_block,
-               v.xcd, v.tz, v.nt, v.occ, v.ilv, v.lf, v.hh, v.ty, v.ns);
+  std::fprintf(f, "%s;%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d\n", key.c_str(), v.block,
+               v.rhs_block, v.xcd, v.tz, v.nt, v.occ, v.ilv, v.lf, v.hh, v.ty, v.ns, v.tm, v.tp);
   std::fclose(f);
 }
 
@@ -555,13 +558,20 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     set_error("rhs_block must be 0 (tuned), 1, 2, 4 or 8, got %d", forced);
     return LQCD_ERR_INVALID_ARG;
   }
-  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty,ns]" pins the configuration
-  // (testing, profiling)
+  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty,ns,tm,tp]" pins the
+  // configuration (testing, profiling).  A t-march configuration applies only
+  // where that kernel exists (8 right-hand sides or more, 12-real links, the
+  // plain and fused modes); other calls fall back to its k_dslash settings.
   if (const char* e = std::getenv("LQCD_DSLASH_CFG")) {
     DslashCfg f;
-    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd, &f.tz,
-                    &f.nt, &f.occ, &f.ilv, &f.lf, &f.hh, &f.ty, &f.ns) >= 4) {
+    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd,
+                    &f.tz, &f.nt, &f.occ, &f.ilv, &f.lf, &f.hh, &f.ty, &f.ns, &f.tm,
+                    &f.tp) >= 4) {
       if (forced) f.rhs_block = forced;
+      if (f.tm > 0 && (c.nrhs < 8 || !dslash_tm_supported(c, f))) {
+        f.tm = 0;
+        if (f.rhs_block > c.nrhs) f.rhs_block = 1;
+      }
       *out = f;
       return LQCD_OK;
     }
@@ -712,10 +722,10 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     if (runs && tuning_verbose())
       fprintf(stderr,
               "[lqcd tune] L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d mode=%d block=%d B=%d xcd=%d "
-              "ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d ns=%d: %.2f us\n",
+              "ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d ns=%d tm=%d tp=%d: %.2f us\n",
               c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, t.mode, cfg.block,
               cfg.rhs_block, cfg.xcd, cfg.ty, cfg.tz, cfg.nt, cfg.occ, cfg.ilv, cfg.lf, cfg.hh,
-              cfg.ns, 1000.0 * ms);
+              cfg.ns, cfg.tm, cfg.tp, 1000.0 * ms);
     if (runs && ms < best_ms) {
       best_ms = ms;
       best = cfg;
@@ -766,6 +776,27 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
                 if (lds < 0 || lds > 64 * 1024) continue;
                 cand.push_back(v);
               }
+      // the t-march kernel, where it exists: eight right-hand sides per
+      // column, a few chunk lengths along t, lanes per column, XCD maps
+      if (c.nrhs >= 8 && (!forced || forced == 8))
+        for (int blk : {64, 128, 256})
+          for (int tp : {2, 4})
+            for (int tm : {4, 6, 8, 12, 16, 24})
+              for (int x : {0, 1})
+                for (int occ : {0, 2}) {
+                  DslashCfg v;
+                  v.block = blk;
+                  v.rhs_block = 8;
+                  v.xcd = x;
+                  v.nt = 1;
+                  v.ns = 1;
+                  v.tm = tm;
+                  v.tp = tp;
+                  v.occ = occ;
+                  const int lds = dslash_lds_bytes(v);
+                  if (lds < 0 || lds > 64 * 1024 || !dslash_tm_supported(t, v)) continue;
+                  cand.push_back(v);
+                }
     }
   }
   // Stage 4: single short timings are noisy and the minimum over ~200 of them
@@ -813,10 +844,10 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   if (tuning_verbose())
     fprintf(stderr,
             "[lqcd tune] chosen L=%dx%dx%dx%d prec=%d fmt=%d nrhs=%d mode=%d: block=%d B=%d "
-            "xcd=%d ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d ns=%d (%.2f us)\n",
+            "xcd=%d ty=%d tz=%d nt=%d occ=%d ilv=%d lf=%d hh=%d ns=%d tm=%d tp=%d (%.2f us)\n",
             c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, t.prec, t.fmt, c.nrhs, t.mode, best.block,
             best.rhs_block, best.xcd, best.ty, best.tz, best.nt, best.occ, best.ilv, best.lf,
-            best.hh, best.ns, 1000.0 * best_ms);
+            best.hh, best.ns, best.tm, best.tp, 1000.0 * best_ms);
   *out = best;
   return LQCD_OK;
 }

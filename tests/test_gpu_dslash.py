@@ -227,6 +227,63 @@ def test_six_slice_tiles(lq, cfg, prec, fmt, tol, monkeypatch):
     assert H.max_rel(got, ref) <= tol
 
 
+TM_CFGS = ["64,8,1,0,1,0,0,0,0,0,1,4,4", "128,8,0,0,1,0,0,0,0,0,1,6,2",
+           "256,8,1,0,1,0,0,0,0,0,1,12,2", "128,8,1,0,1,2,0,0,0,0,1,4,4",
+           "256,8,0,0,1,0,0,0,0,0,1,6,4", "64,8,1,0,1,0,0,0,0,0,1,12,2"]
+
+
+@pytest.mark.parametrize("cfg", TM_CFGS)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 1e-6)])
+@pytest.mark.parametrize("nrhs", [8, 11])
+def test_t_march_configurations(lq, cfg, prec, tol, nrhs, monkeypatch):
+    """The t-march kernel (each thread walks a column along t; 2 or 4 lanes
+    share a column's eight right-hand sides) for chunk lengths 4, 6 and 12 of
+    Lt = 12, every workgroup size, both XCD maps and an occupancy cap, on
+    8 and 11 right-hand sides (a ragged second group): D_oe, D_eo and
+    A = m^2 + sigma - D_eo D_oe against the oracle, and bit for bit equal to a
+    k_dslash configuration."""
+    L = (6, 4, 8, 12)
+    g = lq.Geometry(L)
+    U = _links(L, "haar", 71)
+    f = synth.gaussian_field(L, nrhs, 72)
+    fe = f.copy()
+    fe[:, synth.site_parity(L) == 1, :] = 0.0
+    Up = lq.pack_links(g, cu(U), prec, lq.LINKS12)
+    fr = f.astype(np.complex64).astype(np.complex128) if prec == 1 else f
+    fer = fe.astype(np.complex64).astype(np.complex128) if prec == 1 else fe
+    outs = {}
+    for name, c in (("tm", cfg), ("ref", "64,8,1,0,1,0,0,0,0,0,1")):
+        monkeypatch.setenv("LQCD_DSLASH_CFG", c)
+        outs[name] = (lq.doe(g, Up, lq.pack_spinor(g, cu(f), 0, prec)),
+                      lq.deo(g, Up, lq.pack_spinor(g, cu(f), 1, prec)),
+                      lq.apply_A(g, Up, 0.1, 0.3, lq.pack_spinor(g, cu(f), 0, prec)))
+    for a, b in zip(outs["tm"], outs["ref"]):
+        assert torch.equal(a, b)
+    got = host(lq.unpack_spinor(g, outs["tm"][0], 1))
+    ref = np.stack([oracle.doe(L, U, fr[j]) for j in range(nrhs)])
+    assert H.max_rel(got, ref) <= tol
+    got = host(lq.unpack_spinor(g, outs["tm"][1], 0))
+    ref = np.stack([oracle.deo(L, U, fr[j]) for j in range(nrhs)])
+    assert H.max_rel(got, ref) <= tol
+    got = host(lq.unpack_spinor(g, outs["tm"][2], 0))
+    ref = np.stack([oracle.apply_A(L, U, 0.1, 0.3, fer[j]) for j in range(nrhs)])
+    assert H.max_rel(got, ref) <= tol
+
+
+def test_t_march_invalid_configuration_falls_back(lq, monkeypatch):
+    """A t-march chunk that does not divide Lt is not launched: the call runs
+    k_dslash with the remaining settings and still gives the oracle's result."""
+    L = (4, 4, 4, 6)
+    g = lq.Geometry(L)
+    U = _links(L, "haar", 73)
+    f = synth.gaussian_field(L, 8, 74)
+    Up = lq.pack_links(g, cu(U), lq.F64, lq.LINKS12)
+    monkeypatch.setenv("LQCD_DSLASH_CFG", "64,8,1,0,1,0,0,0,0,0,1,4,2")
+    got = host(lq.unpack_spinor(g, lq.doe(g, Up, lq.pack_spinor(g, cu(f), 0)), 1))
+    ref = np.stack([oracle.doe(L, U, f[j]) for j in range(8)])
+    assert H.max_rel(got, ref) <= 1e-13
+
+
 def test_tuning_cache_file(lq, tmp_path, monkeypatch):
     """LQCD_TUNE_CACHE: a tuned shape is appended to the file; a valid entry
     for the key is used without tuning again (and, every launch variant
