@@ -375,6 +375,25 @@ def rhmc_trajectory_bench(lq, torch, g48, U48):
     return out
 
 
+def force_roofline(lq, torch, g, U64, al, X):
+    """The fermion force kernel on the step's solutions (K = npf x nshift
+    pairs), event-timed: per odd site and pair 8 SU(3) mat-vecs of chi = D_oe X
+    (8 x 66 flops + 7 x 6 adds) and 8 outer products (8 x 72), FP64; bytes: the
+    X vectors once (48 B per even site and pair), the links once (2 x 144 B
+    per odd site) and the output once (2 x 144 B).  Its roof is the larger of
+    bytes / 8 TB/s and flops / 78.6 TFLOP/s (FP64 vector peak)."""
+    F = lq.empty_links(g, lq.F64, lq.LINKS18, "cuda")
+    ms = event_time_ms(lambda: lq.fermion_force(g, U64, al, X, mode=0, out=F), 10)
+    K = X.shape[0] * X.shape[1]
+    flops = g.Vh * K * (8 * 66 + 7 * 6 + 8 * 72)
+    byts = g.Vh * (K * 48 + 2 * 144 * 4 + 2 * 144 * 4)
+    roof_ms = max(byts / 8e12, flops / 78.6e12) * 1e3
+    del F
+    return dict(pairs=K, ms=ms, TFLOPs=flops / (ms * 1e-3) / 1e12, GBps=byts / (ms * 1e-3) / 1e9,
+                roof_ms=roof_ms, frac_of_roof=roof_ms / ms, bound="fp64-alu" if
+                flops / 78.6e12 > byts / 8e12 else "hbm")
+
+
 def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, gpu_shift_updates_per_rhs, X0=None,
                  budget_s=20.0):
     """Oracle multi-shift CG timed on a bounded sample: a few iterations on one
@@ -588,6 +607,7 @@ def main():
     lq.kernel_timing(False)
     ktimes = lq.kernel_timing()
     kernels = kernel_table(g, nrhs, tstats, ktimes)
+    force_line = force_roofline(lq, torch, g, state["U64"], al, state["X"])
     dominant = max(kernels, key=lambda k: kernels[k]["total_ms"])
 
     # time-to-1e-10: plain FP64 GPU multi-shift, one RHS at a time
@@ -608,6 +628,22 @@ def main():
         t64 = time.time() - t0
         fp64 = dict(seconds=t64, iters=it64, max_true_residual=max(tr64))
         log(f"FP64 sequential baseline: {t64:.3f} s")
+        # the same FP64 solve with the right-hand sides batched (18-real links, then
+        # 12-real): separates the gain of batching from that of mixed precision
+        fp64["batched"] = {}
+        for fname, fmt in (("links18", lq.LINKS18), ("links12", lq.LINKS12)):
+            pb = lq.solver_params(mass=w["mass"], tol=1e-10, inner_prec=lq.F64, inner_fmt=fmt,
+                                  use_graph=1)
+            lq.cg_multishift(g, pb, U64, sig, phi_p)  # tune + graph
+            torch.cuda.synchronize()
+            t0 = time.time()
+            _, _, sb = lq.cg_multishift(g, pb, U64, sig, phi_p)
+            torch.cuda.synchronize()
+            fp64["batched"][fname] = dict(
+                seconds=time.time() - t0, iters=sb[0][0]["iters"],
+                max_true_rel_residual=max(s["true_rel_residual"] for row in sb for s in row))
+        log(f"FP64 batched: {fp64['batched']['links18']['seconds']:.3f} s (18-real), "
+            f"{fp64['batched']['links12']['seconds']:.3f} s (12-real)")
         # secondary context: each shift of the first RHS by its own plain FP64 CG
         lq.cg(g, p64, U64, phi_p[0:1].contiguous(), sigma=float(sig[-1]))  # graph capture
         torch.cuda.synchronize()
@@ -708,13 +744,21 @@ def main():
         "data": "synthetic (seeded generators in synth/: Haar links, Gaussian even-site sources)",
         "config": {"workload": w["name"], "lattice": list(L), "nrhs": nrhs, "nshift": nshift,
                    "mass": w["mass"], "tol": 1e-10, "inner": "fp32 12-real",
-                   "reliable_interval": 100, "reliable_delta": 1e-3, "mixed_switch": 1e-3},
+                   "reliable_interval": 100, "reliable_delta": 1e-3, "mixed_switch": 1e-3,
+                   "shift_window": stats[0][0]["shift_window"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "time_to_1e10": {
             "mixed_batched_s": mixed_solve,
             "fp64_sequential_s": fp64["seconds"] if fp64 else None,
             "speedup_mixed_vs_fp64": (fp64["seconds"] / mixed_solve) if fp64 else None,
+            "fp64_batched": fp64["batched"] if fp64 else None,
+            "speedup_split": ({
+                "batching_fp64_18": fp64["seconds"] / fp64["batched"]["links18"]["seconds"],
+                "compression_fp64_12": (fp64["batched"]["links18"]["seconds"]
+                                        / fp64["batched"]["links12"]["seconds"]),
+                "mixed_precision": fp64["batched"]["links12"]["seconds"] / mixed_solve}
+                if fp64 else None),
             "action_plus_force_s": float(np.median(force_times)),
             "fp64_per_shift_cg_1rhs_s": fp64["per_shift_cg_1rhs_s"] if fp64 else None,
             "fp64_per_shift_cg_iters": fp64["per_shift_cg_iters"] if fp64 else None,
@@ -735,6 +779,7 @@ def main():
                    "fp64_max_true_rel_residual": fp64["max_true_residual"] if fp64 else None},
         "kernels": kernels,
         "dslash": dsl,
+        "fermion_force": force_line,
         "rhmc_heatbath": rhmc,
         "rhmc_trajectory": traj,
         "stream": {"copy_GBps": copy_gbs, "triad_GBps": triad_gbs},

@@ -179,7 +179,7 @@ typedef struct {
     int32_t use_graph;         /* 1: replay iteration blocks as a captured hipGraph  */
     int32_t rhs_block;         /* right-hand sides per D_oe/D_eo link load, 0 = tuned */
     int32_t poll_interval;     /* iterations between host convergence checks, 0 = auto
-                                  (20 mixed, 40 FP64)                                */
+                                  (31 mixed, 62 FP64)                                */
     int32_t max_refine;        /* rounds of per-shift refinement allowed, >= 0       */
     int32_t shift_window;      /* multi-shift: iterations between materialisations of
                                   the shifted x_s, p_s (1..31; 1 = every iteration) */
@@ -211,7 +211,7 @@ typedef struct {
 
 /* Fills p with defaults: tol 1e-10, max_iter 10000, F64 inner, LINKS18,
  * reliable_interval 100, use_graph 1, rhs_block 0, poll 0, max_refine 3,
- * shift_window 20, reliable_delta 1e-3, mixed_switch 1e-3, inner_tol_factor 0.7. */
+ * shift_window 31, reliable_delta 1e-3, mixed_switch 1e-3, inner_tol_factor 0.7. */
 void lqcd_solver_params_default(lqcd_solver_params *p);
 
 /* Device workspace that lqcd_cg / lqcd_cg_multishift need for these sizes. */

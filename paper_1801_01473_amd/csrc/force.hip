@@ -52,9 +52,21 @@ constexpr int kMaxScratchDevices = 64;
 std::mutex g_scratch_mu;
 double* g_scratch_dev[kMaxScratchDevices] = {};
 
+// The value of lane (l ^ 1) (CTRL 0xB1: quad permutation 1,0,3,2) or of lane
+// (l ^ 2) (CTRL 0x4E: 2,3,0,1) of the same quad, moved by DPP in the vector
+// pipeline (no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the four lanes of a quad: v + v[l ^ 1], then + the partner pair's
+// sum; every lane of the quad ends with the same bits.
 __device__ __forceinline__ double quad_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
+  v += dpp_quad<0xB1>(v);
+  v += dpp_quad<0x4E>(v);
   return v;
 }
 
@@ -87,6 +99,13 @@ __global__ void __launch_bounds__(kForceBlock) k_force(const KGeom g,
   Su3<double> Mf, Mb;
 #pragma unroll
   for (int e = 0; e < 9; ++e) Mf.e[e] = Mb.e[e] = mk<double>(0, 0);
+  // The hop coefficients sf/2, sb/2 (a sign and a power of two, so exactly)
+  // go into the links, which then give the direction-mu part of chi directly.
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    Uf.e[e] = cscale<double>(0.5 * sf, Uf.e[e]);
+    Ub.e[e] = cscale<double>(0.5 * sb, Ub.e[e]);
+  }
 
   const int64_t vs = int64_t(3) * g.Vh;
   for (int j = 0; j < npf; ++j) {
@@ -103,25 +122,36 @@ __global__ void __launch_bounds__(kForceBlock) k_force(const KGeom g,
       adj_mat_vec<double>(Ub, xb, y2);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        chi[c].x = quad_sum(0.5 * (sf * y1[c].x - sb * y2[c].x));
-        chi[c].y = quad_sum(0.5 * (sf * y1[c].y - sb * y2[c].y));
+        chi[c].x = quad_sum(y1[c].x - y2[c].x);
+        chi[c].y = quad_sum(y1[c].y - y2[c].y);
       }
       // chi already carries the 1/2 of D_oe; the 1/2 of dD_oe and the factor 2 of
-      // the variation cancel, so M takes alpha * eta * s with no further factor.
-      const double cf = -al.a[i] * sf;  // M_mu(y)      += cf X(y+mu) chi(y)^dag
-      const double cb = al.a[i] * sb;   // M_mu(y-mu)   += cb chi(y) X(y-mu)^dag
+      // the variation cancel, so M takes alpha * eta * s with no further factor:
+      //   M_mu(y)    += cf X(y+mu) chi(y)^dag,   cf = -alpha sf
+      //   M_mu(y-mu) += cb chi(y) X(y-mu)^dag,   cb =  alpha sb
+      // with the coefficients folded into chi once per pair.
+      const double cf = -al.a[i] * sf;
+      const double cb = al.a[i] * sb;
+      cplx<double> cfc[3], cbc[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cfc[c] = mk<double>(cf * chi[c].x, -cf * chi[c].y);  // cf conj(chi)
+        cbc[c] = cscale<double>(cb, chi[c]);
+      }
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-          const cplx<double> of = cmul<double>(xf[a], conj_of<double>(chi[b]));
-          const cplx<double> ob = cmul<double>(chi[a], conj_of<double>(xb[b]));
-          Mf.e[3 * a + b].x = fma(cf, of.x, Mf.e[3 * a + b].x);
-          Mf.e[3 * a + b].y = fma(cf, of.y, Mf.e[3 * a + b].y);
-          Mb.e[3 * a + b].x = fma(cb, ob.x, Mb.e[3 * a + b].x);
-          Mb.e[3 * a + b].y = fma(cb, ob.y, Mb.e[3 * a + b].y);
+          cfma<double>(Mf.e[3 * a + b], xf[a], cfc[b]);
+          cfmac<double>(Mb.e[3 * a + b], xb[b], cbc[a]);  // += cb chi[a] conj(xb[b])
         }
     }
+  }
+  // the unscaled links for the projection: U = (2 s) U', exactly
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    Uf.e[e] = cscale<double>(2.0 * sf, Uf.e[e]);
+    Ub.e[e] = cscale<double>(2.0 * sb, Ub.e[e]);
   }
 
   // outputs: forward link at (parity 1, mu, h), backward link at (parity 0, mu, hb)

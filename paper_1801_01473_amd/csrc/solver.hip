@@ -714,7 +714,7 @@ struct Layout {
 };
 
 int poll_for(const lqcd_solver_params& p) {
-  return p.poll_interval > 0 ? p.poll_interval : (p.inner_prec == LQCD_F32 ? 20 : 40);
+  return p.poll_interval > 0 ? p.poll_interval : (p.inner_prec == LQCD_F32 ? 31 : 62);
 }
 
 // Window length of deferred shift updates: shift_window reduced to a divisor
@@ -1763,7 +1763,7 @@ void lqcd_solver_params_default(lqcd_solver_params* p) {
   p->rhs_block = 0;
   p->poll_interval = 0;
   p->max_refine = 3;
-  p->shift_window = 20;
+  p->shift_window = 31;
   p->reliable_delta = 1e-3;
   p->mixed_switch = 1e-3;
   p->inner_tol_factor = 0.7;

@@ -136,12 +136,12 @@ def test_solver_parameter_validation(lq):
     assert lq.solver_workspace_bytes(g, p, 0, 1) == 0
     assert lq.solver_workspace_bytes(g, p, 33, 1) == 0
     # deferred shift updates keep the window's residuals: W FP64 vectors per
-    # right-hand side beyond the per-iteration layout (W = 20 divides poll 40)
-    assert p.shift_window == 20
+    # right-hand side beyond the per-iteration layout (W = 31 divides poll 62)
+    assert p.shift_window == 31
     p1 = lq.solver_params(mass=0.1, shift_window=1)
     vec = 3 * g.Vh * 16
     extra = lq.solver_workspace_bytes(g, p, 12, 8) - lq.solver_workspace_bytes(g, p1, 12, 8)
-    assert extra >= 8 * (20 + 1) * vec
+    assert extra >= 8 * (31 + 1) * vec
     assert lq.solver_workspace_bytes(g, p, 1, 8) == lq.solver_workspace_bytes(g, p1, 1, 8)
     assert lq.solver_workspace_bytes(g, p, 1, 65) == 0
     # a too-small workspace is reported before any device work

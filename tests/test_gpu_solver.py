@@ -322,7 +322,7 @@ def test_kernel_timing_instrumentation(lq):
     assert n64 >= it64 and n32 >= st[0][0]["iters"] - it64
     assert kt["dslash_oe_f64_n2"][0] == n64 and kt["dslash_eo_cg_f32_n2"][0] == n32
     w = st[0][0]["shift_window"]
-    assert w == 20
+    assert w == 31
     # one scheduled flush per window, plus the forced ones at phase ends and reliable updates
     assert kt["ms_flush_f64_n2"][0] >= n64 // w and kt["ms_flush_f32_n2"][0] >= n32 // w
     assert all(ms > 0 for _, ms in kt.values())
@@ -341,7 +341,7 @@ def test_kernel_timing_instrumentation(lq):
 
 
 @pytest.mark.parametrize("mode", MODES[:2])
-@pytest.mark.parametrize("window,poll", [(1, 0), (20, 0), (7, 0), (4, 6), (31, 31)])
+@pytest.mark.parametrize("window,poll", [(1, 0), (20, 40), (7, 0), (4, 6), (31, 0), (31, 31)])
 def test_deferred_shift_updates_match(lq, mode, window, poll):
     """Deferred shift updates (x_s, p_s kept as combinations of the window's
     base residuals, Sec. 2 recurrences regrouped) reach every shift's true
@@ -357,7 +357,7 @@ def test_deferred_shift_updates_match(lq, mode, window, poll):
     X, st, stats = lq.cg_multishift(g, p, U64, sig, b)
     assert st == 0
     Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(2, len(sig), -1, 3)
-    pol = poll if poll else (20 if mode["inner_prec"] == 1 else 40)
+    pol = poll if poll else (31 if mode["inner_prec"] == 1 else 62)
     w_expect = max(d for d in range(1, min(window, 31) + 1) if pol % d == 0)
     for j in range(2):
         for s, sg in enumerate(sig):
