@@ -96,7 +96,8 @@ def event_time_ms(fn, reps):
 def dslash_entry(lq, torch, g, Ul, prec, fmt, n, copy_gbs, label):
     """Standalone D_oe: median launch time, algorithmic GB/s, GFLOP/s (570 per
     output site and RHS; 'executed' adds the row-2 reconstruction per site and
-    link load: 336 for 12-real, 384 with the determinant factor)."""
+    link load: 336 for 12-real, 384 with the determinant factor, 336 + 8 x 54
+    for the U(1) angle format: row 2 and the phase product per link)."""
     cd = torch.complex128 if prec == lq.F64 else torch.complex64
     x = torch.randn(n, 3, g.Vh, dtype=cd, device="cuda")
     y = torch.empty_like(x)
@@ -104,7 +105,8 @@ def dslash_entry(lq, torch, g, Ul, prec, fmt, n, copy_gbs, label):
     byts = g.Vh * dslash_bytes_per_site(prec, fmt, n)
     gbs = byts / (ms * 1e-3) / 1e9
     flops = 570.0 * g.Vh * n
-    exe = flops + {lq.LINKS12: 336.0, lq.LINKS12D: 384.0}.get(fmt, 0.0) * g.Vh
+    exe = flops + {lq.LINKS12: 336.0, lq.LINKS12D: 384.0,
+                   lq.LINKS12T: 336.0 + 8 * 54.0}.get(fmt, 0.0) * g.Vh
     del x, y
     return dict(what=label, us=1000 * ms, GBps=gbs, frac_hbm_peak=gbs / HBM_PEAK_GBS,
                 frac_stream_copy=gbs / copy_gbs, GFLOPs=flops / (ms * 1e-3) / 1e9,
@@ -115,7 +117,7 @@ def dslash_bytes_per_site(prec, fmt, nrhs):
     """Algorithmic bytes per output site: every link once, each input spinor
     once (perfect neighbour reuse), each output once."""
     rb = 8 if prec == 0 else 4
-    links = 8 * {0: 9, 1: 6, 2: 7}[fmt] * 2 * rb
+    links = 8 * {0: 18, 1: 12, 2: 14, 3: 13}[fmt] * rb
     return links + nrhs * 2 * (3 * 2 * rb)
 
 
@@ -671,6 +673,9 @@ def main():
             "fp32_12_1rhs": (lq.F32, lq.LINKS12, 1),
             f"fp32_12_{nrhs}rhs": (lq.F32, lq.LINKS12, nrhs),
             f"fp32_12d_{nrhs}rhs": (lq.F32, lq.LINKS12D, nrhs),
+            f"fp32_12t_{nrhs}rhs": (lq.F32, lq.LINKS12T, nrhs),
+            "fp32_12t_1rhs": (lq.F32, lq.LINKS12T, 1),
+            "fp32_12d_1rhs": (lq.F32, lq.LINKS12D, 1),
             f"fp64_12_{nrhs}rhs": (lq.F64, lq.LINKS12, nrhs)}.items():
         Ul = U64 if (prec, fmt) == (lq.F64, lq.LINKS18) else lq.convert_links(
             g, U64, lq.F64, lq.LINKS18, prec, fmt)

@@ -40,6 +40,12 @@
  *           (LQCD_LINKS12D, rows 0-1 and the determinant d as element 6; row
  *           2 = d conj(row0 x row1), exact for every unitary link, so links
  *           carrying U(1) phases (lqcd_apply_u1_phases) stay compressed).
+ *           LQCD_LINKS12T (the paper's U(1)-phase storage, Sec. 4.1): a link
+ *           u U with U in SU(3) and u = exp(i theta) is stored as rows 0-1 of
+ *           U and the angle theta; each [parity][mu] block holds the six
+ *           complex planes of Vh followed by one plane of Vh reals (theta),
+ *           i.e. 6.5 complex planes (a tensor view [2][4][13][Vh/2]); the
+ *           operator rebuilds row 2 and multiplies by cos theta + i sin theta.
  *   complex = two IEEE doubles (LQCD_F64) or two floats (LQCD_F32).
  *
  * Memory and streams: every data pointer is a device pointer owned by the
@@ -74,7 +80,7 @@ enum lqcd_status {
 };
 
 enum lqcd_prec { LQCD_F64 = 0, LQCD_F32 = 1 };
-enum lqcd_link_fmt { LQCD_LINKS18 = 0, LQCD_LINKS12 = 1, LQCD_LINKS12D = 2 };
+enum lqcd_link_fmt { LQCD_LINKS18 = 0, LQCD_LINKS12 = 1, LQCD_LINKS12D = 2, LQCD_LINKS12T = 3 };
 
 typedef struct {
     int32_t L[4];           /* Lx, Ly, Lz, Lt: each even and >= 2;
@@ -110,7 +116,8 @@ int lqcd_pack_links(const lqcd_geom *g, const void *U_nat, int prec, int fmt,
  * Convert an already packed field into another precision/format
  * (e.g. LQCD_F64/LQCD_LINKS18 -> LQCD_F32/LQCD_LINKS12 for the inner solver).
  * Every source format is first completed to the full matrix; LQCD_LINKS12D
- * destinations store its determinant.
+ * destinations store its determinant; LQCD_LINKS12T destinations split it as
+ * exp(i theta) U with theta = arg(det) / 3 and U = exp(-i theta) V in SU(3).
  */
 int lqcd_convert_links(const lqcd_geom *g, const void *src, int src_prec, int src_fmt,
                        void *dst, int dst_prec, int dst_fmt, void *stream);
@@ -350,11 +357,26 @@ int lqcd_rational_combine(const lqcd_geom *g, int32_t nrhs, int32_t nshift, doub
  * solvers and the fermion force (whose TA(U M) is unchanged by the factor).
  * Phased links are not in SU(3) (det = exp(3 i theta)), so LQCD_LINKS12 --
  * which rebuilds row 2 from det = 1 -- must not be used with them; the
- * compressed format for them is LQCD_LINKS12D (rows 0-1 and the determinant,
- * 7 complex per link), e.g. as the inner solver format.  Stream-ordered.
+ * compressed formats for them are LQCD_LINKS12D (rows 0-1 and the determinant,
+ * 7 complex per link) and LQCD_LINKS12T (rows 0-1 and the angle, 6.5 complex
+ * per link), e.g. as the inner solver format.  Stream-ordered.
  */
 int lqcd_apply_u1_phases(const lqcd_geom *g, const void *U64, const double *theta, void *out,
                          void *stream);
+
+/*
+ * LQCD_LINKS12T links from an SU(3) field and one flavour's U(1) angles
+ * (Sec. 4.1: the gauge field is shared, each flavour keeps its own phases
+ * theta_mu(x), and the operator recomputes cos theta + i sin theta on line):
+ *   U64    packed FP64 18-real SU(3) links (rows 0-1 are stored as they are)
+ *   theta  device FP64 [4][V], natural lexicographic order
+ *   prec   precision of the output (the angle is stored in it too)
+ *   out    packed LQCD_LINKS12T links, lqcd_links_bytes(g, prec, LQCD_LINKS12T)
+ * D_oe/D_eo on `out` equal D_oe/D_eo on lqcd_apply_u1_phases(U64, theta).
+ * Stream-ordered.
+ */
+int lqcd_pack_links_u1(const lqcd_geom *g, const void *U64, const double *theta, int prec,
+                       void *out, void *stream);
 
 /*
  * Stout smearing (Sec. 2: the Dirac operator hops with the k-times stout

@@ -9,7 +9,9 @@ built; there is no CPU fallback.
 
 Layouts follow ``include/lqcd.h``:
   natural links   complex128 [4][V][3][3]     natural fields complex128 [n][V][3]
-  packed links    complex128/complex64 [2][4][NE][Vh]  (NE = 9 or 6)
+  packed links    complex128/complex64 [2][4][NE][Vh]  (NE = 9, 6 or 7), or
+                  [2][4][13][Vh/2] for LINKS12T (six complex planes and one
+                  plane of reals, the U(1) angle, per [parity][mu] block)
   packed spinors  complex128/complex64 [n][3][Vh] (one parity)
 """
 from __future__ import annotations
@@ -27,7 +29,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblqcd.so")
 
 F64, F32 = 0, 1
-LINKS18, LINKS12, LINKS12D = 0, 1, 2
+LINKS18, LINKS12, LINKS12D, LINKS12T = 0, 1, 2, 3
 
 OK = 0
 ERR_INVALID_ARG = 1
@@ -121,6 +123,7 @@ _SIGS = {
     "lqcd_action_noalloc": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _dp, _vp]),
     "lqcd_rational_combine": (ctypes.c_int, [_gp, _i32, _i32, _dbl, _dp, _vp, _vp, _vp, _vp]),
     "lqcd_apply_u1_phases": (ctypes.c_int, [_gp, _vp, _vp, _vp, _vp]),
+    "lqcd_pack_links_u1": (ctypes.c_int, [_gp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "lqcd_stout_smear": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _vp]),
     "lqcd_stout_workspace_bytes": (ctypes.c_size_t, [_gp]),
     "lqcd_stout_force": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _i32, _vp, _vp, ctypes.c_size_t,
@@ -212,7 +215,13 @@ def _cdtype(prec):
 
 
 def _ne(fmt):
-    return {LINKS18: 9, LINKS12: 6, LINKS12D: 7}[fmt]
+    return {LINKS18: 9, LINKS12: 6, LINKS12D: 7, LINKS12T: 13}[fmt]
+
+
+def _links_shape(geom: Geometry, fmt):
+    if fmt == LINKS12T:
+        return (2, 4, 13, geom.Vh // 2)
+    return (2, 4, _ne(fmt), geom.Vh)
 
 
 def links_bytes(geom: Geometry, prec=F64, fmt=LINKS18) -> int:
@@ -224,7 +233,7 @@ def spinor_bytes(geom: Geometry, prec=F64) -> int:
 
 
 def empty_links(geom: Geometry, prec=F64, fmt=LINKS18, device="cuda"):
-    return torch.empty((2, 4, _ne(fmt), geom.Vh), dtype=_cdtype(prec), device=device)
+    return torch.empty(_links_shape(geom, fmt), dtype=_cdtype(prec), device=device)
 
 
 def empty_spinor(geom: Geometry, n=1, prec=F64, device="cuda"):
@@ -241,7 +250,7 @@ def _natural_links_arg(geom: Geometry, t, name):
 
 def pack_links(geom: Geometry, U_nat: torch.Tensor, prec=F64, fmt=LINKS18, out=None):
     _natural_links_arg(geom, U_nat, "U_nat")
-    if prec not in (F64, F32) or fmt not in (LINKS18, LINKS12, LINKS12D):
+    if prec not in (F64, F32) or fmt not in (LINKS18, LINKS12, LINKS12D, LINKS12T):
         raise ValueError("unknown precision or link format")
     out = empty_links(geom, prec, fmt, U_nat.device) if out is None else out
     _links_arg(geom, out, "out", prec, fmt)
@@ -301,7 +310,7 @@ def _prec_of(t):
 
 
 def _fmt_of(U):
-    return {9: LINKS18, 6: LINKS12, 7: LINKS12D}[int(U.shape[2])]
+    return {9: LINKS18, 6: LINKS12, 7: LINKS12D, 13: LINKS12T}[int(U.shape[2])]
 
 
 # ---------------------------------------------------------------- argument checks
@@ -335,10 +344,10 @@ def _links_arg(geom: Geometry, U, name="U", prec=None, fmt=None):
     _tensor(U, name)
     if U.dtype not in (torch.complex128, torch.complex64):
         raise ValueError(f"{name} must be complex128 or complex64 packed links, got {U.dtype}")
-    if U.dim() != 4 or tuple(U.shape[:2]) != (2, 4) or int(U.shape[3]) != geom.Vh \
-            or int(U.shape[2]) not in (9, 6, 7):
-        raise ValueError(f"{name} must be packed links [2][4][9|6|7][{geom.Vh}], "
-                         f"got {tuple(U.shape)}")
+    if U.dim() != 4 or tuple(U.shape[:2]) != (2, 4) or int(U.shape[2]) not in (9, 6, 7, 13) \
+            or int(U.shape[3]) != (geom.Vh // 2 if int(U.shape[2]) == 13 else geom.Vh):
+        raise ValueError(f"{name} must be packed links [2][4][9|6|7][{geom.Vh}] or "
+                         f"[2][4][13][{geom.Vh // 2}], got {tuple(U.shape)}")
     p, f = _prec_of(U), _fmt_of(U)
     if prec is not None and p != prec:
         raise ValueError(f"{name} must be {_cdtype(prec)}, got {U.dtype}")
@@ -607,6 +616,23 @@ def apply_u1_phases(geom: Geometry, U64, theta, out=None):
     out = torch.empty_like(U64) if out is None else out
     _u64_arg(geom, out, "out")
     _check(_fn("lqcd_apply_u1_phases")(geom.c(), _ptr(U64), _ptr(theta), _ptr(out), _stream()))
+    return out
+
+
+def pack_links_u1(geom: Geometry, U64, theta, prec=F32, out=None):
+    """LINKS12T links of one flavour: rows 0-1 of the SU(3) links U64 (packed
+    FP64 18-real) and the angles theta (float64 [4][V], natural order, on the
+    device), stored in precision prec; the operator recomputes exp(i theta)."""
+    _u64_arg(geom, U64)
+    _tensor(theta, "theta")
+    if theta.dtype != torch.float64 or tuple(theta.shape) != (4, geom.V):
+        raise ValueError("theta must be float64 [4][V]")
+    theta = theta.contiguous()
+    out = empty_links(geom, prec, LINKS12T, U64.device) if out is None else out
+    _links_arg(geom, out, "out", prec, LINKS12T)
+    _gpu(theta)
+    _check(_fn("lqcd_pack_links_u1")(geom.c(), _ptr(U64), _ptr(theta), int(prec), _ptr(out),
+                                     _stream()))
     return out
 
 

@@ -66,8 +66,10 @@ int check_prec_fmt(int prec, int fmt) {
     set_error("precision must be LQCD_F64 (0) or LQCD_F32 (1), got %d", prec);
     return LQCD_ERR_INVALID_ARG;
   }
-  if (fmt != LQCD_LINKS18 && fmt != LQCD_LINKS12 && fmt != LQCD_LINKS12D) {
-    set_error("link format must be LQCD_LINKS18 (0), LQCD_LINKS12 (1) or LQCD_LINKS12D (2), got %d",
+  if (fmt != LQCD_LINKS18 && fmt != LQCD_LINKS12 && fmt != LQCD_LINKS12D &&
+      fmt != LQCD_LINKS12T) {
+    set_error("link format must be LQCD_LINKS18 (0), LQCD_LINKS12 (1), LQCD_LINKS12D (2) or "
+              "LQCD_LINKS12T (3), got %d",
               fmt);
     return LQCD_ERR_INVALID_ARG;
   }
@@ -120,7 +122,7 @@ int lqcd_version(void) { return 10000; }
 size_t lqcd_links_bytes(const lqcd_geom* g, int prec, int fmt) {
   if (check_geom(g) != LQCD_OK || check_prec_fmt(prec, fmt) != LQCD_OK) return 0;
   const KGeom k = make_kgeom(g);
-  return size_t(2) * 4 * link_elems(fmt) * size_t(k.Vh) * 2 * real_bytes(prec);
+  return size_t(2) * 4 * link_reals(fmt) * size_t(k.Vh) * real_bytes(prec);
 }
 
 size_t lqcd_spinor_bytes(const lqcd_geom* g, int prec) {

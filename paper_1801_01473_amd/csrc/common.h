@@ -196,8 +196,10 @@ int check_prec_fmt(int prec, int fmt);
 int check_ptr(const void* p, const char* name);
 int check_nrhs(int32_t nrhs);
 
-inline size_t link_elems(int fmt) {
-  return fmt == LQCD_LINKS12 ? 6 : fmt == LQCD_LINKS12D ? 7 : 9;
+// Reals stored per link: 18, 12, 14 (rows 0-1 and the determinant) or 13
+// (rows 0-1 and the U(1) angle).
+inline size_t link_reals(int fmt) {
+  return fmt == LQCD_LINKS12 ? 12 : fmt == LQCD_LINKS12D ? 14 : fmt == LQCD_LINKS12T ? 13 : 18;
 }
 inline size_t real_bytes(int prec) { return prec == LQCD_F32 ? 4 : 8; }
 

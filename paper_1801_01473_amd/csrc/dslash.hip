@@ -115,11 +115,11 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[b][c] = mk<R>(0, 0);
 
-    const int64_t par_stride = int64_t(4) * NE * g.Vh;
+    const int64_t par_stride = int64_t(4) * link_block<NE>(g.Vh);
     const cplx<R>* Uout = static_cast<const cplx<R>*>(a.U) + a.out_par * par_stride;
     const cplx<R>* Uin = static_cast<const cplx<R>*>(a.U) + (1 - a.out_par) * par_stride;
     constexpr uint32_t cb = sizeof(cplx<R>);
-    const uint32_t link_bytes = uint32_t(NE) * uint32_t(g.Vh) * cb;
+    const uint32_t link_bytes = uint32_t(link_block<NE>(g.Vh)) * cb;
     // Input rows of the block's right-hand sides; rows past nrhs alias the
     // last one (loaded and computed, never stored), so the loads of every
     // right-hand side issue together without a branch between them.
@@ -156,15 +156,20 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
         Su3<R> u;
         cplx<R> v[B][3];
         const __amdgpu_buffer_rsrc_t rl =
-            make_res((fw ? Uout : Uin) + int64_t(mu) * NE * g.Vh, link_bytes);
+            make_res((fw ? Uout : Uin) + int64_t(mu) * link_block<NE>(g.Vh), link_bytes);
         const uint32_t ol = uint32_t(fw ? h : nbr) * cb, on = uint32_t(nbr) * cb;
 #pragma unroll
-        for (int e = 0; e < NE; ++e) u.e[e] = ld_buf<R, LAUX>(rl, ol, uint32_t(e) * csoff);
+        for (int e = 0; e < stored_planes<NE>(); ++e)
+          u.e[e] = ld_buf<R, LAUX>(rl, ol, uint32_t(e) * csoff);
+        R th = R(0);
+        if constexpr (NE == 8)
+          th = ld_buf_real<R, LAUX>(rl, uint32_t(fw ? h : nbr) * uint32_t(sizeof(R)), 6u * csoff);
 #pragma unroll
         for (int b = 0; b < B; ++b)
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) v[b][cc] = ld_buf<R>(rin[b], on, uint32_t(cc) * csoff);
         complete_link<R, NE>(u);
+        if constexpr (NE == 8) apply_u1<R>(u, th);
         if (!fw) {  // U^dag
           Su3<R> t = u;
 #pragma unroll
@@ -203,15 +208,21 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
       const int nf = fwd[mu], nb = bwd[mu];
       Su3<R> uf, ub;
       cplx<R> vf[B][3], vb[B][3];
+      R thf = R(0), thb = R(0);
       {
         const __amdgpu_buffer_rsrc_t rf =
-            make_res(Uout + int64_t(mu) * NE * g.Vh, link_bytes);
-        const __amdgpu_buffer_rsrc_t rb = make_res(Uin + int64_t(mu) * NE * g.Vh, link_bytes);
+            make_res(Uout + int64_t(mu) * link_block<NE>(g.Vh), link_bytes);
+        const __amdgpu_buffer_rsrc_t rb =
+            make_res(Uin + int64_t(mu) * link_block<NE>(g.Vh), link_bytes);
         const uint32_t of = uint32_t(h) * cb, ob = uint32_t(nb) * cb;
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
+        for (int e = 0; e < stored_planes<NE>(); ++e) {
           uf.e[e] = ld_buf<R, LAUX>(rf, of, uint32_t(e) * csoff);
           ub.e[e] = ld_buf<R, LAUX>(rb, ob, uint32_t(e) * csoff);
+        }
+        if constexpr (NE == 8) {
+          thf = ld_buf_real<R, LAUX>(rf, uint32_t(h) * uint32_t(sizeof(R)), 6u * csoff);
+          thb = ld_buf_real<R, LAUX>(rb, uint32_t(nb) * uint32_t(sizeof(R)), 6u * csoff);
         }
       }
       {
@@ -226,6 +237,10 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
       }
       complete_link<R, NE>(uf);
       complete_link<R, NE>(ub);
+      if constexpr (NE == 8) {
+        apply_u1<R>(uf, thf);
+        apply_u1<R>(ub, thb);
+      }
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         cplx<R> y[3];
@@ -351,8 +366,8 @@ int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     set_error("non-temporal own-site streams (ns) need non-temporal link loads (nt)");
     return LQCD_ERR_UNSUPPORTED;
   }
-  if constexpr (NE == 7) {
-    // the phased-link format instantiates the plain schedule only (loads
+  if constexpr (NE == 7 || NE == 8) {
+    // the phased-link formats instantiate the plain schedule only (loads
     // first is dropped): half the variants, the same results
     switch ((cfg.nt ? 1 : 0) | (cfg.hh ? 4 : 0) | (cfg.ns ? 8 : 0)) {
       case 0: LQCD_K(0); break;
@@ -434,9 +449,11 @@ int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
   if (c.prec == LQCD_F64)
     return c.fmt == LQCD_LINKS12    ? launch_mode<double, 6>(c, cfg, st)
            : c.fmt == LQCD_LINKS12D ? launch_mode<double, 7>(c, cfg, st)
+           : c.fmt == LQCD_LINKS12T ? launch_mode<double, 8>(c, cfg, st)
                                     : launch_mode<double, 9>(c, cfg, st);
   return c.fmt == LQCD_LINKS12    ? launch_mode<float, 6>(c, cfg, st)
          : c.fmt == LQCD_LINKS12D ? launch_mode<float, 7>(c, cfg, st)
+         : c.fmt == LQCD_LINKS12T ? launch_mode<float, 8>(c, cfg, st)
                                   : launch_mode<float, 9>(c, cfg, st);
 }
 

@@ -14,22 +14,44 @@ constexpr int kBlock = 256;
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// Writes the NE stored elements of the full matrix u at stride Vh: 9 or 6 as
-// is, 7 = rows 0-1 and det u.
+__device__ __forceinline__ double2 det3(const Su3<double>& u) {
+  const double2 m0 = csub<double>(cmul<double>(u.e[4], u.e[8]), cmul<double>(u.e[5], u.e[7]));
+  const double2 m1 = csub<double>(cmul<double>(u.e[3], u.e[8]), cmul<double>(u.e[5], u.e[6]));
+  const double2 m2 = csub<double>(cmul<double>(u.e[3], u.e[7]), cmul<double>(u.e[4], u.e[6]));
+  double2 d = cmul<double>(u.e[0], m0);
+  const double2 t1 = cmul<double>(u.e[1], m1), t2 = cmul<double>(u.e[2], m2);
+  d.x += t2.x - t1.x;
+  d.y += t2.y - t1.y;
+  return d;
+}
+
+// Writes the stored elements of the full matrix u (link h of one [parity][mu]
+// block at `block`): 9 or 6 as is, 7 = rows 0-1 and det u, 8 = rows 0-1 of
+// exp(-i theta) u and theta = arg(det u) / 3 (rounded to R first, so that the
+// stored rows and angle rebuild u).
 template <typename R, int NE>
-__device__ __forceinline__ void store_link(const Su3<double>& u, cplx<R>* dst, int Vh) {
+__device__ __forceinline__ void store_link(const Su3<double>& u, cplx<R>* block, int h, int Vh) {
+  cplx<R>* dst = block + h;
+  if constexpr (NE == 8) {
+    const double2 d = det3(u);
+    const R th = R(atan2(d.y, d.x) / 3.0);
+    double sn, cs;
+    sincos(double(th), &sn, &cs);
+    const double2 ph = make_double2(cs, -sn);
 #pragma unroll
-  for (int e = 0; e < (NE == 7 ? 6 : NE); ++e)
-    dst[int64_t(e) * Vh] = mk<R>((R)u.e[e].x, (R)u.e[e].y);
-  if constexpr (NE == 7) {
-    const double2 m0 = csub<double>(cmul<double>(u.e[4], u.e[8]), cmul<double>(u.e[5], u.e[7]));
-    const double2 m1 = csub<double>(cmul<double>(u.e[3], u.e[8]), cmul<double>(u.e[5], u.e[6]));
-    const double2 m2 = csub<double>(cmul<double>(u.e[3], u.e[7]), cmul<double>(u.e[4], u.e[6]));
-    double2 d = cmul<double>(u.e[0], m0);
-    const double2 t1 = cmul<double>(u.e[1], m1), t2 = cmul<double>(u.e[2], m2);
-    d.x += t2.x - t1.x;
-    d.y += t2.y - t1.y;
-    dst[int64_t(6) * Vh] = mk<R>((R)d.x, (R)d.y);
+    for (int e = 0; e < 6; ++e) {
+      const double2 w = cmul<double>(ph, u.e[e]);
+      dst[int64_t(e) * Vh] = mk<R>((R)w.x, (R)w.y);
+    }
+    reinterpret_cast<R*>(block + int64_t(6) * Vh)[h] = th;
+  } else {
+#pragma unroll
+    for (int e = 0; e < (NE == 7 ? 6 : NE); ++e)
+      dst[int64_t(e) * Vh] = mk<R>((R)u.e[e].x, (R)u.e[e].y);
+    if constexpr (NE == 7) {
+      const double2 d = det3(u);
+      dst[int64_t(6) * Vh] = mk<R>((R)d.x, (R)d.y);
+    }
   }
 }
 
@@ -55,7 +77,30 @@ __global__ void __launch_bounds__(kBlock) k_pack_links(KGeom g, const double2* _
   Su3<double> u;
 #pragma unroll
   for (int e = 0; e < 9; ++e) u.e[e] = src[e];
-  store_link<R, NE>(u, out + (int64_t(par) * 4 + mu) * NE * g.Vh + h, g.Vh);
+  store_link<R, NE>(u, out + (int64_t(par) * 4 + mu) * link_block<NE>(g.Vh), h, g.Vh);
+}
+
+// packed FP64 18-real SU(3) links and natural FP64 angles [4][V] -> packed
+// LQCD_LINKS12T of R (rows 0-1 of U as they are, the angle per link)
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pack_links_u1(KGeom g, const double2* __restrict__ U,
+                                                          const double* __restrict__ theta,
+                                                          cplx<R>* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(8) * g.Vh) return;
+  const int pm = int(i / g.Vh);
+  const int h = int(i % g.Vh);
+  const int par = pm >> 2, mu = pm & 3;
+  const Site s = decode_site(g, h, par);
+  const int64_t lex = int64_t(2) * h + (s.x & 1);
+  const double2* src = U + int64_t(pm) * 9 * g.Vh + h;
+  cplx<R>* block = out + int64_t(pm) * link_block<8>(g.Vh);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const double2 v = src[int64_t(e) * g.Vh];
+    block[int64_t(e) * g.Vh + h] = mk<R>((R)v.x, (R)v.y);
+  }
+  reinterpret_cast<R*>(block + int64_t(6) * g.Vh)[h] = R(theta[int64_t(mu) * 2 * g.Vh + lex]);
 }
 
 // packed F64-18 -> natural complex128
@@ -90,14 +135,16 @@ __global__ void __launch_bounds__(kBlock) k_convert_links(int Vh, const cplx<RS>
   const int64_t pm = i / Vh;  // parity*4 + mu
   const int h = int(i % Vh);
   Su3<double> u;
-  const cplx<RS>* src = in + pm * NS * Vh + h;
+  const cplx<RS>* blk = in + pm * link_block<NS>(Vh);
 #pragma unroll
-  for (int e = 0; e < NS; ++e) {
-    const cplx<RS> v = src[int64_t(e) * Vh];
+  for (int e = 0; e < stored_planes<NS>(); ++e) {
+    const cplx<RS> v = blk[int64_t(e) * Vh + h];
     u.e[e] = mk<double>((double)v.x, (double)v.y);
   }
   complete_link<double, NS>(u);
-  store_link<RD, ND>(u, out + pm * ND * Vh + h, Vh);
+  if constexpr (NS == 8)
+    apply_u1<double>(u, (double)reinterpret_cast<const RS*>(blk + int64_t(6) * Vh)[h]);
+  store_link<RD, ND>(u, out + pm * link_block<ND>(Vh), h, Vh);
 }
 
 // natural complex128 [nrhs][V][3] -> packed [nrhs][3][Vh] of R, one parity
@@ -158,16 +205,37 @@ void conv_launch(const KGeom& k, const void* src, void* dst, hipStream_t st) {
                      dim3(kBlock), 0, st, k.Vh, (const cplx<RS>*)src, (cplx<RD>*)dst);
 }
 
+// the element-count template argument of a link format (8: rows 0-1 and the angle)
+inline int ne_of(int fmt) {
+  return fmt == LQCD_LINKS12 ? 6 : fmt == LQCD_LINKS12D ? 7 : fmt == LQCD_LINKS12T ? 8 : 9;
+}
+
+template <typename RS, int NS, typename RD>
+void conv_ne(const KGeom& k, const void* src, void* dst, int df, hipStream_t st) {
+  switch (ne_of(df)) {
+    case 6: conv_launch<RS, NS, RD, 6>(k, src, dst, st); break;
+    case 7: conv_launch<RS, NS, RD, 7>(k, src, dst, st); break;
+    case 8: conv_launch<RS, NS, RD, 8>(k, src, dst, st); break;
+    default: conv_launch<RS, NS, RD, 9>(k, src, dst, st); break;
+  }
+}
+
 template <typename RS, int NS>
 void conv_dst(const KGeom& k, const void* src, void* dst, int dp, int df, hipStream_t st) {
-  if (dp == LQCD_F64) {
-    if (df == LQCD_LINKS12) conv_launch<RS, NS, double, 6>(k, src, dst, st);
-    else if (df == LQCD_LINKS12D) conv_launch<RS, NS, double, 7>(k, src, dst, st);
-    else conv_launch<RS, NS, double, 9>(k, src, dst, st);
-  } else {
-    if (df == LQCD_LINKS12) conv_launch<RS, NS, float, 6>(k, src, dst, st);
-    else if (df == LQCD_LINKS12D) conv_launch<RS, NS, float, 7>(k, src, dst, st);
-    else conv_launch<RS, NS, float, 9>(k, src, dst, st);
+  if (dp == LQCD_F64)
+    conv_ne<RS, NS, double>(k, src, dst, df, st);
+  else
+    conv_ne<RS, NS, float>(k, src, dst, df, st);
+}
+
+template <typename RS>
+void conv_src(const KGeom& k, const void* src, int sf, void* dst, int dp, int df,
+              hipStream_t st) {
+  switch (ne_of(sf)) {
+    case 6: conv_dst<RS, 6>(k, src, dst, dp, df, st); break;
+    case 7: conv_dst<RS, 7>(k, src, dst, dp, df, st); break;
+    case 8: conv_dst<RS, 8>(k, src, dst, dp, df, st); break;
+    default: conv_dst<RS, 9>(k, src, dst, dp, df, st); break;
   }
 }
 
@@ -175,15 +243,10 @@ void conv_dst(const KGeom& k, const void* src, void* dst, int dp, int df, hipStr
 
 int convert_links_async(const KGeom& k, const void* src, int sp, int sf, void* dst, int dp,
                         int df, hipStream_t st) {
-  if (sp == LQCD_F64) {
-    if (sf == LQCD_LINKS12) conv_dst<double, 6>(k, src, dst, dp, df, st);
-    else if (sf == LQCD_LINKS12D) conv_dst<double, 7>(k, src, dst, dp, df, st);
-    else conv_dst<double, 9>(k, src, dst, dp, df, st);
-  } else {
-    if (sf == LQCD_LINKS12) conv_dst<float, 6>(k, src, dst, dp, df, st);
-    else if (sf == LQCD_LINKS12D) conv_dst<float, 7>(k, src, dst, dp, df, st);
-    else conv_dst<float, 9>(k, src, dst, dp, df, st);
-  }
+  if (sp == LQCD_F64)
+    conv_src<double>(k, src, sf, dst, dp, df, st);
+  else
+    conv_src<float>(k, src, sf, dst, dp, df, st);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
@@ -208,17 +271,44 @@ int lqcd_pack_links(const lqcd_geom* g, const void* U_nat, int prec, int fmt, vo
 #define LQCD_PACK(R, NE)                                                                  \
   hipLaunchKernelGGL((k_pack_links<R, NE>), dim3(grid), dim3(kBlock), 0, s, k, src,       \
                      (cplx<R>*)U_packed)
-  const int ne = fmt == LQCD_LINKS12 ? 6 : fmt == LQCD_LINKS12D ? 7 : 9;
+  const int ne = ne_of(fmt);
   if (prec == LQCD_F64) {
     if (ne == 9) LQCD_PACK(double, 9);
     else if (ne == 6) LQCD_PACK(double, 6);
-    else LQCD_PACK(double, 7);
+    else if (ne == 7) LQCD_PACK(double, 7);
+    else LQCD_PACK(double, 8);
   } else {
     if (ne == 9) LQCD_PACK(float, 9);
     else if (ne == 6) LQCD_PACK(float, 6);
-    else LQCD_PACK(float, 7);
+    else if (ne == 7) LQCD_PACK(float, 7);
+    else LQCD_PACK(float, 8);
   }
 #undef LQCD_PACK
+  LQCD_LAUNCH_CHECK();
+  return LQCD_OK;
+}
+
+int lqcd_pack_links_u1(const lqcd_geom* g, const void* U64, const double* theta, int prec,
+                       void* out, void* stream) {
+  clear_error();
+  int st;
+  if ((st = check_geom(g)) || (st = check_prec_fmt(prec, LQCD_LINKS12T)) ||
+      (st = check_ptr(U64, "U64")) || (st = check_ptr(theta, "theta")) ||
+      (st = check_ptr(out, "out")))
+    return st;
+  if (out == U64 || static_cast<const void*>(theta) == out) {
+    set_error("lqcd_pack_links_u1: out must not alias U64 or theta");
+    return LQCD_ERR_INVALID_ARG;
+  }
+  const KGeom k = make_kgeom(g);
+  const unsigned grid = grid_for(int64_t(8) * k.Vh);
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == LQCD_F64)
+    hipLaunchKernelGGL(k_pack_links_u1<double>, dim3(grid), dim3(kBlock), 0, s, k,
+                       (const double2*)U64, theta, (double2*)out);
+  else
+    hipLaunchKernelGGL(k_pack_links_u1<float>, dim3(grid), dim3(kBlock), 0, s, k,
+                       (const double2*)U64, theta, (float2*)out);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }

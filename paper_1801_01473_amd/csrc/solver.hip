@@ -771,12 +771,12 @@ Layout make_layout(const KGeom& g, const lqcd_solver_params& p, int nshift, int 
   L.pres = take(nparts * 8);
   L.resn = take(size_t(nrhs) * nshift * 8);
   L.has_links = !(iprec == LQCD_F64 && ifmt == LQCD_LINKS18);
-  L.links = L.has_links ? take(size_t(8) * link_elems(ifmt) * g.Vh * 2 * ri) : 0;
+  L.links = L.has_links ? take(size_t(8) * link_reals(ifmt) * g.Vh * ri) : 0;
   // the FP64 opening phase streams FP64 links in the inner format (12-real:
   // a third fewer link bytes than the 18-real copy used for residuals;
   // 12-real + determinant for links with U(1) phases)
   L.links_pre =
-      (L.has_pre && ifmt != LQCD_LINKS18) ? take(size_t(8) * link_elems(ifmt) * g.Vh * 16) : 0;
+      (L.has_pre && ifmt != LQCD_LINKS18) ? take(size_t(8) * link_reals(ifmt) * g.Vh * 8) : 0;
   // deferred shift updates: base directions and window coefficients
   if (L.win > 1) {
     L.pc = take(nrhs * vin);

@@ -37,12 +37,38 @@ __device__ __forceinline__ void reconstruct_row2_det(Su3<R>& u) {
   u.e[8] = cmul<R>(d, c2);
 }
 
-// The full matrix from the NE stored elements (9: as is; 6: SU(3) rows 0-1;
-// 7: rows 0-1 and the determinant).
+// NE = 8 names the U(1)-angle format (LQCD_LINKS12T): rows 0-1 of the SU(3)
+// part as six complex planes, then the angle theta as one plane of reals.
+// Complex planes holding stored elements, and complex numbers in one
+// [parity][mu] block of Vh links (Vh is a multiple of 8).
+template <int NE>
+__host__ __device__ constexpr int stored_planes() { return NE == 8 ? 6 : NE; }
+template <int NE>
+__host__ __device__ __forceinline__ int64_t link_block(int Vh) {
+  return NE == 8 ? int64_t(13) * (Vh / 2) : int64_t(NE) * Vh;
+}
+
+// The full matrix from the stored elements (9: as is; 6: SU(3) rows 0-1;
+// 7: rows 0-1 and the determinant; 8: the SU(3) part of rows 0-1, whose
+// U(1) factor apply_u1 adds).
 template <typename R, int NE>
 __device__ __forceinline__ void complete_link(Su3<R>& u) {
-  if constexpr (NE == 6) reconstruct_row2<R>(u);
+  if constexpr (NE == 6 || NE == 8) reconstruct_row2<R>(u);
   if constexpr (NE == 7) reconstruct_row2_det<R>(u);
+}
+
+// u <- (cos theta + i sin theta) u: the U(1) phase recomputed from its angle
+// (Sec. 4.1), with the library's sincos.
+template <typename R>
+__device__ __forceinline__ void apply_u1(Su3<R>& u, R theta) {
+  R sn, cs;
+  if constexpr (sizeof(R) == 4)
+    sincosf(theta, &sn, &cs);
+  else
+    sincos(theta, &sn, &cs);
+  const cplx<R> ph = mk<R>(cs, sn);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u.e[e] = cmul<R>(ph, u.e[e]);
 }
 
 // Buffer resources: a scalar 64-bit base and byte range for a whole array
@@ -61,6 +87,15 @@ __device__ __forceinline__ cplx<R> ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t vof
     return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
   else
     return __builtin_bit_cast(cplx<R>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+}
+
+// One real through a buffer resource (the angle plane of LQCD_LINKS12T).
+template <typename R, int AUX = 0>
+__device__ __forceinline__ R ld_buf_real(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
+  else
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
 }
 
 // Streaming access to a complex value that is read or written once: the
@@ -99,13 +134,14 @@ __device__ __forceinline__ void st_once(cplx<R>* p, cplx<R> z) {
   }
 }
 
-// Load the link with half index h from a packed [NE][Vh] block.
+// Load the link with half index h from one packed [parity][mu] block.
 template <typename R, int NE>
 __device__ __forceinline__ void load_link(const cplx<R>* __restrict__ base, int h, int Vh,
                                           Su3<R>& u) {
 #pragma unroll
-  for (int e = 0; e < NE; ++e) u.e[e] = base[int64_t(e) * Vh + h];
+  for (int e = 0; e < stored_planes<NE>(); ++e) u.e[e] = base[int64_t(e) * Vh + h];
   complete_link<R, NE>(u);
+  if constexpr (NE == 8) apply_u1<R>(u, reinterpret_cast<const R*>(base + int64_t(6) * Vh)[h]);
 }
 
 // y = U v

@@ -71,6 +71,11 @@ def test_buffer_sizes_match_paper_byte_counts(lq):
     assert 2 * per_site == gold["gauge_12real_fp64_bytes_per_unit_surface_thickness2"]
     assert lq.links_bytes(g, lq.F64, lq.LINKS18) == 4 * 18 * 8 * g.V
     assert lq.links_bytes(g, lq.F32, lq.LINKS12) == 4 * 12 * 4 * g.V
+    # rows 0-1 and the determinant: 14 reals; rows 0-1 and the U(1) angle: 13
+    assert lq.links_bytes(g, lq.F32, lq.LINKS12D) == 4 * 14 * 4 * g.V
+    assert lq.links_bytes(g, lq.F64, lq.LINKS12T) == 4 * 13 * 8 * g.V
+    assert lq.empty_links(g, lq.F32, lq.LINKS12T, "cpu").numel() * 8 == lq.links_bytes(
+        g, lq.F32, lq.LINKS12T)
 
 
 @pytest.mark.parametrize("L", [(3, 4, 4, 4), (4, 4, 4, 0), (4, 4, 4, 1), (4, -2, 4, 4)])
@@ -110,7 +115,7 @@ def test_bad_arguments_are_rejected(lq):
               None) == 1
     assert fn(g.c(), 2, 0, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48), 1,
               None) == 1
-    assert fn(g.c(), 0, 3, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48), 1,
+    assert fn(g.c(), 0, 4, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48), 1,
               None) == 1
     assert fn(g.c(), 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48), 0,
               None) == 1
@@ -304,6 +309,12 @@ def test_pack_stencil_and_cg_validation(lq):
     rejected(pl, g.c(), v(256), 0, 9, v(1024), None)
     rejected(pl, g.c(), None, 0, 0, v(1024), None, msg="U_nat")
     rejected(pl, g.c(), v(256), 0, 0, v(1025), None, msg="aligned")
+    pu = "lqcd_pack_links_u1"
+    rejected(pu, g.c(), None, v(512), 1, v(1024), None, msg="U64")
+    rejected(pu, g.c(), v(256), None, 1, v(1024), None, msg="theta")
+    rejected(pu, g.c(), v(256), v(512), 2, v(1024), None)
+    rejected(pu, g.c(), v(256), v(512), 1, v(256), None, msg="alias")
+    rejected(pu, bad, v(256), v(512), 1, v(1024), None)
     cl = "lqcd_convert_links"
     rejected(cl, g.c(), v(256), 0, 0, v(256), 1, 1, None, msg="different")
     rejected(cl, g.c(), v(256), 0, 0, v(1024), 1, 7, None)

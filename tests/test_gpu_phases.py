@@ -121,6 +121,81 @@ def test_links12d_round_trip_and_dslash(lq):
     assert H.max_rel(bad, ref) > 1e-3
 
 
+def test_links12t_flavour_angles_and_dslash(lq):
+    """The paper's U(1) storage: SU(3) rows 0-1 plus one angle per link, the
+    phase recomputed in the operator.  Built per flavour from the shared SU(3)
+    field and that flavour's angles, or converted from phased links (angle =
+    arg det / 3): round trip to the phased links, D_oe in FP64 and FP32 against
+    the oracle on u U, for two flavours with different charges."""
+    L = (6, 4, 4, 8)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 816)
+    U64 = lq.pack_links(g, cu(U))
+    f = synth.gaussian_even_source(L, 3, 817)
+    fo = synth.gaussian_field(L, 3, 822)
+    fo[:, synth.site_parity(L) == 0, :] = 0.0
+    for charge in (1.0, -2.0 / 3.0):
+        th = charge * (synth.u1_phases_magnetic(L, 3) + synth.u1_phases_chemical(L, 0.45))
+        Up_ref = oracle.phase_links(U, th)
+        ref = np.stack([oracle.doe(L, Up_ref, f[j]) for j in range(3)])
+        Up = lq.apply_u1_phases(g, U64, cu(th))
+        for prec, tol in ((lq.F64, 1e-13), (lq.F32, 1e-6)):
+            Ut = lq.pack_links_u1(g, U64, cu(th), prec)
+            back = lq.convert_links(g, Ut, prec, lq.LINKS12T, lq.F64, lq.LINKS18)
+            assert H.max_rel(host(lq.unpack_links(g, back)), Up_ref) <= (
+                1e-14 if prec == lq.F64 else 1e-6)
+            got = host(lq.unpack_spinor(g, lq.doe(g, Ut, lq.pack_spinor(g, cu(f), 0, prec)), 1))
+            assert H.max_rel(got, ref) <= tol, (charge, prec)
+            Uc = lq.convert_links(g, Up, lq.F64, lq.LINKS18, prec, lq.LINKS12T)
+            got = host(lq.unpack_spinor(g, lq.deo(g, Uc, lq.pack_spinor(g, cu(fo), 1, prec)), 0))
+            ref_eo = np.stack([oracle.deo(L, Up_ref, fo[j]) for j in range(3)])
+            assert H.max_rel(got, ref_eo) <= tol, (charge, prec)
+        Ub = lq.pack_links(g, cu(Up_ref), lq.F64, lq.LINKS12T)
+        assert H.max_rel(host(lq.unpack_links(
+            g, lq.convert_links(g, Ub, lq.F64, lq.LINKS12T, lq.F64, lq.LINKS18))), Up_ref) <= 1e-14
+
+
+@pytest.mark.parametrize("cfg", ["64,1,0,0", "128,2,1,2,1,0,0,1,1,2", "256,8,1,4,1,3,0,0,1,0,1",
+                                 "128,4,0,2,1,0,1,0,0,2,1"])
+def test_links12t_every_launch_configuration(lq, cfg, monkeypatch):
+    monkeypatch.setenv("LQCD_DSLASH_CFG", cfg)
+    L = (6, 4, 8, 6)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 818)
+    th = synth.u1_phases_chemical(L, -0.7) + synth.u1_phases_magnetic(L, 2)
+    Up_ref = oracle.phase_links(U, th)
+    Ul = lq.pack_links_u1(g, lq.pack_links(g, cu(U)), cu(th), lq.F32)
+    f = synth.gaussian_field(L, 5, 819)
+    got = host(lq.unpack_spinor(g, lq.deo(g, Ul, lq.pack_spinor(g, cu(f), 1, lq.F32)), 0))
+    ref = np.stack([oracle.deo(L, Up_ref, f[j]) for j in range(5)])
+    assert H.max_rel(got, ref) <= 1e-6
+
+
+def test_multishift_phased_links12t_inner(lq):
+    """Mixed precision with the angle format as the inner links (converted by
+    the solver from the FP64 phased links, also for its FP64 opening phase),
+    and with the caller's per-flavour angle links as the inner copy: every
+    (rhs, shift) <= 1e-10 by the oracle's true residual."""
+    L = (8, 8, 8, 8)
+    g = lq.Geometry(L)
+    U = synth.links_haar(L, 820)
+    th = synth.u1_phases_chemical(L, 0.5) + synth.u1_phases_magnetic(L, 1)
+    Up_ref = oracle.phase_links(U, th)
+    U64 = lq.pack_links(g, cu(U))
+    Up = lq.apply_u1_phases(g, U64, cu(th))
+    b = synth.gaussian_even_source(L, 2, 821)
+    sig = synth.rational_shifts(6, 1e-3, 1.0)
+    m = 0.05
+    p = lq.solver_params(mass=m, tol=1e-10, inner_prec=lq.F32, inner_fmt=lq.LINKS12T)
+    for Uin in (None, lq.pack_links_u1(g, U64, cu(th), lq.F32)):
+        X, _, stats = lq.cg_multishift(g, p, Up, sig, lq.pack_spinor(g, cu(b), 0), Uinner=Uin)
+        Xn = host(lq.unpack_spinor(g, X.reshape(-1, 3, g.Vh), 0)).reshape(2, len(sig), -1, 3)
+        for j in range(2):
+            for i, s in enumerate(sig):
+                assert oracle.true_residual(L, Up_ref, m, s, b[j], Xn[j, i]) <= 1e-10
+        assert all(s["converged"] == 1 for row in stats for s in row)
+
+
 @pytest.mark.parametrize("cfg", ["64,1,0,0", "128,2,1,2,1,0,0,1,1,2", "256,8,1,4,1,3,0,0,1,0,1",
                                  "128,4,0,2,1,0,1,0,0,2,1", "64,8,0,0,0,2,0,1,0,0"])
 def test_links12d_every_launch_configuration(lq, cfg, monkeypatch):
@@ -174,7 +249,8 @@ def test_phased_dslash_at_workload_size(lq):
     ref = oracle.doe(L, Up_ref, f[0])[None]
     del Up_ref
     for prec, fmt, tol in ((lq.F64, lq.LINKS18, 1e-13), (lq.F64, lq.LINKS12D, 1e-13),
-                           (lq.F32, lq.LINKS12D, 1e-6)):
+                           (lq.F32, lq.LINKS12D, 1e-6), (lq.F64, lq.LINKS12T, 1e-13),
+                           (lq.F32, lq.LINKS12T, 1e-6)):
         Ul = Up if (prec, fmt) == (lq.F64, lq.LINKS18) else lq.convert_links(
             g, Up, lq.F64, lq.LINKS18, prec, fmt)
         got = host(lq.unpack_spinor(g, lq.doe(g, Ul, lq.pack_spinor(g, cu(f), 0, prec)), 1))
