@@ -102,6 +102,13 @@ inline size_t dslash_partials_max(const KGeom& g, int nrhs) {
 
 int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);
 
+// k_dslash for one precision R and link format NE (6: 12-real, 7: 12-real and
+// determinant, 8: 12-real and U(1) angle, 9: 18-real), instantiated in
+// dslash_inst_*.hip; and the FP64 residual mode on 18-real links.
+template <typename R, int NE>
+int dslash_launch_fmt(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);
+int dslash_launch_res(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);
+
 // The t-march kernel family (dslash_tm.hip).
 bool dslash_tm_supported(const DslashCall& c, const DslashCfg& cfg);
 int dslash_tm_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);

@@ -1,0 +1,8 @@
+// k_dslash instantiations: FP64, 12-real + determinant links.
+#include "dslash_kernel.h"
+
+namespace lqcd {
+
+template int dslash_launch_fmt<double, 7>(const DslashCall&, const DslashCfg&, hipStream_t);
+
+}  // namespace lqcd
