@@ -396,6 +396,51 @@ def force_roofline(lq, torch, g, U64, al, X):
                 flops / 78.6e12 > byts / 8e12 else "hbm")
 
 
+def stencil_ab(lq, torch):
+    """A/B of the FP32 12-real 8-RHS D_oe at 48^4 (Haar links, seed 104, random
+    right-hand sides): the tuned k_dslash against the t-march and matrix-core
+    variants pinned in several launch shapes; 3 warm-ups + 20 event-timed
+    launches each, the largest relative difference to the tuned result, and
+    the tuned configuration (read back from a private tuning-cache file)."""
+    import tempfile
+    import synth
+    L = (48, 48, 48, 48)
+    g = lq.Geometry(L)
+    U64 = lq.pack_links(g, torch.from_numpy(synth.links_haar(L, 104)).to("cuda"))
+    Ul = lq.convert_links(g, U64, lq.F64, lq.LINKS18, lq.F32, lq.LINKS12)
+    del U64
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    x = torch.randn(8, 3, g.Vh, dtype=torch.complex64, device="cuda", generator=gen)
+    cache = os.path.join(tempfile.mkdtemp(), "tune.txt")
+    os.environ["LQCD_TUNE_CACHE"] = cache
+    byts = g.Vh * dslash_bytes_per_site(lq.F32, lq.LINKS12, 8)
+    runs = [("tuned", None),
+            ("t_march_tm6_tp2_b64", "64,8,1,0,1,0,0,0,0,0,1,6,2"),
+            ("t_march_tm12_tp4_b128", "128,8,1,0,1,0,0,0,0,0,1,12,4"),
+            ("mfma_b256_lex", "256,8,1,0,1,0,0,0,0,0,1,0,2,1"),
+            ("mfma_b256_tz6", "256,8,1,6,1,0,0,0,0,0,1,0,2,1"),
+            ("mfma_b128_tz6_ty24", "128,8,1,6,1,0,0,0,0,24,1,0,2,1"),
+            ("mfma_b64_tz12_ty24", "64,8,1,12,1,0,0,0,0,24,1,0,2,1")]
+    out, ref = {}, None
+    for name, cfg in runs:
+        if cfg:
+            os.environ["LQCD_DSLASH_CFG"] = cfg
+        else:
+            os.environ.pop("LQCD_DSLASH_CFG", None)
+        y = torch.empty_like(x)
+        ms = event_time_ms(lambda: lq.doe(g, Ul, x, out=y), 20)
+        if ref is None:
+            ref = y
+        d = float(((y - ref).abs().max() / ref.abs().max()).item())
+        out[name] = dict(cfg=cfg, us=1000 * ms, GBps=byts / (ms * 1e-3) / 1e9,
+                         max_rel_diff_vs_tuned=d)
+        log(f"stencil A/B {name}: {1000 * ms:.1f} us, diff {d:.1e}")
+    os.environ.pop("LQCD_DSLASH_CFG", None)
+    os.environ.pop("LQCD_TUNE_CACHE", None)
+    out["tuned"]["cfg"] = open(cache).read().strip().split(";")[-1] if os.path.exists(cache) else None
+    return out
+
+
 def cpu_baseline(w, U, phi, sig, gpu_iters_per_rhs, gpu_shift_updates_per_rhs, X0=None,
                  budget_s=20.0):
     """Oracle multi-shift CG timed on a bounded sample: a few iterations on one
@@ -495,6 +540,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c4")
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--stencil-ab", action="store_true",
+                    help="only the 48^4 FP32 8-RHS D_oe A/B: tuned VALU stencil vs the "
+                         "t-march and matrix-core variants")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rhmc", action="store_true",
                     help="skip the RHMC heatbath / action measurement")
@@ -517,6 +565,9 @@ def main():
         print("bench.py needs a GPU", flush=True)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.stencil_ab:
+        print(json.dumps({"stencil_ab": stencil_ab(lq, torch)}), flush=True)
+        return
     w = WORKLOADS[args.workload]
     L = w["L"]
     g = lq.Geometry(L)

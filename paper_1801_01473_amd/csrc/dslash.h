@@ -73,6 +73,8 @@ struct DslashCfg {
   int tm = 0;       // > 0: march along t, tm slices per thread (k_dslash_tm; needs
                     // rhs_block 8, 12-real links, tz = ty = ilv = lf = hh = 0, nt = ns = 1)
   int tp = 2;       // t-march: lanes per column sharing its eight right-hand sides (2 or 4)
+  int mf = 0;       // 1: the matrix-core contraction (k_dslash_mfma; FP32, 12-real, plain
+                    // mode, rhs_block 8, tm = 0); pinned only, never picked by the tuner
 };
 
 // Dynamic LDS a workgroup reserves so that at most occ waves per SIMD are resident.
@@ -112,6 +114,10 @@ int dslash_launch_res(const DslashCall& c, const DslashCfg& cfg, hipStream_t st)
 // The t-march kernel family (dslash_tm.hip).
 bool dslash_tm_supported(const DslashCall& c, const DslashCfg& cfg);
 int dslash_tm_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);
+
+// The matrix-core variant (dslash_mfma.hip).
+bool dslash_mfma_supported(const DslashCall& c, const DslashCfg& cfg);
+int dslash_mfma_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st);
 
 // Tuned configuration for this call's shape (times candidates on first use
 // with private scratch buffers; cached per process).  `forced_rhs_block` > 0

@@ -24,6 +24,7 @@ int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     return LQCD_ERR_UNSUPPORTED;
   }
   if (cfg.tm > 0) return dslash_tm_launch(c, cfg, st);
+  if (cfg.mf == 1) return dslash_mfma_launch(c, cfg, st);
   if (cfg.tz < 0 || (cfg.tz > 0 && c.g.Lz % cfg.tz != 0) || cfg.ty < 0 ||
       (cfg.ty > 0 && c.g.Ly % cfg.ty != 0)) {
     set_error("tile %d x %d (y, z) must divide Ly = %d, Lz = %d", cfg.ty, cfg.tz, c.g.Ly, c.g.Lz);
@@ -165,20 +166,22 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     set_error("rhs_block must be 0 (tuned), 1, 2, 4 or 8, got %d", forced);
     return LQCD_ERR_INVALID_ARG;
   }
-  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty,ns,tm,tp]" pins the
-  // configuration (testing, profiling).  A t-march configuration applies only
-  // where that kernel exists (8 right-hand sides or more, 12-real links, the
-  // plain and fused modes); other calls fall back to its k_dslash settings.
+  // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty,ns,tm,tp,mf]" pins the
+  // configuration (testing, profiling).  A t-march or matrix-core configuration
+  // applies only where that kernel exists (t-march: 8 right-hand sides or more,
+  // 12-real links, the plain and fused modes; matrix cores: FP32, 12-real, plain
+  // mode without norms); other calls fall back to its k_dslash settings.
   if (const char* e = std::getenv("LQCD_DSLASH_CFG")) {
     DslashCfg f;
-    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block, &f.xcd,
-                    &f.tz, &f.nt, &f.occ, &f.ilv, &f.lf, &f.hh, &f.ty, &f.ns, &f.tm,
-                    &f.tp) >= 4) {
+    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &f.block, &f.rhs_block,
+                    &f.xcd, &f.tz, &f.nt, &f.occ, &f.ilv, &f.lf, &f.hh, &f.ty, &f.ns, &f.tm,
+                    &f.tp, &f.mf) >= 4) {
       if (forced) f.rhs_block = forced;
       if (f.tm > 0 && (c.nrhs < 8 || !dslash_tm_supported(c, f))) {
         f.tm = 0;
         if (f.rhs_block > c.nrhs) f.rhs_block = 1;
       }
+      if (f.mf == 1 && !dslash_mfma_supported(c, f)) f.mf = 0;
       *out = f;
       return LQCD_OK;
     }

@@ -270,6 +270,30 @@ def test_t_march_configurations(lq, cfg, prec, tol, nrhs, monkeypatch):
     assert H.max_rel(got, ref) <= tol
 
 
+@pytest.mark.parametrize("cfg", ["256,8,1,0,1,0,0,0,0,0,1,0,2,1", "128,8,0,6,1,0,0,0,0,0,1,0,2,1",
+                                 "64,8,1,2,1,0,0,0,0,4,1,0,2,1"])
+@pytest.mark.parametrize("nrhs", [8, 11])
+def test_matrix_core_stencil(lq, cfg, nrhs, monkeypatch):
+    """The matrix-core contraction (one quad of lanes per site, the hop as a
+    real 6x6 by 6x8 product on 4x4x1 MFMA blocks), FP32 12-real, eight
+    right-hand sides per group (11: a ragged second group), plain and tiled
+    traversals, a lattice whose site count is not a multiple of the
+    workgroup's sites: D_oe and D_eo against the oracle."""
+    monkeypatch.setenv("LQCD_DSLASH_CFG", cfg)
+    L = (6, 4, 12, 6)
+    g = lq.Geometry(L)
+    U = _links(L, "haar", 75)
+    f = synth.gaussian_field(L, nrhs, 76)
+    Up = lq.pack_links(g, cu(U), lq.F32, lq.LINKS12)
+    fr = f.astype(np.complex64).astype(np.complex128)
+    got = host(lq.unpack_spinor(g, lq.doe(g, Up, lq.pack_spinor(g, cu(f), 0, lq.F32)), 1))
+    ref = np.stack([oracle.doe(L, U, fr[j]) for j in range(nrhs)])
+    assert H.max_rel(got, ref) <= 1e-6
+    got = host(lq.unpack_spinor(g, lq.deo(g, Up, lq.pack_spinor(g, cu(f), 1, lq.F32)), 0))
+    ref = np.stack([oracle.deo(L, U, fr[j]) for j in range(nrhs)])
+    assert H.max_rel(got, ref) <= 1e-6
+
+
 def test_t_march_invalid_configuration_falls_back(lq, monkeypatch):
     """A t-march chunk that does not divide Lt is not launched: the call runs
     k_dslash with the remaining settings and still gives the oracle's result."""
