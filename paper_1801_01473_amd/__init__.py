@@ -131,6 +131,9 @@ _SIGS = {
     "lqcd_gauge_workspace_bytes": (ctypes.c_size_t, [_gp]),
     "lqcd_gauge_action": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _dp, _vp, ctypes.c_size_t, _vp]),
     "lqcd_gauge_force": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
+    "lqcd_gauge_force_staples_workspace_bytes": (ctypes.c_size_t, [_gp]),
+    "lqcd_gauge_force_staples": (ctypes.c_int, [_gp, _vp, _dbl, _dbl, _i32, _vp, _vp,
+                                                ctypes.c_size_t, _vp]),
     "lqcd_md_update_momenta": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _vp]),
     "lqcd_md_update_links": (ctypes.c_int, [_gp, _vp, _dbl, _vp, _vp]),
     "lqcd_kinetic_energy": (ctypes.c_int, [_gp, _vp, _dp, _vp, ctypes.c_size_t, _vp]),
@@ -685,13 +688,24 @@ def gauge_action(geom: Geometry, U64, beta: float, c1: float = SYMANZIK_C1) -> f
 
 
 def gauge_force(geom: Geometry, U64, beta: float, c1: float = SYMANZIK_C1, out=None,
-                accumulate=False):
-    """F = TA(U M) of S_g, packed like the links; accumulate adds into out."""
+                accumulate=False, method: str = "staples"):
+    """F = TA(U M) of S_g, packed like the links; accumulate adds into out.
+    method "staples": through stored plaquette-staple fields (workspace);
+    "direct": every staple of every link multiplied out in place."""
     _u64_arg(geom, U64)
     out = empty_links(geom, F64, LINKS18, U64.device) if out is None else out
     _real_links_out(geom, out, "out")
-    _check(_fn("lqcd_gauge_force")(geom.c(), _ptr(U64), float(beta), float(c1),
-                                   1 if accumulate else 0, _ptr(out), _stream()))
+    if method == "direct":
+        _check(_fn("lqcd_gauge_force")(geom.c(), _ptr(U64), float(beta), float(c1),
+                                       1 if accumulate else 0, _ptr(out), _stream()))
+    elif method == "staples":
+        nbytes = int(_fn("lqcd_gauge_force_staples_workspace_bytes")(geom.c()))
+        ws = _workspace(nbytes, U64.device)
+        _check(_fn("lqcd_gauge_force_staples")(geom.c(), _ptr(U64), float(beta), float(c1),
+                                               1 if accumulate else 0, _ptr(out), _ptr(ws),
+                                               ws.numel(), _stream()))
+    else:
+        raise ValueError(f"unknown gauge force method {method!r}")
     return out
 
 

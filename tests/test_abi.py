@@ -309,6 +309,14 @@ def test_pack_stencil_and_cg_validation(lq):
     rejected(pl, g.c(), v(256), 0, 9, v(1024), None)
     rejected(pl, g.c(), None, 0, 0, v(1024), None, msg="U_nat")
     rejected(pl, g.c(), v(256), 0, 0, v(1025), None, msg="aligned")
+    gs = "lqcd_gauge_force_staples"
+    need = lq._fn("lqcd_gauge_force_staples_workspace_bytes")(g.c())
+    assert need == 4 * 2 * 9 * g.Vh * 16
+    rejected(gs, g.c(), v(256), 1.0, 0.0, 0, v(1024), v(4096), need - 1, None,
+             code=lq.ERR_WORKSPACE)
+    rejected(gs, g.c(), v(256), 1.0, 0.0, 2, v(1024), v(4096), need, None)
+    rejected(gs, g.c(), v(256), 1.0, 0.0, 0, v(1024), v(1024), need, None, msg="distinct")
+    rejected(gs, g.c(), v(256), 1.0, 0.0, 0, v(1024), None, need, None, msg="ws")
     pu = "lqcd_pack_links_u1"
     rejected(pu, g.c(), None, v(512), 1, v(1024), None, msg="U64")
     rejected(pu, g.c(), v(256), None, 1, v(1024), None, msg="theta")

@@ -40,7 +40,11 @@ LATS = [(4, 4, 4, 4), (2, 2, 2, 2), (4, 2, 6, 4), (6, 4, 4, 8)]
 
 @pytest.mark.parametrize("L", LATS)
 @pytest.mark.parametrize("c1", [C1, 0.0])
-def test_gauge_action_and_force_vs_oracle(lq, L, c1):
+@pytest.mark.parametrize("method", ["staples", "direct"])
+def test_gauge_action_and_force_vs_oracle(lq, L, c1, method):
+    """Action and force against the oracle's loop enumeration, for the force
+    through staple fields and the direct per-link staple sum, on lattices
+    with extents 2 (loops wrapping onto themselves), Symanzik and Wilson."""
     g = lq.Geometry(L)
     U = synth.links_exp(L, 0.7, 501)
     U64 = lq.pack_links(g, cu(U))
@@ -48,17 +52,30 @@ def test_gauge_action_and_force_vs_oracle(lq, L, c1):
     S = lq.gauge_action(g, U64, beta, c1)
     Sref = oracle.gauge_action(L, U, beta, c1)
     assert abs(S - Sref) <= 1e-12 * abs(Sref)
-    F = host(lq.unpack_links(g, lq.gauge_force(g, U64, beta, c1)))
+    F = host(lq.unpack_links(g, lq.gauge_force(g, U64, beta, c1, method=method)))
     assert H.max_rel(F, oracle.gauge_force(L, U, beta, c1)) <= 1e-12
 
 
-def test_gauge_force_accumulates(lq):
+@pytest.mark.parametrize("method", ["staples", "direct"])
+def test_gauge_force_accumulates(lq, method):
     L = (4, 4, 4, 4)
     g = lq.Geometry(L)
     U64 = lq.pack_links(g, cu(synth.links_haar(L, 502)))
-    F1 = lq.gauge_force(g, U64, 2.0)
-    F2 = lq.gauge_force(g, U64, 2.0, out=F1.clone(), accumulate=True)
+    F1 = lq.gauge_force(g, U64, 2.0, method=method)
+    F2 = lq.gauge_force(g, U64, 2.0, out=F1.clone(), accumulate=True, method=method)
     assert (F2 - 2 * F1).abs().max().item() <= 1e-14 * F1.abs().max().item()
+
+
+def test_gauge_force_methods_agree_at_workload_size(lq):
+    """48^4 (the workload lattice), links exp(0.5 i H): the force through
+    staple fields equals the direct staple sum on every link (both are
+    checked against the oracle on the small lattices above)."""
+    L = (48, 48, 48, 48)
+    g = lq.Geometry(L)
+    U64 = lq.pack_links(g, cu(synth.links_exp(L, 0.5, 519)))
+    Fd = lq.gauge_force(g, U64, 5.0, method="direct")
+    Fs = lq.gauge_force(g, U64, 5.0, method="staples")
+    assert ((Fs - Fd).abs().max() / Fd.abs().max()).item() <= 1e-13
 
 
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (2, 4, 2, 6)])
