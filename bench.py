@@ -23,6 +23,11 @@ solves of the same systems, D_oe/D_eo bandwidth against the 8 TB/s peak and a
 STREAM ceiling, the roofline of the dominant kernel measured with HIP events,
 and the CPU oracle timed on a bounded sample.
 
+Stencil launch configurations start from the shipped MI355X tuning cache
+(paper_1801_01473_amd/tune/gfx950_256cu.txt, written by the stencil tuner on
+an MI355X; shapes it lacks are tuned during the warm-up step); --retune tunes
+every shape from scratch, LQCD_TUNE_CACHE=<file> uses the caller's cache.
+
 --profile-kernels runs one warm mixed solve of the workload, one measured solve
 bracketed by small copy launches (markers in the dispatch list), standalone D_oe
 launches and a copy kernel of known size (for rocprofv3 counter collection)
@@ -180,25 +185,57 @@ def kernel_table(g, nrhs, stats, ktimes):
     return out
 
 
-def measured_traffic(kernel_class):
+SHIPPED_TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                  "paper_1801_01473_amd", "tune", "gfx950_256cu.txt")
+
+# tuning-cache key fields (precision, link format, mode) of the solve's kernel classes
+KERNEL_CLASS_KEY = {"dslash_eo_cg_f32": (1, 1, 2), "dslash_oe_f32": (1, 1, 0),
+                    "dslash_eo_cg_f64": (0, 1, 2), "dslash_oe_f64": (0, 1, 0)}
+
+
+def tuned_config(cache, L, kernel_class, nrhs):
+    """The configuration the stencil tuner chose for a kernel class in this
+    run, read back from the tuning-cache file (the last entry for its key), or
+    None."""
+    base = kernel_class.rsplit("_", 1)[0]
+    if cache is None or base not in KERNEL_CLASS_KEY or not os.path.exists(cache):
+        return None
+    prec, fmt, mode = KERNEL_CLASS_KEY[base]
+    tail = f"/{L[0]}x{L[1]}x{L[2]}x{L[3]}/p{prec}/f{fmt}/n{nrhs}/b0/m{mode}"
+    found = None
+    with open(cache) as f:
+        for line in f:
+            key, _, cfg = line.strip().partition(";")
+            if key.endswith(tail):
+                found = cfg
+    return found
+
+
+def measured_traffic(kernel_class, cfg):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE passes, or None when the dominant kernel is another
-    one or the stencil sources changed since the counters were taken."""
+    FETCH_SIZE / WRITE_SIZE passes, with a note.  The bytes are None when the
+    dominant kernel is another one, when the stencil sources changed since the
+    counters were taken, or when the tuner chose another configuration in this
+    run than in the counter runs (the traffic depends on the traversal)."""
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "dominant_kernel_traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, "no counter record"
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_class") != kernel_class:
-        return None
+        return None, f"counters are for {rec.get('kernel_class')}"
     h = hashlib.sha256()
     for src in rec["sources"]:
         with open(os.path.join(here, src), "rb") as f:
             h.update(f.read())
     if h.hexdigest() != rec["source_sha256"]:
-        return None
-    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+        return None, "stencil sources changed since the counters were taken"
+    if cfg != rec["tuned_configuration"]:
+        return None, (f"counters taken with configuration {rec['tuned_configuration']}, "
+                      f"this run tuned {cfg}")
+    return (rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"],
+            f"configuration {cfg}, as in the counter runs")
 
 
 def config3_m2(lq, torch):
@@ -550,6 +587,9 @@ def main():
     ap.add_argument("--rhmc-only", action="store_true",
                     help="only the RHMC measurements (heatbath, action, trajectory, gauge "
                          "force, stout smearing), for profiling them")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune every stencil shape from scratch instead of starting from "
+                         "the shipped MI355X tuning cache")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="one solve + standalone D_oe + copy kernel, for counter runs")
     args = ap.parse_args()
@@ -569,6 +609,22 @@ def main():
     if args.stencil_ab:
         print(json.dumps({"stencil_ab": stencil_ab(lq, torch)}), flush=True)
         return
+    # The tuner's choices are read back from the tuning cache: a private file
+    # unless the caller names one.  The private file starts from the shipped
+    # MI355X cache (the configurations the committed counters were taken
+    # with; its keys name gfx950 and 256 CUs, so other devices tune afresh),
+    # unless --retune asks for tuning from scratch.
+    tune_cache = os.environ.get("LQCD_TUNE_CACHE") or None
+    if tune_cache is None:
+        import atexit
+        import shutil
+        import tempfile
+        tmp = tempfile.mkdtemp()
+        atexit.register(shutil.rmtree, tmp, True)
+        tune_cache = os.path.join(tmp, "tune.txt")
+        if not args.retune:
+            shutil.copyfile(SHIPPED_TUNE_CACHE, tune_cache)
+        os.environ["LQCD_TUNE_CACHE"] = tune_cache
     w = WORKLOADS[args.workload]
     L = w["L"]
     g = lq.Geometry(L)
@@ -758,7 +814,8 @@ def main():
         rhmc = rhmc_heatbath(lq, torch, g, U64, w["mass"], nrhs)
         traj = rhmc_trajectory_bench(lq, torch, g, U64)
     kd = kernels[dominant]
-    traffic = measured_traffic(dominant)
+    dom_cfg = tuned_config(tune_cache, L, dominant, nrhs)
+    traffic, traffic_note = measured_traffic(dominant, dom_cfg)
     roof = {
         "kernel": f"{dominant} ({kd['kernel']})",
         "bound": "hbm",
@@ -769,7 +826,10 @@ def main():
         "traffic": traffic,
         "traffic_source": ("rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 per launch from "
                            "profiles/dominant_kernel_traffic.json, taken with the stencil "
-                           "sources whose sha256 it records (null when they changed)"),
+                           "sources whose sha256 it records and the tuned configuration it "
+                           "names (null when either differs)"),
+        "traffic_note": traffic_note,
+        "tuned_configuration": dom_cfg,
         "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
         "avg_launch_us": kd["avg_us"],
         "share_of_solve_kernel_time": kd["total_ms"] / sum(v["total_ms"] for v in kernels.values()),

@@ -188,17 +188,31 @@ def test_force_and_action_validation(lq):
     assert "S must be" in lq.last_error()
 
 
-def test_bench_traffic_record_is_tied_to_the_profiled_sources():
+def test_bench_traffic_record_is_tied_to_the_profiled_sources(tmp_path):
     """The bench reports the dominant kernel's counter traffic only for the
-    kernel class that was profiled and only while the stencil sources hash to
-    the profiled ones."""
+    kernel class that was profiled, only while the stencil sources hash to the
+    profiled ones and only when the tuner chose the profiled configuration;
+    the shipped tuning cache holds that configuration."""
     import json
     import bench
     rec = json.load(open(os.path.join(ROOT, "profiles", "dominant_kernel_traffic.json")))
     assert rec["read_bytes_per_launch"] > 0 and rec["write_bytes_per_launch"] > 0
-    assert bench.measured_traffic("not_the_profiled_kernel") is None
-    got = bench.measured_traffic(rec["kernel_class"])
-    assert got is None or got == rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    cfg = rec["tuned_configuration"]
+    assert bench.measured_traffic("not_the_profiled_kernel", cfg)[0] is None
+    assert bench.measured_traffic(rec["kernel_class"], "64,1,1,0,0,0,0,0,0,0,0,0,2")[0] is None
+    got, note = bench.measured_traffic(rec["kernel_class"], cfg)
+    assert got == rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"], note
+    # the configuration is read back from a tuning cache (last entry of the key)
+    L = (48, 48, 48, 48)
+    shipped = bench.tuned_config(bench.SHIPPED_TUNE_CACHE, L, rec["kernel_class"], 8)
+    assert shipped == cfg
+    cache = tmp_path / "tune.txt"
+    key = "v1/gfx950:sramecc+:xnack-/256cu/48x48x48x48/p1/f1/n8/b0/m2"
+    cache.write_text(f"{key};1,1,1,0,0,0,0,0,0,0\n{key};{cfg}\n"
+                     "v1/gfx950:sramecc+:xnack-/256cu/48x48x48x48/p1/f1/n8/b0/m0;2,2\n")
+    assert bench.tuned_config(str(cache), L, rec["kernel_class"], 8) == cfg
+    assert bench.tuned_config(str(cache), L, rec["kernel_class"], 4) is None
+    assert bench.tuned_config(None, L, rec["kernel_class"], 8) is None
 
 
 def test_gauge_phase_stout_and_rational_validation(lq):
