@@ -26,6 +26,7 @@
 #include "common.h"
 #include "solver.h"
 #include "su3.h"
+#include "tile.h"
 
 namespace lqcd {
 
@@ -74,12 +75,18 @@ __global__ void __launch_bounds__(kForceBlock) k_force(const KGeom g,
                                                        const double2* __restrict__ U,
                                                        const double2* __restrict__ X, int npf,
                                                        int nshift, const Alphas al, int mode,
-                                                       int accumulate,
+                                                       int accumulate, int ty, int tz,
                                                        double2* __restrict__ F) {
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int h = int(tid >> 2);  // odd site
+  // Every even X is read by its eight odd neighbours, for every pair, so the
+  // sites sharing neighbours run close together and on one XCD (one L2):
+  // consecutive blocks of an XCD take consecutive sites of a (y, z)-tiled
+  // order with t inside the tile.
+  const int lb = xcd_block(blockIdx.x, gridDim.x, 1);
+  const int64_t tid = int64_t(lb) * blockDim.x + threadIdx.x;
+  const int i = int(tid >> 2);
   const int mu = int(tid & 3);
-  if (h >= g.Vh) return;  // whole quads leave together
+  if (i >= g.Vh) return;  // whole quads leave together
+  const int h = tiled_half_index(g, i, ty, tz);  // odd site
   const Site s = decode_site(g, h, 1);
   int fwd[4], bwd[4];
   neighbours(g, s, h, fwd, bwd);
@@ -347,9 +354,13 @@ int lqcd_fermion_force(const lqcd_geom* g, const void* U64, int32_t npf, int32_t
   for (int i = 0; i < nshift; ++i) al.a[i] = alpha[i];
   const int64_t threads = int64_t(4) * k.Vh;
   const unsigned grid = unsigned((threads + kForceBlock - 1) / kForceBlock);
+  // small (y, z) tiles: a tile's t slice is a few dozen waves, so the +-t
+  // neighbours of a site are loaded by waves at nearly the same pair (at 48^4
+  // 6 x 6 tiles: 11.4 ms against 12.4 ms lexicographic, both XCD-contiguous)
+  const int tz = small_tile(k.Lz), ty = small_tile(k.Ly) ? small_tile(k.Ly) : k.Ly;
   hipLaunchKernelGGL(k_force, dim3(grid), dim3(kForceBlock), 0, (hipStream_t)stream, k,
                      (const double2*)U64, (const double2*)X, npf, nshift, al, mode, accumulate,
-                     (double2*)F);
+                     ty, tz, (double2*)F);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }

@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "tile.h"
 
 namespace lqcd {
 
@@ -239,15 +240,19 @@ __device__ __forceinline__ M3 traceless_antiherm(const M3& w) {
   return r;
 }
 
-// One thread per link: idx = (parity * 4 + mu) * Vh + h, so each (parity,
-// mu, element) plane is written coalesced.
+// One thread per link: idx = (parity * 4 + mu) * Vh + i, so each (parity,
+// mu, element) plane is written coalesced; the blocks of one XCD take
+// consecutive i, and i runs through z slabs of tz slices with t inside the
+// slab (tz = 0: lexicographic), so the neighbour links one thread loads are
+// the ones its neighbours load, while still in that XCD's L2.
 template <int SEL>
 __global__ void __launch_bounds__(kGaugeBlock) k_gauge_force(KGeom g, const double2* __restrict__ U,
                                                              double beta, double c0, double c1,
-                                                             int accumulate, double2* F) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                             int accumulate, int tz, double2* F) {
+  const int64_t idx =
+      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(8) * g.Vh) return;
-  const int h = int(idx % g.Vh);
+  const int h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
   const int pm = int(idx / g.Vh);
   const int par = pm >> 2, mu = pm & 3;
   const C4 x = site_c4(g, h, par);
@@ -301,13 +306,16 @@ __device__ __forceinline__ M3 sfield(const KGeom& g, const double2* __restrict__
   return r;
 }
 
-// pass 1: one thread per site (idx = parity * Vh + h)
+// pass 1: one thread per site (idx = parity * Vh + i; sites in the z-slab
+// order of k_gauge_force, blocks XCD-contiguous)
 __global__ void __launch_bounds__(kGaugeBlock) k_staple_fields(KGeom g,
                                                                const double2* __restrict__ U,
-                                                               int mu, int nu, double2* P) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                               int mu, int nu, int tz,
+                                                               double2* P) {
+  const int64_t idx =
+      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(2) * g.Vh) return;
-  const int par = int(idx / g.Vh), h = int(idx % g.Vh);
+  const int par = int(idx / g.Vh), h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
   const C4 x = site_c4(g, h, par);
 #pragma unroll 1
   for (int f = 0; f < 4; ++f) {
@@ -328,16 +336,17 @@ __global__ void __launch_bounds__(kGaugeBlock) k_staple_fields(KGeom g,
 }
 
 // pass 2: one thread per link of the two directions (idx = (side * 2 + parity)
-// * Vh + h; side 0: a = mu, side 1: a = nu).  first_mask bit side: write F_a
-// instead of adding to it.
+// * Vh + i; side 0: a = mu, side 1: a = nu; sites in the z-slab order, blocks
+// XCD-contiguous).  first_mask bit side: write F_a instead of adding to it.
 __global__ void __launch_bounds__(kGaugeBlock) k_force_pair(KGeom g, const double2* __restrict__ U,
                                                             const double2* __restrict__ P,
                                                             int mu, int nu, double beta,
                                                             double c0, double c1, int first_mask,
-                                                            double2* F) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                            int tz, double2* F) {
+  const int64_t idx =
+      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(4) * g.Vh) return;
-  const int sp = int(idx / g.Vh), h = int(idx % g.Vh);
+  const int sp = int(idx / g.Vh), h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
   const int side = sp >> 1, par = sp & 1;
   const int a = side ? nu : mu, b = side ? mu : nu;
   const int fp = side ? 2 : 0, fm = side ? 3 : 1, fmo = side ? 1 : 3;  // P+_ab, P-_ab, P-_ba
@@ -904,20 +913,21 @@ int lqcd_gauge_force(const lqcd_geom* g, const void* U64, double beta, double c1
   // the later ones add TA(U (-beta/3) A_k) onto the first's result.
   const dim3 grid(unsigned((n + kGaugeBlock - 1) / kGaugeBlock));
   const hipStream_t s = (hipStream_t)stream;
+  const int tz = slab_tile(k.Lz);
   if (c1 == 0.0) {
     hipLaunchKernelGGL(k_gauge_force<kStaplePlaq>, grid, dim3(kGaugeBlock), 0, s, k,
-                       (const double2*)U64, beta, 1.0, 0.0, accumulate, (double2*)F);
+                       (const double2*)U64, beta, 1.0, 0.0, accumulate, tz, (double2*)F);
     LQCD_LAUNCH_CHECK();
     return LQCD_OK;
   }
   hipLaunchKernelGGL(k_gauge_force<kStaplePass1>, grid, dim3(kGaugeBlock), 0, s, k,
-                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, accumulate, (double2*)F);
+                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, accumulate, tz, (double2*)F);
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_gauge_force<kStaplePass2>, grid, dim3(kGaugeBlock), 0, s, k,
-                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, 1, (double2*)F);
+                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, 1, tz, (double2*)F);
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_gauge_force<kStaplePass3>, grid, dim3(kGaugeBlock), 0, s, k,
-                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, 1, (double2*)F);
+                     (const double2*)U64, beta, 1.0 - 8.0 * c1, c1, 1, tz, (double2*)F);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
@@ -953,6 +963,7 @@ int lqcd_gauge_force_staples(const lqcd_geom* g, const void* U64, double beta, d
   const hipStream_t s = (hipStream_t)stream;
   const dim3 g1(unsigned((int64_t(2) * k.Vh + kGaugeBlock - 1) / kGaugeBlock));
   const dim3 g2(unsigned((int64_t(4) * k.Vh + kGaugeBlock - 1) / kGaugeBlock));
+  const int tz = slab_tile(k.Lz);
   int seen = 0;  // directions whose F has been written
   for (int mu = 0; mu < 4; ++mu)
     for (int nu = mu + 1; nu < 4; ++nu) {
@@ -963,10 +974,10 @@ int lqcd_gauge_force_staples(const lqcd_geom* g, const void* U64, double beta, d
       }
       seen |= (1 << mu) | (1 << nu);
       hipLaunchKernelGGL(k_staple_fields, g1, dim3(kGaugeBlock), 0, s, k, (const double2*)U64,
-                         mu, nu, (double2*)ws);
+                         mu, nu, tz, (double2*)ws);
       LQCD_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_force_pair, g2, dim3(kGaugeBlock), 0, s, k, (const double2*)U64,
-                         (const double2*)ws, mu, nu, beta, 1.0 - 8.0 * c1, c1, first,
+                         (const double2*)ws, mu, nu, beta, 1.0 - 8.0 * c1, c1, first, tz,
                          (double2*)F);
       LQCD_LAUNCH_CHECK();
     }
