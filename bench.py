@@ -586,7 +586,7 @@ def main():
                     help="skip the RHMC heatbath / action measurement")
     ap.add_argument("--rhmc-only", action="store_true",
                     help="only the RHMC measurements (heatbath, action, trajectory, gauge "
-                         "force, stout smearing), for profiling them")
+                         "force, stout smearing, fermion force), for profiling them")
     ap.add_argument("--retune", action="store_true",
                     help="tune every stencil shape from scratch instead of starting from "
                          "the shipped MI355X tuning cache")
@@ -642,7 +642,16 @@ def main():
         U64 = lq.pack_links(g, U_dev)
         rh = rhmc_heatbath(lq, torch, g, U64, w["mass"], nrhs)
         tr = rhmc_trajectory_bench(lq, torch, g, U64)
-        print(json.dumps({"rhmc_heatbath": rh, "rhmc_trajectory": tr}), flush=True)
+        # the fermion force on solutions of the step's shape (seeded Gaussian
+        # stand-ins: the kernel's cost does not depend on the values)
+        gen = torch.Generator(device="cuda").manual_seed(11)
+        Xs = torch.randn(nrhs, nshift, 3, g.Vh, dtype=torch.complex128, device="cuda",
+                         generator=gen)
+        ff = force_roofline(lq, torch, g, U64, al, Xs)
+        del Xs
+        log(f"fermion force {L[0]}x{L[1]}x{L[2]}x{L[3]}, {ff['pairs']} pairs: {ff['ms']:.2f} ms")
+        print(json.dumps({"rhmc_heatbath": rh, "rhmc_trajectory": tr, "fermion_force": ff}),
+              flush=True)
         return
 
     if args.profile_kernels:

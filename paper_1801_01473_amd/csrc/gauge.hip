@@ -626,11 +626,14 @@ __device__ __forceinline__ void stout_x(const KGeom& g, const double2* __restric
   X = m_scale(-rho, traceless_antiherm(m_mul(u, A)));
 }
 
+// One thread per link, in the XCD-contiguous z-slab order of k_gauge_force.
 __global__ void __launch_bounds__(kGaugeBlock) k_stout_smear(KGeom g, const double2* __restrict__ U,
-                                                             double rho, double2* __restrict__ out) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                             double rho, int tz,
+                                                             double2* __restrict__ out) {
+  const int64_t idx =
+      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(8) * g.Vh) return;
-  const int h = int(idx % g.Vh);
+  const int h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
   const int pm = int(idx / g.Vh);
   const C4 x = site_c4(g, h, pm >> 2);
   M3 A, u, X;
@@ -681,13 +684,14 @@ __device__ void expm_frechet(const M3& X, const M3& B, M3& E, M3& G) {
 // link: K = rho Lam^dag U and the local part Mloc = M' E + rho A Lam^dag of
 // M, Lam = TA(L(X, U M')).
 __global__ void __launch_bounds__(kGaugeBlock) k_stout_lambda(KGeom g, const double2* __restrict__ U,
-                                                              double rho,
+                                                              double rho, int tz,
                                                               const double2* __restrict__ Gp,
                                                               double2* __restrict__ K,
                                                               double2* __restrict__ Mloc) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t idx =
+      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(8) * g.Vh) return;
-  const int h = int(idx % g.Vh);
+  const int h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
   const int pm = int(idx / g.Vh);
   const C4 x = site_c4(g, h, pm >> 2);
   M3 A, u, X;
@@ -721,10 +725,12 @@ __global__ void __launch_bounds__(kGaugeBlock) k_stout_lambda(KGeom g, const dou
 __global__ void __launch_bounds__(kGaugeBlock) k_stout_gather(KGeom g, const double2* __restrict__ U,
                                                               const double2* __restrict__ K,
                                                               const double2* __restrict__ Mloc,
-                                                              int mode, double2* __restrict__ out) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                              int mode, int tz,
+                                                              double2* __restrict__ out) {
+  const int64_t idx =
+      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(8) * g.Vh) return;
-  const int h = int(idx % g.Vh);
+  const int h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
   const int pm = int(idx / g.Vh);
   const int a = pm & 3;
   const C4 y = site_c4(g, h, pm >> 2);
@@ -809,7 +815,7 @@ int lqcd_stout_smear(const lqcd_geom* g, const void* U64, double rho, void* out,
   const int64_t n = int64_t(8) * k.Vh;
   hipLaunchKernelGGL(k_stout_smear, dim3(unsigned((n + kGaugeBlock - 1) / kGaugeBlock)),
                      dim3(kGaugeBlock), 0, (hipStream_t)stream, k, (const double2*)U64, rho,
-                     (double2*)out);
+                     slab_tile(k.Lz), (double2*)out);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
@@ -851,11 +857,12 @@ int lqcd_stout_force(const lqcd_geom* g, const void* U64, double rho, const void
   double2* Mloc = K + n * 9;
   const hipStream_t s = (hipStream_t)stream;
   const dim3 grid(unsigned((n + kGaugeBlock - 1) / kGaugeBlock));
+  const int tz = slab_tile(k.Lz);
   hipLaunchKernelGGL(k_stout_lambda, grid, dim3(kGaugeBlock), 0, s, k, (const double2*)U64, rho,
-                     (const double2*)G_smeared, K, Mloc);
+                     tz, (const double2*)G_smeared, K, Mloc);
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_stout_gather, grid, dim3(kGaugeBlock), 0, s, k, (const double2*)U64,
-                     (const double2*)K, (const double2*)Mloc, mode, (double2*)out);
+                     (const double2*)K, (const double2*)Mloc, mode, tz, (double2*)out);
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
 }
