@@ -240,21 +240,23 @@ __device__ __forceinline__ M3 traceless_antiherm(const M3& w) {
   return r;
 }
 
-// One thread per link: idx = (parity * 4 + mu) * Vh + i, so each (parity,
-// mu, element) plane is written coalesced; the blocks of one XCD take
-// consecutive i, and i runs through z slabs of tz slices with t inside the
-// slab (tz = 0: lexicographic), so the neighbour links one thread loads are
-// the ones its neighbours load, while still in that XCD's L2.
+// One thread per link in the link_thread order (segment = mu; both parities
+// of 64 half indices per workgroup, so each (parity, mu, element) plane is
+// written coalesced); the blocks of one XCD take consecutive chunks, and the
+// half index runs through z slabs of tz slices with t inside the slab
+// (tz = 0: lexicographic), so the neighbour links one thread loads are the
+// ones its neighbours load, while still in that XCD's L2.
 template <int SEL>
 __global__ void __launch_bounds__(kGaugeBlock) k_gauge_force(KGeom g, const double2* __restrict__ U,
                                                              double beta, double c0, double c1,
                                                              int accumulate, int tz, double2* F) {
-  const int64_t idx =
-      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(8) * g.Vh) return;
-  const int h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
-  const int pm = int(idx / g.Vh);
-  const int par = pm >> 2, mu = pm & 3;
+  LinkThread lt;
+  if (!link_thread(g, int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x,
+                   lt))
+    return;
+  const int h = tiled_half_index(g, lt.i, g.Ly, tz);
+  const int par = lt.par, mu = lt.seg;
+  const int pm = par * 4 + mu;
   const C4 x = site_c4(g, h, par);
   const M3 A = staples<SEL>(g, U, x, mu, c0, c1);
   M3 W = m_mul(link(g, U, x, mu), A);
@@ -306,16 +308,17 @@ __device__ __forceinline__ M3 sfield(const KGeom& g, const double2* __restrict__
   return r;
 }
 
-// pass 1: one thread per site (idx = parity * Vh + i; sites in the z-slab
-// order of k_gauge_force, blocks XCD-contiguous)
+// pass 1: one thread per site (the link_thread order with one segment; sites
+// in the z-slab order of k_gauge_force, blocks XCD-contiguous)
 __global__ void __launch_bounds__(kGaugeBlock) k_staple_fields(KGeom g,
                                                                const double2* __restrict__ U,
                                                                int mu, int nu, int tz,
                                                                double2* P) {
-  const int64_t idx =
-      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(2) * g.Vh) return;
-  const int par = int(idx / g.Vh), h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
+  LinkThread lt;
+  if (!link_thread(g, int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x,
+                   lt))
+    return;
+  const int par = lt.par, h = tiled_half_index(g, lt.i, g.Ly, tz);
   const C4 x = site_c4(g, h, par);
 #pragma unroll 1
   for (int f = 0; f < 4; ++f) {
@@ -335,19 +338,21 @@ __global__ void __launch_bounds__(kGaugeBlock) k_staple_fields(KGeom g,
   }
 }
 
-// pass 2: one thread per link of the two directions (idx = (side * 2 + parity)
-// * Vh + i; side 0: a = mu, side 1: a = nu; sites in the z-slab order, blocks
-// XCD-contiguous).  first_mask bit side: write F_a instead of adding to it.
+// pass 2: one thread per link of the two directions (the link_thread order,
+// segment = side; side 0: a = mu, side 1: a = nu; sites in the z-slab order,
+// blocks XCD-contiguous).  first_mask bit side: write F_a instead of adding
+// to it.
 __global__ void __launch_bounds__(kGaugeBlock) k_force_pair(KGeom g, const double2* __restrict__ U,
                                                             const double2* __restrict__ P,
                                                             int mu, int nu, double beta,
                                                             double c0, double c1, int first_mask,
                                                             int tz, double2* F) {
-  const int64_t idx =
-      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(4) * g.Vh) return;
-  const int sp = int(idx / g.Vh), h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
-  const int side = sp >> 1, par = sp & 1;
+  LinkThread lt;
+  if (!link_thread(g, int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x,
+                   lt))
+    return;
+  const int h = tiled_half_index(g, lt.i, g.Ly, tz);
+  const int side = lt.seg, par = lt.par;
   const int a = side ? nu : mu, b = side ? mu : nu;
   const int fp = side ? 2 : 0, fm = side ? 3 : 1, fmo = side ? 1 : 3;  // P+_ab, P-_ab, P-_ba
   const C4 x = site_c4(g, h, par);
@@ -626,15 +631,16 @@ __device__ __forceinline__ void stout_x(const KGeom& g, const double2* __restric
   X = m_scale(-rho, traceless_antiherm(m_mul(u, A)));
 }
 
-// One thread per link, in the XCD-contiguous z-slab order of k_gauge_force.
+// One thread per link, in the thread and site order of k_gauge_force.
 __global__ void __launch_bounds__(kGaugeBlock) k_stout_smear(KGeom g, const double2* __restrict__ U,
                                                              double rho, int tz,
                                                              double2* __restrict__ out) {
-  const int64_t idx =
-      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(8) * g.Vh) return;
-  const int h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
-  const int pm = int(idx / g.Vh);
+  LinkThread lt;
+  if (!link_thread(g, int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x,
+                   lt))
+    return;
+  const int h = tiled_half_index(g, lt.i, g.Ly, tz);
+  const int pm = lt.par * 4 + lt.seg;
   const C4 x = site_c4(g, h, pm >> 2);
   M3 A, u, X;
   stout_x(g, U, x, pm & 3, rho, A, u, X);
@@ -688,11 +694,12 @@ __global__ void __launch_bounds__(kGaugeBlock) k_stout_lambda(KGeom g, const dou
                                                               const double2* __restrict__ Gp,
                                                               double2* __restrict__ K,
                                                               double2* __restrict__ Mloc) {
-  const int64_t idx =
-      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(8) * g.Vh) return;
-  const int h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
-  const int pm = int(idx / g.Vh);
+  LinkThread lt;
+  if (!link_thread(g, int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x,
+                   lt))
+    return;
+  const int h = tiled_half_index(g, lt.i, g.Ly, tz);
+  const int pm = lt.par * 4 + lt.seg;
   const C4 x = site_c4(g, h, pm >> 2);
   M3 A, u, X;
   stout_x(g, U, x, pm & 3, rho, A, u, X);
@@ -727,11 +734,12 @@ __global__ void __launch_bounds__(kGaugeBlock) k_stout_gather(KGeom g, const dou
                                                               const double2* __restrict__ Mloc,
                                                               int mode, int tz,
                                                               double2* __restrict__ out) {
-  const int64_t idx =
-      int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(8) * g.Vh) return;
-  const int h = tiled_half_index(g, int(idx % g.Vh), g.Ly, tz);
-  const int pm = int(idx / g.Vh);
+  LinkThread lt;
+  if (!link_thread(g, int64_t(xcd_block(blockIdx.x, gridDim.x, 1)) * blockDim.x + threadIdx.x,
+                   lt))
+    return;
+  const int h = tiled_half_index(g, lt.i, g.Ly, tz);
+  const int pm = lt.par * 4 + lt.seg;
   const int a = pm & 3;
   const C4 y = site_c4(g, h, pm >> 2);
   const int64_t base = int64_t(pm) * 9 * g.Vh + h;
@@ -812,8 +820,8 @@ int lqcd_stout_smear(const lqcd_geom* g, const void* U64, double rho, void* out,
     return LQCD_ERR_INVALID_ARG;
   }
   const KGeom k = make_kgeom(g);
-  const int64_t n = int64_t(8) * k.Vh;
-  hipLaunchKernelGGL(k_stout_smear, dim3(unsigned((n + kGaugeBlock - 1) / kGaugeBlock)),
+  const int64_t n = 4 * link_threads_per_segment(k.Vh);
+  hipLaunchKernelGGL(k_stout_smear, dim3(unsigned(n / kGaugeBlock)),
                      dim3(kGaugeBlock), 0, (hipStream_t)stream, k, (const double2*)U64, rho,
                      slab_tile(k.Lz), (double2*)out);
   LQCD_LAUNCH_CHECK();
@@ -856,7 +864,7 @@ int lqcd_stout_force(const lqcd_geom* g, const void* U64, double rho, const void
   double2* K = static_cast<double2*>(ws);
   double2* Mloc = K + n * 9;
   const hipStream_t s = (hipStream_t)stream;
-  const dim3 grid(unsigned((n + kGaugeBlock - 1) / kGaugeBlock));
+  const dim3 grid(unsigned(4 * link_threads_per_segment(k.Vh) / kGaugeBlock));
   const int tz = slab_tile(k.Lz);
   hipLaunchKernelGGL(k_stout_lambda, grid, dim3(kGaugeBlock), 0, s, k, (const double2*)U64, rho,
                      tz, (const double2*)G_smeared, K, Mloc);
@@ -915,10 +923,10 @@ int lqcd_gauge_force(const lqcd_geom* g, const void* U64, double beta, double c1
     return LQCD_ERR_INVALID_ARG;
   }
   const KGeom k = make_kgeom(g);
-  const int64_t n = int64_t(8) * k.Vh;
+  const int64_t n = 4 * link_threads_per_segment(k.Vh);
   // F is linear in the staple sum, so the shapes split over three launches:
   // the later ones add TA(U (-beta/3) A_k) onto the first's result.
-  const dim3 grid(unsigned((n + kGaugeBlock - 1) / kGaugeBlock));
+  const dim3 grid(unsigned(n / kGaugeBlock));
   const hipStream_t s = (hipStream_t)stream;
   const int tz = slab_tile(k.Lz);
   if (c1 == 0.0) {
@@ -968,8 +976,8 @@ int lqcd_gauge_force_staples(const lqcd_geom* g, const void* U64, double beta, d
   }
   const KGeom k = make_kgeom(g);
   const hipStream_t s = (hipStream_t)stream;
-  const dim3 g1(unsigned((int64_t(2) * k.Vh + kGaugeBlock - 1) / kGaugeBlock));
-  const dim3 g2(unsigned((int64_t(4) * k.Vh + kGaugeBlock - 1) / kGaugeBlock));
+  const dim3 g1(unsigned(link_threads_per_segment(k.Vh) / kGaugeBlock));
+  const dim3 g2(unsigned(2 * link_threads_per_segment(k.Vh) / kGaugeBlock));
   const int tz = slab_tile(k.Lz);
   int seen = 0;  // directions whose F has been written
   for (int mu = 0; mu < 4; ++mu)

@@ -43,4 +43,30 @@ inline int slab_tile(int L) {
   return 0;
 }
 
+// Thread order of the per-link kernels: a segment (a direction or a side)
+// outermost, then chunks of kLinkChunk half indices in which the two halves
+// of a workgroup take the same half indices of parity 0 and of parity 1.
+// A link's staples and neighbours alternate between the parities, so both
+// parities of a region are read while they are in the same XCD's L2.  The
+// grid covers link_threads_per_segment() threads per segment; threads whose
+// half index i is past Vh do nothing (the return value).
+constexpr int kLinkChunk = 64;  // half the per-link workgroup (128 threads)
+
+struct LinkThread {
+  int seg, par, i;
+};
+
+__host__ __device__ inline int64_t link_threads_per_segment(int Vh) {
+  return int64_t(2) * ((Vh + kLinkChunk - 1) / kLinkChunk) * kLinkChunk;
+}
+
+__device__ __forceinline__ bool link_thread(const KGeom& g, int64_t idx, LinkThread& t) {
+  const int64_t per = link_threads_per_segment(g.Vh);
+  t.seg = int(idx / per);
+  const int64_t loc = idx % per;
+  t.par = int((loc / kLinkChunk) & 1);
+  t.i = int((loc / (2 * kLinkChunk)) * kLinkChunk + loc % kLinkChunk);
+  return t.i < g.Vh;
+}
+
 }  // namespace lqcd
