@@ -47,6 +47,11 @@ struct DslashCall {
   const int* live = nullptr;  // per right-hand side work flag, null = all
   int live_stride = 0;        // in ints
   const int* halt = nullptr;  // early-exit flag checked at kernel entry
+  // 1: the site blocks run in reverse order (the same blocks, sites, partials
+  // and bits).  The solver runs D_eo against the direction of the D_oe before
+  // it, so D_eo first reads the t that D_oe wrote last, while it is still in
+  // the last-level (MALL) cache.
+  int rev = 0;
   double* partials = nullptr; // [nrhs][nblocks]
 };
 

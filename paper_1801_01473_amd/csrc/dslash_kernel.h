@@ -76,7 +76,8 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
   const KGeom& g = a.g;
   // workgroup -> (site block, RHS group)
   const int nblk = ilv ? gridDim.x / ngroups : gridDim.x;
-  const int lb = xcd_block(blockIdx.x, gridDim.x, xcd);
+  const int lb0 = xcd_block(blockIdx.x, gridDim.x, xcd);
+  const int lb = a.rev ? int(gridDim.x) - 1 - lb0 : lb0;  // reverse block order
   const int blk = ilv ? lb / ngroups : lb;
   const int rhs0 = (ilv ? lb % ngroups : blockIdx.y) * B;
   bool lv[B];

@@ -1051,6 +1051,7 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   d3.live_stride = kStateStrideI;
   d3.halt = &gf->all_done;
   d3.partials = c.at<double>(c.L.pr);
+  d3.rev = 1;  // against D_oe's order: the last t it wrote is read first (MALL hits)
   ev = timing_begin(s);
   if ((rc = dslash_launch(d3, ph.c_eo, s))) return rc;
   timing_end(ev, s, "dslash_eo_cg" + tag);
