@@ -842,6 +842,9 @@ def main():
         "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
         "avg_launch_us": kd["avg_us"],
         "share_of_solve_kernel_time": kd["total_ms"] / sum(v["total_ms"] for v in kernels.values()),
+        # the HBM rate the counter traffic implies at this run's launch time, next to the
+        # box's STREAM copy: how much of the gap to the peak is re-fetch, how much rate
+        "traffic_GBps": (traffic / (kd["avg_us"] * 1e-6) / 1e9) if traffic else None,
     }
 
     cpu = None
