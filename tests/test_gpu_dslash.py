@@ -363,3 +363,36 @@ def test_paper_lattice_shape_every_format_8rhs(lq):
         got = host(lq.unpack_spinor(g, lq.deo(g, Ul, lq.pack_spinor(g, cu(fo), 1, prec)), 0))
         assert H.max_rel(got, ref_eo) <= tol, ("D_eo", prec, fmt)
         del Ul, got
+
+
+def test_largest_accepted_lattice(lq):
+    """The largest lattice class the library accepts (144 Vh just below 2^32,
+    here 88^3 x 86, 98 % of the 32-bit offset range of an FP64 18-real link
+    block): D_oe and D_eo in FP64 18-real and D_oe in FP32 18-real against
+    the oracle on the whole field, with Gaussian 3x3 links (no SU(3) property
+    is needed by the 18-real format)."""
+    L = (88, 88, 88, 86)
+    g = lq.Geometry(L)
+    assert 144 * g.Vh < 2 ** 32 and 144 * (88 ** 4 // 2) >= 2 ** 32
+    gen = torch.Generator(device="cuda").manual_seed(881)
+    Un = torch.randn(4, g.V, 3, 3, dtype=torch.complex128, device="cuda", generator=gen)
+    U64 = lq.pack_links(g, Un)
+    U = host(Un)
+    del Un
+    f = host(torch.randn(1, g.V, 3, dtype=torch.complex128, device="cuda", generator=gen))
+    threads = oracle.get_threads()
+    oracle.set_threads(16)
+    try:
+        got = host(lq.unpack_spinor(g, lq.doe(g, U64, lq.pack_spinor(g, cu(f), 0)), 1))[0]
+        assert H.max_rel(got, oracle.doe(L, U, f[0])) <= 1e-13
+        got = host(lq.unpack_spinor(g, lq.deo(g, U64, lq.pack_spinor(g, cu(f), 1)), 0))[0]
+        assert H.max_rel(got, oracle.deo(L, U, f[0])) <= 1e-13
+        U32 = lq.convert_links(g, U64, lq.F64, lq.LINKS18, lq.F32, lq.LINKS18)
+        del U64
+        Ur = U.astype(np.complex64).astype(np.complex128)
+        fr = f.astype(np.complex64).astype(np.complex128)
+        got = host(lq.unpack_spinor(g, lq.doe(g, U32, lq.pack_spinor(g, cu(f), 0, lq.F32)), 1))[0]
+        assert H.max_rel(got, oracle.doe(L, Ur, fr[0])) <= 1e-6
+    finally:
+        oracle.set_threads(threads)
+        torch.cuda.empty_cache()
