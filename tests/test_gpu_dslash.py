@@ -396,3 +396,30 @@ def test_largest_accepted_lattice(lq):
     finally:
         oracle.set_threads(threads)
         torch.cuda.empty_cache()
+
+
+def test_largest_accepted_lattice_8rhs(lq):
+    """Eight right-hand sides through one link load at the largest lattice
+    class the library accepts (88^3 x 86): FP32 18-real D_oe against the
+    oracle for every right-hand side, Gaussian 3x3 links."""
+    L = (88, 88, 88, 86)
+    g = lq.Geometry(L)
+    gen = torch.Generator(device="cuda").manual_seed(882)
+    Un = torch.randn(4, g.V, 3, 3, dtype=torch.complex128, device="cuda", generator=gen)
+    U32 = lq.pack_links(g, Un, lq.F32, lq.LINKS18)
+    Ur = host(Un.to(torch.complex64).to(torch.complex128))
+    del Un
+    f = torch.randn(8, g.V, 3, dtype=torch.complex128, device="cuda", generator=gen)
+    out = lq.doe(g, U32, lq.pack_spinor(g, f, 0, lq.F32))
+    del U32
+    fr = host(f.to(torch.complex64).to(torch.complex128))
+    del f
+    threads = oracle.get_threads()
+    oracle.set_threads(16)
+    try:
+        for j in range(8):
+            got = host(lq.unpack_spinor(g, out[j:j + 1].contiguous(), 1))[0]
+            assert H.max_rel(got, oracle.doe(L, Ur, fr[j])) <= 1e-6, j
+    finally:
+        oracle.set_threads(threads)
+        torch.cuda.empty_cache()
