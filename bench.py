@@ -193,6 +193,15 @@ KERNEL_CLASS_KEY = {"dslash_eo_cg_f32": (1, 1, 2), "dslash_oe_f32": (1, 1, 0),
                     "dslash_eo_cg_f64": (0, 1, 2), "dslash_oe_f64": (0, 1, 0)}
 
 
+def rhs_pairs(kernel_class, nrhs):
+    """Whether the multi-shift solve runs this stencil class on interleaved
+    right-hand-side pairs: the FP32 classes at an even RHS count, unless
+    LQCD_RHS_PAIRS=0 keeps the systems one after the other."""
+    base = kernel_class.rsplit("_", 1)[0]
+    return (base.endswith("_f32") and nrhs >= 2 and nrhs % 2 == 0
+            and not os.environ.get("LQCD_RHS_PAIRS", "").startswith("0"))
+
+
 def tuned_config(cache, L, kernel_class, nrhs):
     """The configuration the stencil tuner chose for a kernel class in this
     run, read back from the tuning-cache file (the last entry for its key), or
@@ -202,6 +211,8 @@ def tuned_config(cache, L, kernel_class, nrhs):
         return None
     prec, fmt, mode = KERNEL_CLASS_KEY[base]
     tail = f"/{L[0]}x{L[1]}x{L[2]}x{L[3]}/p{prec}/f{fmt}/n{nrhs}/b0/m{mode}"
+    if rhs_pairs(kernel_class, nrhs):
+        tail += "/pairs"
     found = None
     with open(cache) as f:
         for line in f:

@@ -52,6 +52,13 @@ struct DslashCall {
   // it, so D_eo first reads the t that D_oe wrote last, while it is still in
   // the last-level (MALL) cache.
   int rev = 0;
+  // 1: in, diag and (plain mode) out hold the right-hand sides as interleaved
+  // pairs: rows 2q and 2q + 1 share the 2 * stride values from row 2q's start,
+  // complex element (c, h) of row 2q + e at index 2 (c Vh + h) + e.  FP32,
+  // 12- or 18-real links, plain or fused CG mode, nrhs and the RHS block even,
+  // strides of at least 3 Vh.  The stencil then moves each element of two
+  // right-hand sides with one 16-byte access (same arithmetic, same bits).
+  int pairs = 0;
   double* partials = nullptr; // [nrhs][nblocks]
 };
 

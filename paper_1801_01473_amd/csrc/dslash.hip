@@ -23,6 +23,18 @@ int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
     set_error("unsupported dslash block size %d", cfg.block);
     return LQCD_ERR_UNSUPPORTED;
   }
+  if (c.pairs) {
+    const int64_t vs = int64_t(3) * c.g.Vh;
+    if (c.prec != LQCD_F32 || (c.fmt != LQCD_LINKS12 && c.fmt != LQCD_LINKS18) ||
+        (c.mode != DM_PLAIN && c.mode != DM_CG) || c.nrhs % 2 != 0 || cfg.rhs_block % 2 != 0 ||
+        cfg.tm > 0 || cfg.mf == 1 || c.in_stride < vs ||
+        (c.mode == DM_PLAIN && c.out_stride < vs) || (c.mode == DM_CG && c.diag_stride < vs)) {
+      set_error("right-hand-side pairs need FP32 12- or 18-real links, the plain or fused CG "
+                "mode, an even number of right-hand sides and RHS block, k_dslash, and rows "
+                "of at least 3 Vh values");
+      return LQCD_ERR_UNSUPPORTED;
+    }
+  }
   if (cfg.tm > 0) return dslash_tm_launch(c, cfg, st);
   if (cfg.mf == 1) return dslash_mfma_launch(c, cfg, st);
   if (cfg.tz < 0 || (cfg.tz > 0 && c.g.Lz % cfg.tz != 0) || cfg.ty < 0 ||
@@ -52,11 +64,11 @@ int dslash_launch(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
 
 namespace {
 
-using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int>;
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, DslashCfg> g_tune;
 
-DslashCfg default_cfg(int nrhs, int forced, int prec) {
+DslashCfg default_cfg(int nrhs, int forced, int prec, int pairs) {
   DslashCfg c;
   c.block = 256;
   c.xcd = 1;
@@ -64,6 +76,7 @@ DslashCfg default_cfg(int nrhs, int forced, int prec) {
   int b = 1;
   while (b * 2 <= std::min(nrhs, 8)) b *= 2;
   c.rhs_block = forced > 0 ? forced : b;
+  if (pairs && c.rhs_block < 2) c.rhs_block = 2;
   return c;
 }
 
@@ -103,9 +116,9 @@ std::string tune_cache_key(const DslashCall& c, int forced) {
   for (char& ch : arch)
     if (ch == ';' || ch == ' ') ch = '_';
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "v%d/%s/%dcu/%dx%dx%dx%d/p%d/f%d/n%d/b%d/m%d", kTuneCacheFormat,
+  std::snprintf(buf, sizeof(buf), "v%d/%s/%dcu/%dx%dx%dx%d/p%d/f%d/n%d/b%d/m%d%s", kTuneCacheFormat,
                 arch.c_str(), cus, c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, c.prec, c.fmt, c.nrhs, forced,
-                c.mode);
+                c.mode, c.pairs ? "/pairs" : "");
   return buf;
 }
 
@@ -118,7 +131,8 @@ bool cfg_valid(const DslashCall& c, const DslashCfg& f, int forced) {
          (f.ns == 0 || (f.ns == 1 && f.nt == 1)) &&
          (f.ilv == 0 || f.ilv == 1) && f.occ >= 0 && dslash_lds_bytes(f) >= 0 &&
          dslash_lds_bytes(f) <= 64 * 1024 && f.tm >= 0 &&
-         (f.tm == 0 || dslash_tm_supported(c, f));
+         (f.tm == 0 || dslash_tm_supported(c, f)) &&
+         (!c.pairs || (f.rhs_block % 2 == 0 && f.tm == 0 && f.mf == 0));
 }
 
 // The last valid entry for the key, if any.
@@ -166,6 +180,10 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
     set_error("rhs_block must be 0 (tuned), 1, 2, 4 or 8, got %d", forced);
     return LQCD_ERR_INVALID_ARG;
   }
+  if (c.pairs && forced == 1) {
+    set_error("right-hand-side pairs need an RHS block of 2, 4 or 8");
+    return LQCD_ERR_INVALID_ARG;
+  }
   // LQCD_DSLASH_CFG="block,rhs_block,xcd,tz[,nt,occ,ilv,lf,hh,ty,ns,tm,tp,mf]" pins the
   // configuration (testing, profiling).  A t-march or matrix-core configuration
   // applies only where that kernel exists (t-march: 8 right-hand sides or more,
@@ -177,6 +195,7 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
                     &f.xcd, &f.tz, &f.nt, &f.occ, &f.ilv, &f.lf, &f.hh, &f.ty, &f.ns, &f.tm,
                     &f.tp, &f.mf) >= 4) {
       if (forced) f.rhs_block = forced;
+      if (c.pairs && f.rhs_block == 1) f.rhs_block = 2;  // pairs load two rows at once
       if (f.tm > 0 && (c.nrhs < 8 || !dslash_tm_supported(c, f))) {
         f.tm = 0;
         if (f.rhs_block > c.nrhs) f.rhs_block = 1;
@@ -186,7 +205,7 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
       return LQCD_OK;
     }
   }
-  const TuneKey key{c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, c.prec, c.fmt, c.nrhs, forced, c.mode};
+  const TuneKey key{c.g.Lx, c.g.Ly, c.g.Lz, c.g.Lt, c.prec, c.fmt, c.nrhs, forced, c.mode, c.pairs};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -195,7 +214,7 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
       return LQCD_OK;
     }
   }
-  DslashCfg best = default_cfg(c.nrhs, forced, c.mode == DM_RES ? LQCD_F64 : c.prec);
+  DslashCfg best = default_cfg(c.nrhs, forced, c.mode == DM_RES ? LQCD_F64 : c.prec, c.pairs);
   if (!tuning_enabled()) {
     *out = best;
     return LQCD_OK;
@@ -222,6 +241,7 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   for (int blk : {64, 128, 256})
     for (int b : {1, 2, 4, 8}) {
       if (forced ? b != forced : b > c.nrhs) continue;
+      if (c.pairs && b == 1) continue;  // pairs load two rows at once
       for (int x : {0, 1})
         for (int tz : {0, 2, 4, 8}) {
           if (tz && (c.g.Lz % tz || tz >= c.g.Lz)) continue;
@@ -281,6 +301,7 @@ int dslash_tuned(const DslashCall& c, int forced, hipStream_t st, DslashCfg* out
   t.partials = reinterpret_cast<double*>(static_cast<char*>(scratch) + fields);
   t.prec = c.prec;
   t.fmt = c.fmt;
+  t.pairs = c.pairs;  // same bytes per field, read and written as pairs
   if (c.mode == DM_RES) {  // the residual kernels run on FP64 18-real links
     t.prec = LQCD_F64;
     t.fmt = LQCD_LINKS18;

@@ -62,7 +62,11 @@ __device__ __forceinline__ int64_t r_slot(const DslashCall& a, int j, int ahead)
 // every load of a direction before its arithmetic (more loads in flight per
 // wave, more registers held), bit 2 walks the eight hops one per iteration
 // (half the loads held per iteration, so more waves fit; the backward link is
-// conjugate-transposed in registers so that one product serves both).
+// conjugate-transposed in registers so that one product serves both), bit 4
+// reads the input, the fused update's own-site direction (diag) and the plain
+// mode's output as right-hand-side pairs (DslashCall::pairs; FP32, B even):
+// one 16-byte access moves the same element of two right-hand sides, half the
+// memory instructions of separate rows, with the same arithmetic and bits.
 template <typename R, int NE, int B, int MODE, typename RO, int V>
 __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xcd, const int tz,
                                                 const int ty, const int ngroups,
@@ -71,6 +75,10 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
   constexpr bool LF = (V & 2) != 0;
   constexpr bool HH = (V & 4) != 0;
   constexpr bool NS = (V & 8) != 0;  // own-site operands and outputs non-temporal
+  constexpr bool PR = (V & 16) != 0;  // right-hand sides in interleaved pairs
+  static_assert(!PR || (sizeof(R) == 4 && B % 2 == 0 && (MODE == DM_PLAIN || MODE == DM_CG)),
+                "pairs: FP32, an even RHS block, plain or fused CG mode");
+  constexpr int NRow = PR ? B / 2 : B;  // input rows loaded per element (pairs count once)
   __shared__ double lds[B][4];
   if (a.halt && *a.halt) return;
   const KGeom& g = a.g;
@@ -117,13 +125,19 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
     // Input rows of the block's right-hand sides; rows past nrhs alias the
     // last one (loaded and computed, never stored), so the loads of every
     // right-hand side issue together without a branch between them.
-    __amdgpu_buffer_rsrc_t rin[B];
+    // With pairs, rows 2q and 2q + 1 (nrhs even) fill the 2 in_stride values
+    // from row 2q's start, element by element: the pair's resource covers
+    // both, a site's element sits at 16 bytes per site, a colour 16 Vh bytes on.
+    __amdgpu_buffer_rsrc_t rin[NRow];
 #pragma unroll
-    for (int b = 0; b < B; ++b)
-      rin[b] = make_res(static_cast<const cplx<R>*>(a.in) +
-                            int64_t(rhs0 + b < a.nrhs ? rhs0 + b : a.nrhs - 1) * a.in_stride,
-                        3u * uint32_t(g.Vh) * cb);
+    for (int b = 0; b < NRow; ++b) {
+      const int jr = PR ? (rhs0 + 2 * b < a.nrhs ? rhs0 + 2 * b : a.nrhs - 2)
+                        : (rhs0 + b < a.nrhs ? rhs0 + b : a.nrhs - 1);
+      rin[b] = make_res(static_cast<const cplx<R>*>(a.in) + int64_t(jr) * a.in_stride,
+                        (PR ? 6u : 3u) * uint32_t(g.Vh) * cb);
+    }
     const uint32_t csoff = uint32_t(g.Vh) * cb;  // colour stride in bytes
+    constexpr uint32_t pw = PR ? 2u : 1u;          // element width of the input rows
 
     if (HH) {
       // one hop per iteration: k = 2 mu + (0 forward, 1 backward)
@@ -158,10 +172,19 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
         R th = R(0);
         if constexpr (NE == 8)
           th = ld_buf_real<R, LAUX>(rl, uint32_t(fw ? h : nbr) * uint32_t(sizeof(R)), 6u * csoff);
+        if constexpr (PR) {
 #pragma unroll
-        for (int b = 0; b < B; ++b)
+          for (int q = 0; q < NRow; ++q)
 #pragma unroll
-          for (int cc = 0; cc < 3; ++cc) v[b][cc] = ld_buf<R>(rin[b], on, uint32_t(cc) * csoff);
+            for (int cc = 0; cc < 3; ++cc)
+              ld_buf_pair(rin[q], pw * on, uint32_t(cc) * pw * csoff, v[2 * q][cc],
+                          v[2 * q + 1][cc]);
+        } else {
+#pragma unroll
+          for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) v[b][cc] = ld_buf<R>(rin[b], on, uint32_t(cc) * csoff);
+        }
         complete_link<R, NE>(u);
         if constexpr (NE == 8) apply_u1<R>(u, th);
         if (!fw) {  // U^dag
@@ -182,7 +205,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
           }
         }
         if (LF) {
-          __builtin_amdgcn_sched_group_barrier(0x020, NE + 3 * B, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, NE + 3 * NRow, 0);
           __builtin_amdgcn_sched_group_barrier(0x002, 4096, 0);
         }
       }
@@ -221,13 +244,25 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
       }
       {
         const uint32_t of = uint32_t(nf) * cb, ob = uint32_t(nb) * cb;
+        if constexpr (PR) {
 #pragma unroll
-        for (int b = 0; b < B; ++b)
+          for (int q = 0; q < NRow; ++q)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            vf[b][c] = ld_buf<R>(rin[b], of, uint32_t(c) * csoff);
-            vb[b][c] = ld_buf<R>(rin[b], ob, uint32_t(c) * csoff);
-          }
+            for (int c = 0; c < 3; ++c) {
+              ld_buf_pair(rin[q], pw * of, uint32_t(c) * pw * csoff, vf[2 * q][c],
+                          vf[2 * q + 1][c]);
+              ld_buf_pair(rin[q], pw * ob, uint32_t(c) * pw * csoff, vb[2 * q][c],
+                          vb[2 * q + 1][c]);
+            }
+        } else {
+#pragma unroll
+          for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              vf[b][c] = ld_buf<R>(rin[b], of, uint32_t(c) * csoff);
+              vb[b][c] = ld_buf<R>(rin[b], ob, uint32_t(c) * csoff);
+            }
+        }
       }
       complete_link<R, NE>(uf);
       complete_link<R, NE>(ub);
@@ -253,7 +288,7 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
       }
       // loads-first variant: every load of the iteration, then the arithmetic
       if (LF) {
-        __builtin_amdgcn_sched_group_barrier(0x020, 2 * NE + 6 * B, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 2 * NE + 6 * NRow, 0);
         __builtin_amdgcn_sched_group_barrier(0x002, 4096, 0);
       }
     }
@@ -265,12 +300,26 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
     cplx<R> dv[B][3], rv[B][3];
     double2 bv[B][3];
     if (MODE != DM_PLAIN) {
+      if constexpr (PR) {  // the direction pair of rows 2q, 2q + 1 (as the input)
+#pragma unroll
+        for (int q = 0; q < NRow; ++q) {
+          const int jp = rhs0 + 2 * q < a.nrhs ? rhs0 + 2 * q : a.nrhs - 2;
+          const cplx<R>* d =
+              static_cast<const cplx<R>*>(a.diag) + int64_t(jp) * a.diag_stride + 2 * h;
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            ld_once_pair<NS>(d + 2 * int64_t(c) * g.Vh, dv[2 * q][c], dv[2 * q + 1][c]);
+        }
+      }
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         const int jl = rhs0 + b < a.nrhs ? rhs0 + b : a.nrhs - 1;
-        const cplx<R>* d = static_cast<const cplx<R>*>(a.diag) + int64_t(jl) * a.diag_stride + h;
+        if constexpr (!PR) {
+          const cplx<R>* d =
+              static_cast<const cplx<R>*>(a.diag) + int64_t(jl) * a.diag_stride + h;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dv[b][c] = ld_once<R, NS>(d + int64_t(c) * g.Vh);
+          for (int c = 0; c < 3; ++c) dv[b][c] = ld_once<R, NS>(d + int64_t(c) * g.Vh);
+        }
         if (MODE == DM_CG) {
           const cplx<R>* r = static_cast<const cplx<R>*>(a.r) + r_slot(a, jl, 0) * a.r_stride + h;
 #pragma unroll
@@ -285,11 +334,27 @@ __global__ void __launch_bounds__(256) k_dslash(const DslashCall a, const int xc
       }
     }
 
+    if constexpr (PR && MODE == DM_PLAIN) {
+      // a pair is written if either row is live (rows 2q, 2q + 1 < nrhs then);
+      // the other row of such a pair belongs to a finished system, whose
+      // output nothing reads
+#pragma unroll
+      for (int q = 0; q < NRow; ++q) {
+        if (!lv[2 * q] && !lv[2 * q + 1]) continue;
+        cplx<R>* out = static_cast<cplx<R>*>(a.out) + int64_t(rhs0 + 2 * q) * a.out_stride + 2 * h;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          st_once_pair<NS>(out + 2 * int64_t(c) * g.Vh, acc[2 * q][c], acc[2 * q + 1][c]);
+      }
+    }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       if (!lv[b]) continue;
       const int j = rhs0 + b;
-      if (MODE == DM_PLAIN) {
+      if (MODE == DM_PLAIN && PR) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nrm[b] += cnorm2<R>(acc[b][c]);
+      } else if (MODE == DM_PLAIN) {
         cplx<R>* out = static_cast<cplx<R>*>(a.out) + int64_t(j) * a.out_stride + h;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -359,6 +424,31 @@ int launch_one(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
   if (cfg.ns && !cfg.nt) {
     set_error("non-temporal own-site streams (ns) need non-temporal link loads (nt)");
     return LQCD_ERR_UNSUPPORTED;
+  }
+  if (c.pairs) {  // interleaved right-hand-side pairs (FP32, 12/18-real, B even)
+    if constexpr (sizeof(R) == 4 && (NE == 6 || NE == 9) && B % 2 == 0 &&
+                  (MODE == DM_PLAIN || MODE == DM_CG)) {
+      switch ((cfg.nt ? 1 : 0) | (cfg.lf ? 2 : 0) | (cfg.hh ? 4 : 0) | (cfg.ns ? 8 : 0)) {
+        case 0: LQCD_K(16); break;
+        case 1: LQCD_K(17); break;
+        case 2: LQCD_K(18); break;
+        case 3: LQCD_K(19); break;
+        case 4: LQCD_K(20); break;
+        case 5: LQCD_K(21); break;
+        case 6: LQCD_K(22); break;
+        case 7: LQCD_K(23); break;
+        case 9: LQCD_K(25); break;
+        case 11: LQCD_K(27); break;
+        case 13: LQCD_K(29); break;
+        default: LQCD_K(31); break;
+      }
+      LQCD_LAUNCH_CHECK();
+      return LQCD_OK;
+    } else {
+      set_error("right-hand-side pairs need FP32 12- or 18-real links, an even RHS block "
+                "and the plain or fused CG mode");
+      return LQCD_ERR_UNSUPPORTED;
+    }
   }
   if constexpr (NE == 7 || NE == 8) {
     // the phased-link formats instantiate the plain schedule only (loads

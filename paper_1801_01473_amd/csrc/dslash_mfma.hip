@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(256) k_dslash_mfma(const DslashCall a, const i
 }  // namespace
 
 bool dslash_mfma_supported(const DslashCall& c, const DslashCfg& cfg) {
-  return cfg.mf == 1 && c.prec == LQCD_F32 && c.fmt == LQCD_LINKS12 && c.mode == DM_PLAIN &&
+  return cfg.mf == 1 && !c.pairs && c.prec == LQCD_F32 && c.fmt == LQCD_LINKS12 && c.mode == DM_PLAIN &&
          c.partials == nullptr && cfg.rhs_block == 8 && cfg.tm == 0 &&
          (cfg.block == 64 || cfg.block == 128 || cfg.block == 256) &&
          (cfg.tz == 0 || c.g.Lz % cfg.tz == 0) && (cfg.ty == 0 || c.g.Ly % cfg.ty == 0);

@@ -313,7 +313,7 @@ int launch_tm_p(const DslashCall& c, const DslashCfg& cfg, hipStream_t st) {
 }  // namespace
 
 bool dslash_tm_supported(const DslashCall& c, const DslashCfg& cfg) {
-  if (!(cfg.tm > 0 && c.g.Lt % cfg.tm == 0 && cfg.rhs_block == 8 &&
+  if (!(cfg.tm > 0 && !c.pairs && c.g.Lt % cfg.tm == 0 && cfg.rhs_block == 8 &&
         (cfg.tp == 2 || cfg.tp == 4) && c.fmt == LQCD_LINKS12 &&
         (c.mode == DM_PLAIN || c.mode == DM_AXPY || c.mode == DM_CG) && cfg.tz == 0 &&
         cfg.ty == 0 && cfg.ilv == 0 && cfg.lf == 0 && cfg.hh == 0 && cfg.nt == 1 &&

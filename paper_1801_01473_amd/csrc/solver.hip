@@ -122,15 +122,25 @@ __global__ void __launch_bounds__(kVecBlock) k_copy_to_inner(const double2* __re
   if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = s;
 }
 
+// Index of complex element (system j, colour c, half site h) of a field of
+// [nsys][3][Vh] values, or, with pairs, of the same field with systems 2q and
+// 2q + 1 interleaved element by element in their 6 Vh values (the layout the
+// FP32 stencils read and write with 16-byte accesses).
+__device__ __forceinline__ int64_t sys_index(int pairs, int j, int c, int h, int Vh) {
+  return pairs ? (int64_t(j & ~1) * 3 + 2 * c) * Vh + 2 * int64_t(h) + (j & 1)
+               : (int64_t(j) * 3 + c) * Vh + h;
+}
+
 // p_s = r for every shift, optionally x_s = 0; partials of |r|^2 (= |p|^2)
-// (pc, when given: the base direction of deferred shift updates, also = r)
+// (pc, when given: the base direction of deferred shift updates, also = r,
+// in pairs when pc_pairs)
 template <typename RI, typename RX>
 __global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restrict__ r, int R,
                                                          cplx<RI>* __restrict__ p,
                                                          cplx<RX>* __restrict__ x,
-                                                         cplx<RI>* __restrict__ pc, int nshift,
-                                                         int zero_x, int Vh,
-                                                         double* __restrict__ part) {
+                                                         cplx<RI>* __restrict__ pc,
+                                                         int pc_pairs, int nshift, int zero_x,
+                                                         int Vh, double* __restrict__ part) {
   __shared__ double lds[kVecBlock / 64];
   const int j = blockIdx.y;
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,7 +150,7 @@ __global__ void __launch_bounds__(kVecBlock) k_init_dirs(const cplx<RI>* __restr
     for (int c = 0; c < 3; ++c) {
       const cplx<RI> z = r[(int64_t(j) * R * 3 + c) * Vh + h];  // slot 0
       s += cnorm2<RI>(z);
-      if (pc) pc[(int64_t(j) * 3 + c) * Vh + h] = z;
+      if (pc) pc[sys_index(pc_pairs, j, c, h, Vh)] = z;
       for (int k = 0; k < nshift; ++k) {
         const int64_t i = ((int64_t(j) * nshift + k) * 3 + c) * Vh + h;
         p[i] = z;
@@ -436,6 +446,52 @@ __global__ void __launch_bounds__(kVecBlock) k_base_update(const SysState* __res
   if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = pn;
 }
 
+// k_base_update<float> for base directions stored in pairs (systems 2q and
+// 2q + 1 interleaved, blockIdx.y = q): one thread updates a site of both with
+// 16-byte accesses, the same arithmetic per system and the same partials; a
+// system that does not update keeps its values bit for bit.
+__global__ void __launch_bounds__(kVecBlock) k_base_update_pairs(
+    const SysState* __restrict__ st, const float2* __restrict__ r, int R,
+    float4* __restrict__ pc, int base, int Vh, double* __restrict__ part) {
+  __shared__ double lds0[kVecBlock / 64], lds1[kVecBlock / 64];
+  const int j0 = 2 * blockIdx.y, j1 = j0 + 1;
+  const SysState& S0 = st[j0];
+  const SysState& S1 = st[j1];
+  const bool u0 = S0.upd_any != 0, u1 = S1.upd_any != 0;
+  if (!u0 && !u1) return;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rs0 = int64_t(j0) * R + S0.iters % R, rs1 = int64_t(j1) * R + S1.iters % R;
+  double pn0 = 0.0, pn1 = 0.0;
+  if (h < Vh) {
+    const float zs0 = float(S0.zeta[base]), bs0 = float(S0.b_s[base]);
+    const float zs1 = float(S1.zeta[base]), bs1 = float(S1.b_s[base]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = (int64_t(blockIdx.y) * 3 + c) * Vh + h;  // float4 units
+      const float2 rv0 = r[(rs0 * 3 + c) * Vh + h];
+      const float2 rv1 = r[(rs1 * 3 + c) * Vh + h];
+      float4 pv = pc[i];
+      if (u0) {
+        pv.x = fma(zs0, rv0.x, bs0 * pv.x);
+        pv.y = fma(zs0, rv0.y, bs0 * pv.y);
+        pn0 += cnorm2<float>(make_float2(pv.x, pv.y));
+      }
+      if (u1) {
+        pv.z = fma(zs1, rv1.x, bs1 * pv.z);
+        pv.w = fma(zs1, rv1.y, bs1 * pv.w);
+        pn1 += cnorm2<float>(make_float2(pv.z, pv.w));
+      }
+      pc[i] = pv;
+    }
+  }
+  pn0 = block_sum(pn0, lds0);
+  pn1 = block_sum(pn1, lds1);
+  if (threadIdx.x == 0) {
+    if (u0) part[int64_t(j0) * gridDim.x + blockIdx.x] = pn0;
+    if (u1) part[int64_t(j1) * gridDim.x + blockIdx.x] = pn1;
+  }
+}
+
 // K6: applies the window of every system that has one open (wpos > 0) to the
 // shifts updated in it; WM >= window length bounds the unrolled ring.
 // The window's residuals r(k0 + 1 .. k0 + n) are ring slots (k0 + q) % R,
@@ -612,9 +668,9 @@ template <typename RI>
 __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __restrict__ st,
                                                             const cplx<RI>* __restrict__ r, int R,
                                                             cplx<RI>* __restrict__ p,
-                                                            cplx<RI>* __restrict__ pc, int nshift,
-                                                            int base, int Vh,
-                                                            double* __restrict__ part) {
+                                                            cplx<RI>* __restrict__ pc,
+                                                            int pc_pairs, int nshift, int base,
+                                                            int Vh, double* __restrict__ part) {
   __shared__ double lds[kVecBlock / 64];
   const int j = blockIdx.y;
   const SysState& S = st[j];
@@ -632,7 +688,7 @@ __global__ void __launch_bounds__(kVecBlock) k_restart_dirs(const SysState* __re
         p[((int64_t(j) * nshift + s) * 3 + c) * Vh + h] = pv;
         if (s == base) {
           pn += cnorm2<RI>(pv);
-          if (pc) pc[(int64_t(j) * 3 + c) * Vh + h] = pv;
+          if (pc) pc[sys_index(pc_pairs, j, c, h, Vh)] = pv;
         }
       }
     }
@@ -650,7 +706,7 @@ __global__ void __launch_bounds__(kVecBlock) k_to_fp32(const SysState* __restric
                                                        const double2* __restrict__ pc64,
                                                        float2* __restrict__ r32,
                                                        float2* __restrict__ p32,
-                                                       float2* __restrict__ pc32,
+                                                       float2* __restrict__ pc32, int pc_pairs,
                                                        float2* __restrict__ xlo, int nshift,
                                                        int base, int Vh,
                                                        double* __restrict__ part) {
@@ -666,7 +722,7 @@ __global__ void __launch_bounds__(kVecBlock) k_to_fp32(const SysState* __restric
       r32[irr] = make_float2(float(r64[irr].x), float(r64[irr].y));
       if (pc64) {
         const float2 pv = make_float2(float(pc64[ir].x), float(pc64[ir].y));
-        pc32[ir] = pv;
+        pc32[sys_index(pc_pairs, j, c, h, Vh)] = pv;
         pn += cnorm2<float>(pv);
       }
       for (int s = 0; s < nshift; ++s) {
@@ -916,6 +972,7 @@ struct Phase {
   const void* U = nullptr;
   size_t r = 0, t = 0, p = 0;  // workspace offsets of r, t (odd), p_s
   size_t pc = 0;               // base direction (deferred shift updates)
+  int pairs = 0;               // pc and t hold the systems in interleaved pairs (FP32)
   void* x = nullptr;           // solution accumulator: FP64 solutions or FP32 partial sums
   DslashCfg c_oe, c_eo;
   int nb_oe = 0, nb_eo = 0;
@@ -939,6 +996,13 @@ struct Core {
 };
 
 bool is_mixed(const Ctx& c) { return c.iprec == LQCD_F32; }
+
+// LQCD_RHS_PAIRS=0 keeps the FP32 base directions and t one system after the
+// other (for comparisons); unset or any other value: pairs wherever they apply.
+bool rhs_pairs_enabled() {
+  const char* e = std::getenv("LQCD_RHS_PAIRS");
+  return !(e && e[0] == '0');
+}
 
 // residual ring slots per system (1: r updated in place)
 int rslots(const Core& k) { return k.win > 1 ? k.win + 1 : 1; }
@@ -1016,6 +1080,7 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   d1.in_stride = win ? vs : int64_t(k.nshift) * vs;
   d1.out = c.ws + ph.t;
   d1.out_stride = vs;
+  d1.pairs = ph.pairs;
   d1.live = &st->live;
   d1.live_stride = kStateStrideI;
   d1.halt = &gf->all_done;
@@ -1038,6 +1103,7 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   d3.diag_stride = win ? vs : int64_t(k.nshift) * vs;
   d3.r = c.ws + ph.r;
   d3.r_stride = vs;
+  d3.pairs = ph.pairs;
   if (win) {
     d3.r_iter = &st->iters;
     d3.r_iter_stride = kStateStrideI;
@@ -1066,7 +1132,11 @@ int launch_iteration(const Ctx& c, const Core& k, const Phase& ph, hipStream_t s
   const dim3 grid(k.nbv, k.nsys);
   if (win) {
     ev = timing_begin(s);
-    if (ph.prec == LQCD_F32)
+    if (ph.pairs)
+      hipLaunchKernelGGL(k_base_update_pairs, dim3(k.nbv, k.nsys / 2), dim3(kVecBlock), 0, s, st,
+                         c.at<const float2>(ph.r), rslots(k), c.at<float4>(ph.pc), k.base,
+                         c.g.Vh, c.at<double>(c.L.pp));
+    else if (ph.prec == LQCD_F32)
       hipLaunchKernelGGL(k_base_update<float>, grid, dim3(kVecBlock), 0, s, st,
                          c.at<const float2>(ph.r), rslots(k), c.at<float2>(ph.pc), k.base,
                          c.g.Vh, c.at<double>(c.L.pp));
@@ -1148,7 +1218,8 @@ int launch_reliable(const Ctx& c, const Core& k, hipStream_t s) {
   LQCD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_restart_dirs<float>, dim3(k.nbv, k.nsys), dim3(kVecBlock), 0, s, st,
                      c.at<const float2>(c.L.r), rslots(k), c.at<float2>(c.L.p),
-                     k.win > 1 ? c.at<float2>(c.L.pc) : nullptr, k.nshift, k.base, c.g.Vh,
+                     k.win > 1 ? c.at<float2>(c.L.pc) : nullptr, k.main.pairs, k.nshift,
+                     k.base, c.g.Vh,
                      c.at<double>(c.L.pp));
   LQCD_LAUNCH_CHECK();
   return LQCD_OK;
@@ -1174,6 +1245,7 @@ std::string graph_key(const Ctx& c, const Core& k, const Phase& ph) {
   add(&ph.t, sizeof(size_t));
   add(&ph.p, sizeof(size_t));
   add(&ph.pc, sizeof(size_t));
+  add(&ph.pairs, sizeof(int));
   add(&ph.x, sizeof(void*));
   add(&ph.c_oe, sizeof(DslashCfg));
   add(&ph.c_eo, sizeof(DslashCfg));
@@ -1255,6 +1327,7 @@ int read_flags(const Ctx& c, GlobalFlags* host) {
 int tune_phase(const Ctx& c, const Core& k, Phase& ph) {
   int rc;
   DslashCall t = phase_call(c, k, ph, 1);
+  t.pairs = ph.pairs;
   if ((rc = dslash_tuned(t, c.p.rhs_block, c.s, &ph.c_oe))) return rc;
   t.out_par = 0;
   t.mode = DM_CG;
@@ -1280,6 +1353,11 @@ int setup_core(const Ctx& c, Core& k) {
   m.x = mixed ? static_cast<void*>(c.ws + c.L.xlo) : static_cast<void*>(k.x);
   m.rel_d2 = mixed ? c.p.reliable_delta * c.p.reliable_delta : 0.0;
   m.sw2 = 0.0;
+  // The FP32 stencils read and write the base direction and t as pairs of
+  // systems when there is an even number of them (16-byte accesses).
+  m.pairs = mixed && k.win > 1 && k.nsys % 2 == 0 &&
+            (c.ifmt == LQCD_LINKS12 || c.ifmt == LQCD_LINKS18) && c.p.rhs_block != 1 &&
+            rhs_pairs_enabled();
   k.two_phase = mixed && c.L.has_pre && !k.guess && k.nshift > 1;
   if (k.two_phase) {
     Phase& q = k.pre;
@@ -1385,12 +1463,13 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
     hipLaunchKernelGGL((k_init_dirs<float, float>), gv, dim3(kVecBlock), 0, s,
                        c.at<const float2>(first.r), rslots(k), c.at<float2>(first.p),
                        (float2*)first.x,
-                       k.win > 1 ? c.at<float2>(first.pc) : nullptr, k.nshift, 1, c.g.Vh,
+                       k.win > 1 ? c.at<float2>(first.pc) : nullptr, first.pairs, k.nshift, 1,
+                       c.g.Vh,
                        c.at<double>(c.L.pp));
   } else {
     hipLaunchKernelGGL((k_init_dirs<double, double>), gv, dim3(kVecBlock), 0, s,
                        c.at<const double2>(first.r), rslots(k), c.at<double2>(first.p), k.x,
-                       k.win > 1 ? c.at<double2>(first.pc) : nullptr, k.nshift,
+                       k.win > 1 ? c.at<double2>(first.pc) : nullptr, 0, k.nshift,
                        k.guess ? 0 : 1, c.g.Vh, c.at<double>(c.L.pp));
   }
   LQCD_LAUNCH_CHECK();
@@ -1419,7 +1498,7 @@ int core_solve(const Ctx& c, Core& k, const double* m2s_host, const double* delt
                          c.at<const double2>(c.L.p64),
                          w ? c.at<const double2>(c.L.pc64) : nullptr, c.at<float2>(c.L.r),
                          c.at<float2>(c.L.p), w ? c.at<float2>(c.L.pc) : nullptr,
-                         c.at<float2>(c.L.xlo), k.nshift, k.base, c.g.Vh,
+                         k.main.pairs, c.at<float2>(c.L.xlo), k.nshift, k.base, c.g.Vh,
                          c.at<double>(c.L.pp));
       LQCD_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_sc_phase2, dim3(1), dim3(64), 0, s, st, k.nsys, k.nshift);

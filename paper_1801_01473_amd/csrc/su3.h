@@ -98,6 +98,43 @@ __device__ __forceinline__ R ld_buf_real(__amdgpu_buffer_rsrc_t r, uint32_t voff
     return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
 }
 
+// Two single-precision complex values stored next to each other (the same
+// element of two right-hand sides kept as an interleaved pair) in one 16-byte
+// buffer load: a holds the first, b the second.
+template <int AUX = 0>
+__device__ __forceinline__ void ld_buf_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                            uint32_t soff, cplx<float>& a, cplx<float>& b) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 v = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+  a = mk<float>(v.x, v.y);
+  b = mk<float>(v.z, v.w);
+}
+
+// Streaming 16-byte access to such a pair (p 16-byte aligned); NT as below.
+template <bool NT>
+__device__ __forceinline__ void ld_once_pair(const cplx<float>* p, cplx<float>& a,
+                                             cplx<float>& b) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4* q = reinterpret_cast<const f4*>(p);
+  const f4 v = NT ? __builtin_nontemporal_load(q) : *q;
+  a = mk<float>(v.x, v.y);
+  b = mk<float>(v.z, v.w);
+}
+
+template <bool NT>
+__device__ __forceinline__ void st_once_pair(cplx<float>* p, cplx<float> a, cplx<float> b) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  f4 v;
+  v.x = a.x;
+  v.y = a.y;
+  v.z = b.x;
+  v.w = b.y;
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+  else
+    *reinterpret_cast<f4*>(p) = v;
+}
+
 // Streaming access to a complex value that is read or written once: the
 // non-temporal hint lets the caches evict it first.  NT = false is a plain access.
 template <typename R, bool NT>

@@ -188,7 +188,7 @@ def test_force_and_action_validation(lq):
     assert "S must be" in lq.last_error()
 
 
-def test_bench_traffic_record_is_tied_to_the_profiled_sources(tmp_path):
+def test_bench_traffic_record_is_tied_to_the_profiled_sources(tmp_path, monkeypatch):
     """The bench reports the dominant kernel's counter traffic only for the
     kernel class that was profiled, only while the stencil sources hash to the
     profiled ones and only when the tuner chose the profiled configuration;
@@ -206,13 +206,20 @@ def test_bench_traffic_record_is_tied_to_the_profiled_sources(tmp_path):
     L = (48, 48, 48, 48)
     shipped = bench.tuned_config(bench.SHIPPED_TUNE_CACHE, L, rec["kernel_class"], 8)
     assert shipped == cfg
+    # (the FP32 classes of an even RHS count run on RHS pairs: keys ending in /pairs)
     cache = tmp_path / "tune.txt"
     key = "v1/gfx950:sramecc+:xnack-/256cu/48x48x48x48/p1/f1/n8/b0/m2"
-    cache.write_text(f"{key};1,1,1,0,0,0,0,0,0,0\n{key};{cfg}\n"
-                     "v1/gfx950:sramecc+:xnack-/256cu/48x48x48x48/p1/f1/n8/b0/m0;2,2\n")
+    cache.write_text(f"{key}/pairs;1,2,1,0,0,0,0,0,0,0\n{key}/pairs;{cfg}\n"
+                     f"{key};64,8,1,0,0,0,0,0,0,0\n"
+                     "v1/gfx950:sramecc+:xnack-/256cu/48x48x48x48/p1/f1/n8/b0/m0/pairs;2,2\n")
+    assert bench.rhs_pairs(rec["kernel_class"], 8)
     assert bench.tuned_config(str(cache), L, rec["kernel_class"], 8) == cfg
     assert bench.tuned_config(str(cache), L, rec["kernel_class"], 4) is None
     assert bench.tuned_config(None, L, rec["kernel_class"], 8) is None
+    assert not bench.rhs_pairs("dslash_eo_cg_f64_n8", 8) and not bench.rhs_pairs(
+        rec["kernel_class"], 1)
+    monkeypatch.setenv("LQCD_RHS_PAIRS", "0")
+    assert bench.tuned_config(str(cache), L, rec["kernel_class"], 8) == "64,8,1,0,0,0,0,0,0,0"
 
 
 def test_gauge_phase_stout_and_rational_validation(lq):

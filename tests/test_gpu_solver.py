@@ -65,7 +65,7 @@ def test_cg_free_field_converges_in_four_iterations(lq):
 
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 2, 8), (8, 8, 8, 8)])
 @pytest.mark.parametrize("mode", MODES[:2])
-@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("nrhs", [1, 3, 4])
 def test_multishift_every_shift_true_residual(lq, L, mode, nrhs):
     m = 0.02
     U = synth.links_exp(L, 0.5, 103)
@@ -132,6 +132,47 @@ def test_nontemporal_streams_same_bits(lq, mode, cfg, monkeypatch):
     monkeypatch.delenv("LQCD_DSLASH_CFG")
     lq.finalize()
     assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("fmt", [1, 0])
+@pytest.mark.parametrize("switch", [1e-3, 0.0])
+@pytest.mark.parametrize("cfg", ["128,8,1,2,1,3,0,1,1,0,1", "256,4,1,2,1,0,0,1,0,2,1",
+                                 "64,2,0,0,0,0,1,0,0,0,0"])
+def test_rhs_pairs_same_bits(lq, fmt, switch, cfg, monkeypatch):
+    """With an even number of right-hand sides the FP32 phase of a mixed
+    multi-shift solve keeps the base direction and D_oe's output as
+    interleaved pairs (16-byte stencil accesses, a paired base update).  With
+    the stencil configuration pinned, the solutions and every deterministic
+    statistic are the same bits as with the systems one after the other
+    (LQCD_RHS_PAIRS=0): one-hop and two-hop schedules, RHS blocks 8 (pairs
+    past the four systems alias the last one), 4 and 2, cached and
+    non-temporal streams, 12- and 18-real links, with and without the FP64
+    opening phase (the switch to FP32 and the FP32 start both write pairs),
+    through reliable updates; every shift meets the oracle's true residual."""
+    L = (8, 4, 6, 4)
+    U = synth.links_haar(L, 111)
+    g, U64, b_nat, b = setup(lq, L, U, 211, 4)
+    sig = synth.rational_shifts(5, 1e-3, 1.0)
+    p = lq.solver_params(mass=0.05, tol=1e-10, inner_prec=1, inner_fmt=fmt, mixed_switch=switch)
+    keys = ("iters", "reliable_updates", "refine_iters", "converged", "true_rel_residual",
+            "iters_fp64", "shift_updates_fp64", "shift_updates_fp32")
+    monkeypatch.setenv("LQCD_DSLASH_CFG", cfg)
+    out = []
+    for pairs in ("0", "1"):
+        monkeypatch.setenv("LQCD_RHS_PAIRS", pairs)
+        lq.finalize()
+        X, _, stats = lq.cg_multishift(g, p, U64, sig, b)
+        out.append((X, [[{k: s[k] for k in keys} for s in row] for row in stats]))
+    monkeypatch.delenv("LQCD_RHS_PAIRS")
+    monkeypatch.delenv("LQCD_DSLASH_CFG")
+    lq.finalize()
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][0], out[1][0])
+    assert all(s["converged"] == 1 for row in out[1][1] for s in row)
+    Xn = host(lq.unpack_spinor(g, out[1][0].reshape(-1, 3, g.Vh), 0)).reshape(4, len(sig), -1, 3)
+    for j in range(4):
+        for s_, sg in enumerate(sig):
+            assert oracle.true_residual(L, U, 0.05, sg, b_nat[j], Xn[j, s_]) <= 1e-10
 
 
 @pytest.mark.parametrize("mode", [dict(inner_prec=0, inner_fmt=1), MODES[1]])
