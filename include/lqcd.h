@@ -273,10 +273,11 @@ int lqcd_cg(const lqcd_geom *g, const lqcd_solver_params *p, const void *U64_pac
  * link load in D_oe/D_eo.  With FP32 inner precision, 12- or 18-real inner
  * links and an even nrhs, the FP32 phase keeps the base directions and D_oe's
  * output in the workspace with right-hand sides 2q and 2q + 1 interleaved
- * element by element, so the stencils load both with one 16-byte access; the
- * results are the same bits as with separate rows, which the environment
- * variable LQCD_RHS_PAIRS=0 selects (comparisons).  b, x and the workspace
- * size are unaffected.  1 <= nrhs <= 64.
+ * element by element, so the stencils load both with one 16-byte access; with
+ * the same stencil launch configurations the results are the same bits as
+ * with separate rows, which the environment variable LQCD_RHS_PAIRS=0 selects
+ * (comparisons).  b, x and the workspace size are unaffected.
+ * 1 <= nrhs <= 64.
  */
 int lqcd_cg_multishift(const lqcd_geom *g, const lqcd_solver_params *p,
                        const void *U64_packed, const void *Uinner, int32_t nshift,
