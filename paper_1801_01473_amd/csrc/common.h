@@ -153,6 +153,34 @@ __device__ __forceinline__ double strided_sum(const double* __restrict__ p, int 
   return s;
 }
 
+// strided_sum of two arrays at once: the loads of both batches issue
+// together, so the two reductions wait for one chain of memory round trips
+// instead of two; each sum adds its terms in strided_sum's order (same bits).
+__device__ __forceinline__ void strided_sum2(const double* __restrict__ p, int n,
+                                             const double* __restrict__ q, int m, double* sp,
+                                             double* sq) {
+  constexpr int kBatch = 16;
+  const int nm = n > m ? n : m;
+  double s = 0.0, t = 0.0;
+  for (int i0 = threadIdx.x; i0 < nm; i0 += kBatch * blockDim.x) {
+    double v[kBatch], w[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = i0 + u * int(blockDim.x);
+      v[u] = i < n ? p[i] : 0.0;
+      w[u] = i < m ? q[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = i0 + u * int(blockDim.x);
+      if (i < n) s += v[u];
+      if (i < m) t += w[u];
+    }
+  }
+  *sp = s;
+  *sq = t;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* lds) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -71,6 +71,23 @@ __device__ double wg_sum(const double* __restrict__ p, int n, double* lds) {
   return s;
 }
 
+// wg_sum of two arrays with their loads overlapped (strided_sum2): the same
+// two results, bit for bit, in one chain of memory round trips.
+__device__ void wg_sum2(const double* __restrict__ p, int n, const double* __restrict__ q, int m,
+                        double* lds, double* sp, double* sq) {
+  __shared__ double bc[2];
+  double s, t;
+  strided_sum2(p, n, q, m, &s, &t);
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) bc[0] = s;
+  t = block_sum(t, lds);
+  if (threadIdx.x == 0) bc[1] = t;
+  __syncthreads();
+  *sp = bc[0];
+  *sq = bc[1];
+  __syncthreads();
+}
+
 __device__ __forceinline__ bool finite_d(double v) { return v == v && fabs(v) <= 1.7e308; }
 
 template <typename T>
@@ -232,8 +249,8 @@ __global__ void __launch_bounds__(kScalarThreads) k_sc_alpha(SysState* __restric
                                                               int nb_p) {
   __shared__ double lds[kScalarThreads / 64];
   const int j = blockIdx.x;
-  const double tt = wg_sum(part_t + int64_t(j) * nb_t, nb_t, lds);
-  const double pp = wg_sum(part_p + int64_t(j) * nb_p, nb_p, lds);
+  double tt, pp;
+  wg_sum2(part_t + int64_t(j) * nb_t, nb_t, part_p + int64_t(j) * nb_p, nb_p, lds, &tt, &pp);
   if (threadIdx.x != 0) return;
   SysState& S = st[j];
   S.upd_any = 0;
