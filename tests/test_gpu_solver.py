@@ -175,6 +175,35 @@ def test_rhs_pairs_same_bits(lq, fmt, switch, cfg, monkeypatch):
             assert oracle.true_residual(L, U, 0.05, sg, b_nat[j], Xn[j, s_]) <= 1e-10
 
 
+@pytest.mark.parametrize("nrhs", [2, 6])
+@pytest.mark.parametrize("cfg", ["128,8,1,2,1,3,0,1,1,0,1", "256,4,1,2,1,0,0,1,0,2,1"])
+def test_rhs_pairs_other_counts(lq, nrhs, cfg, monkeypatch):
+    """Right-hand-side pairs at 2 and 6 systems: with RHS blocks of 8 and 4 the
+    pairs past the last system alias the last pair (loaded, never stored);
+    same bits as separate rows, every shift at the oracle's 1e-10."""
+    L = (8, 4, 6, 4)
+    U = synth.links_haar(L, 113)
+    g, U64, b_nat, b = setup(lq, L, U, 213, nrhs)
+    sig = synth.rational_shifts(4, 1e-3, 1.0)
+    p = lq.solver_params(mass=0.05, tol=1e-10, inner_prec=1, inner_fmt=1)
+    monkeypatch.setenv("LQCD_DSLASH_CFG", cfg)
+    out = []
+    for pairs in ("0", "1"):
+        monkeypatch.setenv("LQCD_RHS_PAIRS", pairs)
+        lq.finalize()
+        X, _, stats = lq.cg_multishift(g, p, U64, sig, b)
+        out.append((X, [[(s["iters"], s["true_rel_residual"]) for s in row] for row in stats]))
+    monkeypatch.delenv("LQCD_RHS_PAIRS")
+    monkeypatch.delenv("LQCD_DSLASH_CFG")
+    lq.finalize()
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][0], out[1][0])
+    Xn = host(lq.unpack_spinor(g, out[1][0].reshape(-1, 3, g.Vh), 0)).reshape(nrhs, len(sig), -1, 3)
+    for j in range(nrhs):
+        for s_, sg in enumerate(sig):
+            assert oracle.true_residual(L, U, 0.05, sg, b_nat[j], Xn[j, s_]) <= 1e-10
+
+
 @pytest.mark.parametrize("mode", [dict(inner_prec=0, inner_fmt=1), MODES[1]])
 @pytest.mark.parametrize("tm", ["128,8,1,0,1,0,0,0,0,0,1,4,4", "256,8,0,0,1,0,0,0,0,0,1,8,2"])
 def test_t_march_solve_same_bits(lq, mode, tm, monkeypatch):
